@@ -1,0 +1,114 @@
+"""Pins for the balancer oracle: exhaustive search on tiny instances, Graham's
+bound for largest-first list scheduling, and the worked patterns of the paper's
+Experiments A, B and C (Section VI)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exhaustive
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def patterns():
+    with open(os.path.join(GOLD, "balancer_patterns.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                name, S, om, w, exp = line.split()
+                yield (name, int(S), np.array([int(v) for v in om.split(",")], np.int32),
+                       np.array([float(v) for v in w.split(",")]),
+                       dict(kv.split("=") for kv in exp.split(";")))
+
+
+@pytest.mark.parametrize("pat", list(patterns()), ids=lambda p: p[0])
+def test_paper_patterns_greedy(pat):
+    name, S, old, w, exp = pat
+    m = oracle.greedy(w, S)
+    heavy = w > w.min()
+    if "migrated" in exp:
+        assert int((m != old).sum()) == int(exp["migrated"])
+    nh = int(exp["per_slot"][0])
+    nl = int(exp["per_slot"][2])
+    for s in range(S):
+        assert int((heavy & (m == s)).sum()) == nh
+        assert int((~heavy & (m == s)).sum()) == nl
+
+
+def random_instances(n, seed, Cmax=9, Smax=3):
+    rng = np.random.default_rng(seed)
+    for _ in range(n):
+        C = int(rng.integers(1, Cmax + 1))
+        S = int(rng.integers(2, Smax + 1))
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            w = rng.integers(1, 20, size=C).astype(float)      # many ties
+        elif kind == 1:
+            w = rng.uniform(0.1, 10.0, size=C)
+        else:
+            w = np.round(rng.pareto(1.5, size=C) * 100 + 1)     # heavy tailed
+        yield w, S
+
+
+def test_greedy_vs_exhaustive():
+    worst = 1.0
+    for w, S in random_instances(400, 11):
+        C = len(w)
+        m = oracle.greedy(w, S)
+        assert m.min() >= 0 and m.max() < S
+        opt = exhaustive.optimum(w, S)
+        g = exhaustive.max_load(w, m, S)
+        assert g >= opt - 1e-9
+        assert g <= (4 / 3 - 1 / (3 * S)) * opt + 1e-9          # Graham 1969
+        assert g <= w.sum() / S + w.max() + 1e-9
+        if C <= S:
+            assert g == pytest.approx(opt)
+        worst = max(worst, g / opt)
+    assert worst > 1.0          # the instances do exercise suboptimal cases
+
+
+def test_greedy_ties_and_order():
+    # equal loads go round-robin in id order; the heaviest chunk lands on slot 0
+    m = oracle.greedy(np.ones(7), 3)
+    assert list(m) == [0, 1, 2, 0, 1, 2, 0]
+    m = oracle.greedy(np.array([1.0, 5.0, 3.0]), 5)
+    assert list(m) == [2, 0, 1]
+
+
+def test_refine_postconditions_random():
+    rng = np.random.default_rng(5)
+    for w, S in random_instances(400, 12, Cmax=10, Smax=4):
+        old = rng.integers(0, S, size=len(w)).astype(np.int32)
+        for thr in (1.0, 1.05, 1.3):
+            m = oracle.refine(w, old, S, thr)
+            assert exhaustive.refine_postconditions(w, old, m, S, thr) == []
+
+
+def test_refine_keeps_balanced_map():
+    w = np.array([2.0, 2.0, 1.0, 1.0, 1.0, 1.0, 2.0, 2.0])
+    old = np.array([0, 1, 0, 0, 1, 1, 2, 3], np.int32)   # loads 4, 4, 2, 2 ... not balanced
+    m = oracle.refine(w, old, 4, 1.05)
+    L = oracle.slot_loads(w, m, 4)
+    assert L.max() <= 3.0 * 1.05
+    balanced = np.array([0, 1, 2, 3, 2, 3, 0, 1], np.int32)  # loads 3 each
+    assert list(oracle.refine(w, balanced, 4, 1.05)) == list(balanced)
+
+
+def test_refine_moves_fewer_than_greedy_on_table5_shift():
+    """After the load shift of Experiment C (two processors with 3 heavy + 1 light, two
+    with 1 heavy + 3 light), a refinement restores balance while moving far fewer
+    chunks than a greedy remap of the same state."""
+    w = np.array([2.0] * 8 + [1.0] * 8)
+    old = np.array([0, 0, 0, 1, 2, 2, 2, 3, 0, 1, 1, 1, 2, 3, 3, 3], np.int32)
+    L = oracle.slot_loads(w, old, 4)
+    assert list(L) == [7, 5, 7, 5]
+    r = oracle.refine(w, old, 4, 1.0)
+    g = oracle.greedy(w, 4)
+    assert oracle.slot_loads(w, r, 4).max() == 6
+    assert int((r != old).sum()) < int((g != old).sum())
+
+
+def test_block_map():
+    assert list(oracle.block_map(16, 4)) == [0] * 4 + [1] * 4 + [2] * 4 + [3] * 4
+    assert list(oracle.block_map(3, 8)) == [0, 1, 2]

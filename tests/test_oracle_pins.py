@@ -1,0 +1,246 @@
+"""Pins for the CPU oracle: each test checks the oracle against something other
+than itself (closed forms, published generator outputs, symmetries, invariants,
+brute force), so that a dropped term, a wrong sign, a wrong index or a
+transposed operand in it fails at least one test."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_4218_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny(nx=12, ny=10, nz=6, kmin=0, kmax=0, hot=((5, 4, 0, 0),), sigma=3.0, px=3, py=2,
+         cc=0.4, cn=0.1, eps=0.01, steps=4, seed=77, alpha=32):
+    xs, ys = W.make_splits(nx, ny, px, py)
+    return W.Workload(name="tiny", nx=nx, ny=ny, nz=nz, px=px, py=py, xsplit=xs, ysplit=ys,
+                      hot=list(hot), sigma=sigma, kmin=kmin, kmax=kmax, steps=steps,
+                      c_center=cc, c_nbr=cn, eps=eps, seed=seed, alpha_work=alpha)
+
+
+# ---------------------------------------------------------------- generator
+def test_splitmix64_published_outputs():
+    with open(os.path.join(GOLD, "splitmix64.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert rows
+    for seed, idx, out in rows:
+        assert oracle.splitmix64(int(seed), int(idx)) == int(out)
+
+
+def test_init_field_distribution():
+    q = oracle.init_field(32, 16, 8, seed=5)
+    assert q.min() >= -1.0 and q.max() < 1.0
+    assert np.all(q * 2 ** 23 == np.round(q * 2 ** 23))          # multiples of 2^-23
+    assert abs(q.mean()) < 0.02 and abs(q.var() - 1 / 3) < 0.02  # uniform on [-1, 1)
+    # value of cell n is the (n+1)-th generator output, top 24 bits, centred
+    n = 1234
+    m = oracle.splitmix64(5, n) >> 40
+    assert q.reshape(-1)[n] == (m - 2 ** 23) / 2 ** 23
+
+
+# ---------------------------------------------------------------- stencil (k = 0)
+def eigen_field(nx, ny, nz, m, n, l):
+    x = np.arange(nx)[None, :, None]
+    y = np.arange(ny)[:, None, None]
+    z = np.arange(nz)[None, None, :]
+    return (np.cos(2 * np.pi * m * x / nx) * np.cos(2 * np.pi * n * y / ny)
+            * np.cos(np.pi * l * (z + 0.5) / nz))
+
+
+@pytest.mark.parametrize("mnl", [(0, 0, 0), (1, 0, 0), (0, 2, 0), (0, 0, 1), (3, 1, 2), (6, 5, 5)])
+def test_stencil_eigenmodes(mnl):
+    """With no physics the update is linear and shift-invariant: separable cos modes
+    (periodic in x, y; DCT-II in z, which meets the mirror ghost exactly) are
+    eigenvectors with eigenvalue cc + 2cn[cos(2pi m/nx) + cos(2pi n/ny) + cos(pi l/nz)]."""
+    nx, ny, nz = 12, 10, 6
+    m, n, l = mnl
+    q0 = eigen_field(nx, ny, nz, m, n, l)
+    wl = tiny(nx, ny, nz, kmin=0, kmax=0, steps=5)
+    q, _, _, _ = oracle.run(wl, q0=q0)
+    mu = 0.4 + 0.2 * (math.cos(2 * math.pi * m / nx) + math.cos(2 * math.pi * n / ny)
+                      + math.cos(math.pi * l / nz))
+    np.testing.assert_allclose(q[0], mu ** 5 * q0, atol=1e-13, rtol=0)
+
+
+def test_stencil_matches_roll_formulation():
+    """Independent formulation of the same update with array rolls (periodic x/y)
+    and edge replication (mirror ghost in z)."""
+    rng = np.random.default_rng(3)
+    q = rng.uniform(-1, 1, size=(7, 9, 5))
+    s = oracle.stencil(q, 0.4, 0.1)
+    zpad = np.concatenate([q[:, :, :1], q, q[:, :, -1:]], axis=2)
+    nb = (np.roll(q, 1, axis=1) + np.roll(q, -1, axis=1) + np.roll(q, 1, axis=0)
+          + np.roll(q, -1, axis=0) + zpad[:, :, :-2] + zpad[:, :, 2:])
+    np.testing.assert_allclose(s, 0.4 * q + 0.1 * nb, atol=1e-15, rtol=0)
+
+
+def test_stencil_single_level_centre_weight():
+    """nz = 1: both z neighbours are the cell itself (zero flux), so s = 0.6 q + 0.1 (4 lateral)."""
+    q = np.zeros((3, 3, 1))
+    q[1, 1, 0] = 1.0
+    s = oracle.stencil(q, 0.4, 0.1)
+    assert s[1, 1, 0] == pytest.approx(0.6, abs=1e-15)
+    assert s[0, 1, 0] == pytest.approx(0.1, abs=1e-15)
+    assert s[0, 0, 0] == 0.0
+
+
+def test_mass_conserved_without_physics():
+    wl = tiny(16, 12, 7, kmin=0, kmax=0, steps=6)
+    q0 = oracle.init_field(16, 12, 7, seed=9)
+    m0 = q0.sum()
+    _, _, ck, _ = oracle.run(wl, q0=q0)
+    np.testing.assert_allclose(ck, m0, atol=1e-12 * np.abs(q0).sum())
+
+
+@pytest.mark.parametrize("c", [-1.0, -0.5, 0.0, 0.25, 0.7, 1.0])
+def test_constant_field_without_physics(c):
+    wl = tiny(kmin=0, kmax=0, steps=5)
+    q, _, _, _ = oracle.run(wl, q0=np.full((wl.ny, wl.nx, wl.nz), c))
+    np.testing.assert_allclose(q, c, atol=4e-15, rtol=0)
+
+
+@pytest.mark.parametrize("c", [-1.0, 0.0, 1.0])
+def test_fixed_points_with_physics(c):
+    """-1, 0 and 1 are fixed points of the stencil (weights sum to one) and of
+    Phi (q - q^3 = 0), so they survive the full update with physics on."""
+    wl = tiny(kmin=1, kmax=40, steps=4)
+    q, _, _, _ = oracle.run(wl, q0=np.full((wl.ny, wl.nx, wl.nz), c))
+    np.testing.assert_allclose(q, c, atol=1e-14, rtol=0)
+
+
+# ---------------------------------------------------------------- column map Phi
+def test_phi_linear_growth_near_zero():
+    """Phi(q) = q + eps(q - q^3) has slope 1 + eps at 0: tiny values grow by (1+eps)^k."""
+    q0, k = 1e-12, 50
+    s = np.full((1, 1, 1), q0)
+    out = oracle.physics(s, np.array([[k]]), eps=0.01)[0, 0, 0]
+    assert out == pytest.approx(q0 * 1.01 ** k, rel=1e-12)
+
+
+def test_phi_contraction_near_one():
+    """Slope at +-1 is 1 - 2 eps: a small offset from 1 shrinks by (1 - 2 eps)^k."""
+    d, k = 1e-9, 40
+    s = np.array([[[1 - d, -1 + d]]])
+    out = oracle.physics(s, np.array([[k]]), eps=0.01)[0, 0]
+    assert 1 - out[0] == pytest.approx(d * 0.98 ** k, rel=1e-5)
+    assert out[1] + 1 == pytest.approx(d * 0.98 ** k, rel=1e-5)
+
+
+def test_phi_odd_monotone_bounded():
+    v = np.linspace(0, 1, 21)
+    s = np.concatenate([-v[:0:-1], v]).reshape(1, 1, 41)   # exactly symmetric samples
+    out = oracle.physics(s, np.array([[7]]), eps=0.01)[0, 0]
+    np.testing.assert_array_equal(out, -out[::-1])          # odd
+    assert np.all(np.diff(out) > 0)                          # monotone
+    assert np.all(np.abs(out) <= 1.0)
+    assert np.all(np.abs(out[1:-1]) >= np.abs(s[0, 0, 1:-1]))  # pushed away from 0
+
+
+def test_identity_stencil_leaves_only_phi():
+    """cc = 1, cn = 0 make the Jacobi step the identity, so the update is Phi^k per cell."""
+    wl = tiny(kmin=1, kmax=9, cc=1.0, cn=0.0, steps=1)
+    q0 = oracle.init_field(wl.nx, wl.ny, wl.nz, seed=4)[0]
+    q, _, _, k = oracle.run(wl, q0=q0)
+    ref = oracle.physics(q0, k, eps=0.01)
+    np.testing.assert_array_equal(q[0], ref)
+
+
+# ---------------------------------------------------------------- cost field k
+def test_kfield_gaussian_levels():
+    """k >= kmin + j exactly where (kmax-kmin) exp(-r^2/(2 sigma^2)) >= j, i.e. where
+    r^2 <= 2 sigma^2 ln((kmax-kmin)/j); counted here by brute force over lattice offsets."""
+    nx = ny = 64
+    sigma, kmin, kmax = 8.0, 1, 32
+    k = oracle.kfield(nx, ny, [(32, 32, 0, 0)], 0, sigma, kmin, kmax)
+    assert k[32, 32] == kmax and (k == kmax).sum() == 1
+    assert k.min() == kmin
+    for j in (1, 2, 5, 16, 30, 31):
+        bound = 2 * sigma ** 2 * math.log((kmax - kmin) / j)
+        count = sum(1 for dx in range(-32, 32) for dy in range(-32, 32)
+                    if dx * dx + dy * dy <= bound)
+        assert (k >= kmin + j).sum() == count, j
+
+
+def test_kfield_periodic_minimum_image_and_motion():
+    nx, ny = 40, 30
+    hot = [(2, 1, 3, -2)]
+    k0 = oracle.kfield(nx, ny, hot, 0, 5.0, 1, 50)
+    # minimum image: the hotspot at the edge wraps around symmetrically
+    assert k0[1, 1] == k0[1, 3] and k0[0, 2] == k0[2, 2]
+    assert k0[1, nx - 1] == k0[1, 5] and k0[ny - 1, 2] == k0[3, 2]
+    # a moving hotspot translates the field: k_t(x, y) = k_0(x - vx t, y - vy t)
+    for t in (1, 7, 45):
+        kt = oracle.kfield(nx, ny, hot, t, 5.0, 1, 50)
+        np.testing.assert_array_equal(kt, np.roll(np.roll(k0, 3 * t, axis=1), -2 * t, axis=0))
+
+
+def test_kfield_two_hotspots_is_max():
+    nx, ny = 48, 48
+    a = oracle.kfield(nx, ny, [(10, 12, 0, 0)], 0, 6.0, 1, 100)
+    b = oracle.kfield(nx, ny, [(30, 33, 0, 0)], 0, 6.0, 1, 100)
+    ab = oracle.kfield(nx, ny, [(10, 12, 0, 0), (30, 33, 0, 0)], 0, 6.0, 1, 100)
+    np.testing.assert_array_equal(ab, np.maximum(a, b))
+
+
+def test_zero_column_cost_reduces_to_stencil():
+    wl = tiny(kmin=0, kmax=0, steps=1)
+    q0 = oracle.init_field(wl.nx, wl.ny, wl.nz, seed=3)[0]
+    q, _, _, k = oracle.run(wl, q0=q0)
+    assert np.all(k == 0)
+    np.testing.assert_array_equal(q[0], oracle.stencil(q0))
+
+
+# ---------------------------------------------------------------- symmetries
+def test_odd_symmetry_bit_exact():
+    wl = tiny(kmin=1, kmax=30, steps=3)
+    q0 = oracle.init_field(wl.nx, wl.ny, wl.nz, seed=8)
+    a, _, _, _ = oracle.run(wl, q0=q0)
+    b, _, _, _ = oracle.run(wl, q0=-q0)
+    np.testing.assert_array_equal(a, -b)
+
+
+def test_translation_bit_exact():
+    """Shifting the initial field and every hotspot by one cell in x shifts the result."""
+    wl = tiny(kmin=1, kmax=30, steps=3, hot=((5, 4, 1, 0),))
+    q0 = oracle.init_field(wl.nx, wl.ny, wl.nz, seed=8)
+    a, _, _, _ = oracle.run(wl, q0=q0)
+    b, _, _, _ = oracle.run(wl.replace(hot=[(6, 4, 1, 0)]), q0=np.roll(q0, 1, axis=2))
+    np.testing.assert_array_equal(np.roll(a, 1, axis=2), b)
+
+
+def test_bounded_by_one():
+    wl = tiny(kmin=1, kmax=300, steps=6)
+    q, _, _, _ = oracle.run(wl)
+    assert np.abs(q).max() <= 1.0
+
+
+# ---------------------------------------------------------------- loads
+def test_work_loads():
+    wl = tiny(12, 10, 6, kmin=0, kmax=0, steps=1, px=3, py=2, alpha=7)
+    _, work, _, _ = oracle.run(wl)
+    ncols = [(wl.xsplit[i + 1] - wl.xsplit[i]) * (wl.ysplit[j + 1] - wl.ysplit[j])
+             for j in range(wl.py) for i in range(wl.px)]
+    np.testing.assert_array_equal(work[0], [7 * 6 * n for n in ncols])
+    wl2 = tiny(12, 10, 6, kmin=1, kmax=40, steps=2, px=3, py=2, alpha=7)
+    _, work2, _, klast = oracle.run(wl2)
+    assert work2[1].sum() == 6 * (7 * 12 * 10 + int(klast.sum()))
+    # the chunk layout is row-major over (y-chunk, x-chunk)
+    c = 1 * wl2.px + 2
+    sub = klast[wl2.ysplit[1]:wl2.ysplit[2], wl2.xsplit[2]:wl2.xsplit[3]]
+    assert work2[1][c] == 6 * (7 * sub.size + int(sub.sum()))
+
+
+def test_dirichlet_splits_valid():
+    xs, ys = W.make_splits(2048, 2048, 64, 64, "dirichlet", 20.0, 2005)
+    for s, n in ((xs, 2048), (ys, 2048)):
+        assert s[0] == 0 and s[-1] == n and len(s) == 65
+        d = np.diff(s)
+        assert d.min() >= 1
+        assert 0.3 < d.min() / 32 and d.max() / 32 < 2.5
+    # extreme concentration still yields a valid split
+    xs, _ = W.make_splits(40, 40, 40, 2, "dirichlet", 0.05, 1)
+    assert np.all(np.diff(xs) == 1)
