@@ -1,0 +1,227 @@
+/*
+ * lbgrid.h -- C ABI of liblbgrid.so: an over-decomposed 3D grid update with
+ * per-chunk GPU load measurement and chunk-to-slot rebalancing on one MI355X
+ * (gfx950), after "Dynamic Load Balancing in GPU-Based Systems -- Early
+ * Experiments" (Fazenda, Mendes, Kale, Panetta, Rodrigues; arXiv 1310.4218).
+ *
+ * The paper's synthetic application (Section IV, Fig. 2) advances a
+ * 2D-decomposed grid of virtual processors (VPs) one time step at a time:
+ * a 3D Jacobi update, then a column "physics" loop whose trip count is set by
+ * a load-control array moved across the domain (Section VI, Fig. 4).  Loads
+ * are measured per VP (Section V) and a balancer (GreedyLB, RefineSwapLB,
+ * Section VI) migrates VPs between processors.  On one GPU:
+ *   VP          -> chunk: a rectangle of grid columns with all nz levels
+ *   processor   -> slot: a queue served by a group of workgroups of one
+ *                  persistent kernel
+ *   migration   -> an update of the chunk->slot table (no data moves)
+ *   measurement -> in-kernel per-chunk work counts and wall-clock ticks
+ *
+ * One time step, for every cell (x, y, z) of every field:
+ *   s = c_center*q + c_nbr*(((((q[x-1] + q[x+1]) + q[y-1]) + q[y+1]) + q[z-1]) + q[z+1])
+ *       x and y periodic; z mirror ghost (q[-1] = q[0], q[nz] = q[nz-1]);
+ *   k = kmin + floor((kmax-kmin) * max_h exp(-r_h^2 / (2 sigma^2))), r_h^2 the
+ *       integer minimum-image squared distance from (x, y) to hotspot h, which
+ *       sits at (hx0 + hvx*t, hy0 + hvy*t) mod (nx, ny) at time t = t0 + step;
+ *   q' = Phi^k(s),  Phi(q) = q + eps*(q - (q*q)*q).
+ * Chunk c = j*px + i covers columns [xsplit[i], xsplit[i+1]) x [ysplit[j], ysplit[j+1]).
+ * Field layout: q[((f*ny + y)*nx + x)*nz + z], the vertical index fastest
+ * (the column layout of Fig. 1).
+ *
+ * Conventions for every call:
+ *  - Every call returns an lb_status; the library never aborts or throws.
+ *    On failure lb_last_error(ctx) (or lb_last_error(NULL) for calls without a
+ *    context) gives a message; HIP failures carry hipGetErrorString's text.
+ *  - Device buffers are borrowed: the caller allocates them (lb_query gives the
+ *    sizes) and keeps them alive and untouched until lb_destroy.
+ *  - Host arrays passed in are copied before the call returns; host output
+ *    arrays are caller-allocated.
+ *  - A context is not thread-safe.  Separate contexts are independent.
+ *  - GPU work is enqueued on the stream given to lb_grid_init; calls that
+ *    return host data synchronize that stream first.
+ */
+#ifndef LBGRID_H
+#define LBGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_ABI_VERSION 1
+#define LB_MAX_HOT 4
+#define LB_NBUF 3
+
+typedef enum {
+    LB_OK = 0,
+    LB_E_INVAL = -1,       /* bad argument or configuration                   */
+    LB_E_STATE = -2,       /* call not valid in the context's current state   */
+    LB_E_HIP = -3,         /* a HIP runtime call failed                       */
+    LB_E_NOMEM = -4,       /* host allocation failed or a buffer is too small */
+    LB_E_UNSUPPORTED = -5  /* valid request this build does not implement     */
+} lb_status;
+
+/* Arithmetic of the fields. */
+enum { LB_FP32 = 0, LB_FP32_KAHAN = 1, LB_FP64 = 2 };
+/* How lb_step runs a step. */
+enum {
+    LB_PLAIN = 0,          /* one kernel launch per chunk, chunks in id order  */
+    LB_PERSISTENT = 1,     /* one persistent launch per step, replayed from a
+                              captured HIP graph                               */
+    LB_PLAIN_GRAPH = 2,    /* LB_PLAIN's launches replayed from a HIP graph    */
+    LB_PERSISTENT_EAGER = 3 /* LB_PERSISTENT launched directly (no graph)      */
+};
+/* Load source for lb_measure / lb_rebalance. */
+enum { LB_LOAD_WORK = 0, LB_LOAD_TIME = 1 };
+/* Balancer. */
+enum { LB_GREEDY = 0, LB_REFINE = 1, LB_REFINESWAP = 2 };
+
+typedef struct lb_ctx lb_ctx;
+
+/* Problem and launch configuration.  lb_config_default fills every field with
+ * the defaults shown. */
+typedef struct {
+    int32_t nx, ny, nz;      /* grid cells; nz levels per column (>= 1 each)    */
+    int32_t nfields;         /* independent fields sharing one cost field (1)  */
+    int32_t px, py;          /* chunks along x and y                          */
+    const int32_t *xsplit;   /* px+1 strictly increasing split points, [0] = 0,
+                                [px] = nx; NULL = equal split floor(i*nx/px)   */
+    const int32_t *ysplit;   /* likewise for y                                */
+    int32_t precision;       /* LB_FP32 | LB_FP32_KAHAN | LB_FP64              */
+    double c_center;         /* 0.4                                           */
+    double c_nbr;            /* 0.1                                           */
+    double eps;              /* 0.01                                          */
+    int32_t nhot;            /* 0..LB_MAX_HOT hotspots (0: k = kmin)           */
+    int32_t hx0[LB_MAX_HOT], hy0[LB_MAX_HOT];   /* start cell of each hotspot  */
+    int32_t hvx[LB_MAX_HOT], hvy[LB_MAX_HOT];   /* cells per step              */
+    double sigma;            /* Gaussian width in cells (> 0)                 */
+    int32_t kmin, kmax;      /* 0 <= kmin <= kmax: column-loop trip range      */
+    int32_t alpha_work;      /* work units per cell for the stencil (32)       */
+    int32_t nslots;          /* S, the balancer's processors (256)            */
+    int32_t wg_per_slot;     /* G workgroups per slot; 0 = max(1, 2048/S)     */
+    int32_t tile_x, tile_y;  /* columns per work item along x, y; 0 = 16, 16   */
+    int32_t steal;           /* 1: a workgroup whose slot queue is empty takes
+                                items from other slots (default 1)            */
+    int32_t graph_steps;     /* persistent steps per captured graph (10)      */
+    int64_t t0;              /* time index of step 0 (hotspot phase)          */
+    uint64_t seed;           /* seed of the SplitMix64 initial field           */
+} lb_config;
+
+/* Device buffers: ptr[0] and ptr[1] hold the two field copies (ping-pong),
+ * ptr[2] the workspace (tables, queues, loads, counters). */
+typedef struct {
+    void *ptr[LB_NBUF];
+    size_t bytes[LB_NBUF];
+} lb_buffers;
+
+/* Per-context counters, filled by lb_stats. */
+typedef struct {
+    int64_t steps;           /* steps enqueued since init                     */
+    int32_t nchunks;         /* C                                             */
+    int32_t ntiles;          /* work items (tiles of chunks)                  */
+    int32_t nslots;          /* S                                             */
+    int32_t nwg;             /* workgroups of the persistent launch (S*G)     */
+    int32_t block;           /* threads per workgroup                         */
+    int32_t tile_x, tile_y;
+    double clock_hz;         /* rate of the in-kernel wall clock              */
+    double last_checksum;    /* FP64 sum of all cells after the last step     */
+    int64_t measured_steps;  /* steps accumulated in the current load window  */
+} lb_stats_t;
+
+/* Fill *cfg with the defaults listed in lb_config. */
+void lb_config_default(lb_config *cfg);
+
+/* Validate *cfg and report the device bytes each buffer needs in
+ * sizes_out->bytes (ptr entries are set to NULL).  No GPU needed.
+ * Errors: LB_E_INVAL (message names the field). */
+int lb_query(const lb_config *cfg, lb_buffers *sizes_out);
+
+/* Create a context over the caller's device buffers (sizes at least those of
+ * lb_query) on the current HIP device.  hip_stream (a hipStream_t, may be
+ * NULL for the null stream) orders all GPU work of the context.
+ * init_field: NULL for the seeded SplitMix64 field (value of cell n is
+ * ((splitmix64 output n+1) >> 40 - 2^23) * 2^-23), else nfields*ny*nx*nz
+ * values of the precision's element type (float for LB_FP32 and
+ * LB_FP32_KAHAN, double for LB_FP64), host or device memory.
+ * The initial chunk->slot map is the block map floor(c*S/C) (c for C < S)
+ * (Section VI, Table V: "0000 1111 2222 3333").  Returns LB_OK and *out, or
+ * an error with *out = NULL. */
+int lb_grid_init(const lb_config *cfg, const lb_buffers *bufs, void *hip_stream,
+                 const void *init_field, lb_ctx **out);
+
+/* Enqueue nsteps >= 0 time steps in the given mode (LB_PLAIN, LB_PERSISTENT,
+ * LB_PLAIN_GRAPH, LB_PERSISTENT_EAGER); asynchronous.  Every mode gives
+ * bit-identical fields and loads.  Loads of every step are added to the
+ * current measurement window (Section V: the measured time steps). */
+int lb_step(lb_ctx *ctx, int32_t nsteps, int32_t mode);
+
+/* Synchronize, copy the window's per-chunk loads (C doubles; LB_LOAD_WORK:
+ * sum over steps of nz*nfields*(alpha_work + k) per column, exact integers;
+ * LB_LOAD_TIME: in-kernel wall-clock ticks) to loads_out (may be NULL) and,
+ * when reset != 0, start a new window.  The copy is also kept for
+ * lb_rebalance. */
+int lb_measure(lb_ctx *ctx, int32_t source, double *loads_out, int32_t reset);
+
+/* Compute a new chunk->slot map with strategy LB_GREEDY (Section VI,
+ * Experiment A: heaviest chunk to the least loaded slot), LB_REFINE (move
+ * chunks off slots above threshold*average, Experiment B without swaps) or
+ * LB_REFINESWAP (refine, then swap pairs where no move fits) from loads
+ * (C doubles, or NULL for the loads kept by the last lb_measure: LB_E_STATE
+ * if there is none), install it and rebuild the per-slot work queues in
+ * descending per-tile cost.  Outputs (each may be NULL): map_out[C],
+ * *nmigrated, lambda_before_after[2] = max slot load / average slot load
+ * under the old and the new map. */
+int lb_rebalance(lb_ctx *ctx, int32_t strategy, double threshold, const double *loads,
+                 int32_t *map_out, int32_t *nmigrated, double *lambda_before_after);
+
+/* Install an explicit map (C slot indices in [0, S)) with per-chunk costs for
+ * the queue order (NULL: equal costs, chunk id order). */
+int lb_set_map(lb_ctx *ctx, const int32_t *map, const double *cost);
+
+/* Synchronize and copy field `field` of the current step (native precision,
+ * ny*nx*nz elements) to dst (host or device, dst_bytes at least that) when
+ * dst is not NULL; *checksum_out (may be NULL) receives the FP64 sum of its
+ * cells, computed on the device in a fixed order. */
+int lb_fields(lb_ctx *ctx, int32_t field, void *dst, size_t dst_bytes, double *checksum_out);
+
+/* Synchronize and fill *out. */
+int lb_stats(lb_ctx *ctx, lb_stats_t *out);
+
+/* Synchronize and copy per-workgroup busy ticks of the persistent launches in
+ * the current window (n >= nwg doubles).  max/avg of these is the workgroup
+ * imbalance of the persistent kernel. */
+int lb_wg_busy(lb_ctx *ctx, double *out, int32_t n);
+
+/* Synchronize and copy per-tile claim counts since the last reset (n >= ntiles
+ * int32); every tile is processed exactly once per step.  reset != 0 zeroes them. */
+int lb_visits(lb_ctx *ctx, int32_t *out, int32_t n, int32_t reset);
+
+/* Synchronize and copy the per-step FP64 sums of all cells of the last
+ * min(n, 1024, steps) steps, oldest first.  Returns the count in *got. */
+int lb_checksums(lb_ctx *ctx, double *out, int32_t n, int32_t *got);
+
+/* Host-only balancer (no GPU, no context): the same computation lb_rebalance
+ * uses.  old_map may be NULL for LB_GREEDY (then *nmigrated counts chunks off
+ * the block map). */
+int lb_balance_host(const double *loads, const int32_t *old_map, int32_t C, int32_t S,
+                    int32_t strategy, double threshold, int32_t *map_out, int32_t *nmigrated);
+
+/* Release the context (synchronizes its stream first).  NULL is a no-op. */
+void lb_destroy(lb_ctx *ctx);
+
+/* Last error message of ctx, or of the calling thread when ctx is NULL. */
+const char *lb_last_error(const lb_ctx *ctx);
+
+/* LB_ABI_VERSION of the built library. */
+int lb_abi_version(void);
+
+/* sizeof(lb_config) and sizeof(lb_stats_t) as compiled into the library, so that
+ * bindings can check their struct layouts. */
+size_t lb_config_bytes(void);
+size_t lb_stats_bytes(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBGRID_H */

@@ -1,0 +1,133 @@
+// Host load balancers of the library: GreedyLB and RefineLB over chunk loads
+// (Section VI of the paper: GreedyLB in Experiment A, RefineSwapLB in
+// Experiments B and C; Refine is its move-only part).
+//
+// Chunks are the paper's virtual processors, slots its processors.  All
+// decisions are made on FP64 loads with a fixed operation order, so that the
+// same loads always give the same map:
+//   - chunk order: load descending, then chunk id ascending;
+//   - slot choice: lowest load, then lowest slot index;
+//   - W (total load) sums the loads in chunk id order, slot loads accumulate in
+//     chunk id order, limit = (W / S) * threshold.
+#include <algorithm>
+#include <cstdint>
+#include <functional>
+#include <queue>
+#include <utility>
+#include <vector>
+
+#include "lbgrid_internal.h"
+
+namespace lbgrid {
+
+namespace {
+
+std::vector<int32_t> heavy_first(const double* w, int32_t C) {
+    std::vector<int32_t> ord(static_cast<size_t>(C));
+    for (int32_t c = 0; c < C; ++c) ord[c] = c;
+    std::stable_sort(ord.begin(), ord.end(), [w](int32_t a, int32_t b) { return w[a] > w[b]; });
+    return ord;  // stable: equal loads keep ascending ids
+}
+
+// GreedyLB: heaviest chunk first onto the least loaded slot.  A binary heap of
+// (load, slot) pairs gives the lowest load with the lowest index on ties.
+void greedy(const double* w, int32_t C, int32_t S, int32_t* map) {
+    using Entry = std::pair<double, int32_t>;
+    std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> heap;
+    for (int32_t s = 0; s < S; ++s) heap.push({0.0, s});
+    for (int32_t c : heavy_first(w, C)) {
+        Entry e = heap.top();
+        heap.pop();
+        map[c] = e.second;
+        heap.push({e.first + w[c], e.second});
+    }
+}
+
+// RefineLB: while the most loaded slot p (not yet given up) is above the limit,
+// move its heaviest chunk that still fits under the limit on the least loaded
+// slot q; give p up when no chunk fits.  A chunk moved onto q never makes q
+// exceed the limit, so a slot that receives chunks is never a source later
+// and every chunk moves at most once.
+void refine(const double* w, const int32_t* old_map, int32_t C, int32_t S, double thr,
+            int32_t* map) {
+    double W = 0.0;
+    for (int32_t c = 0; c < C; ++c) W += w[c];
+    const double limit = (W / static_cast<double>(S)) * thr;
+
+    std::vector<double> L(static_cast<size_t>(S), 0.0);
+    for (int32_t c = 0; c < C; ++c) {
+        map[c] = old_map[c];
+        L[map[c]] += w[c];
+    }
+    // per-slot chunk lists in heavy-first order
+    std::vector<std::vector<int32_t>> on(static_cast<size_t>(S));
+    for (int32_t c : heavy_first(w, C)) on[map[c]].push_back(c);
+
+    std::vector<char> given_up(static_cast<size_t>(S), 0);
+    for (;;) {
+        int32_t p = -1;
+        for (int32_t s = 0; s < S; ++s)
+            if (!given_up[s] && (p < 0 || L[s] > L[p])) p = s;
+        if (p < 0 || !(L[p] > limit)) break;
+        int32_t q = static_cast<int32_t>(std::min_element(L.begin(), L.end()) - L.begin());
+        // L[q] + w[c] is non-increasing along the heavy-first list: binary search
+        // for the first chunk whose move keeps q at or under the limit.
+        std::vector<int32_t>& lp = on[p];
+        const double Lq = L[q];
+        auto it = std::partition_point(lp.begin(), lp.end(),
+                                       [&](int32_t c) { return !(Lq + w[c] <= limit); });
+        if (it == lp.end() || p == q) {
+            given_up[p] = 1;
+            continue;
+        }
+        int32_t c = *it;
+        lp.erase(it);
+        map[c] = q;
+        L[p] -= w[c];
+        L[q] += w[c];
+        std::vector<int32_t>& lq = on[q];
+        auto pos = std::lower_bound(lq.begin(), lq.end(), c, [w](int32_t a, int32_t b) {
+            return w[a] > w[b] || (w[a] == w[b] && a < b);
+        });
+        lq.insert(pos, c);
+    }
+}
+
+}  // namespace
+
+void block_map(int32_t C, int32_t S, int32_t* map) {
+    for (int32_t c = 0; c < C; ++c)
+        map[c] = (C >= S) ? static_cast<int32_t>((static_cast<int64_t>(c) * S) / C) : c;
+}
+
+double imbalance(const double* w, const int32_t* map, int32_t C, int32_t S) {
+    std::vector<double> L(static_cast<size_t>(S), 0.0);
+    double W = 0.0;
+    for (int32_t c = 0; c < C; ++c) {
+        L[map[c]] += w[c];
+        W += w[c];
+    }
+    if (!(W > 0.0)) return 1.0;
+    return *std::max_element(L.begin(), L.end()) / (W / static_cast<double>(S));
+}
+
+int balance(const double* w, const int32_t* old_map, int32_t C, int32_t S, int strategy,
+            double threshold, int32_t* map_out) {
+    if (C < 0 || S < 1 || (C > 0 && (!w || !map_out))) return -1;
+    for (int32_t c = 0; c < C; ++c)
+        if (!(w[c] >= 0.0)) return -1;  // rejects negatives and NaN
+    if (strategy == kGreedy) {
+        greedy(w, C, S, map_out);
+        return 0;
+    }
+    if (strategy == kRefine) {
+        if (!old_map || !(threshold > 0.0)) return -1;
+        for (int32_t c = 0; c < C; ++c)
+            if (old_map[c] < 0 || old_map[c] >= S) return -1;
+        refine(w, old_map, C, S, threshold, map_out);
+        return 0;
+    }
+    return -2;
+}
+
+}  // namespace lbgrid

@@ -1,0 +1,563 @@
+// Device code of liblbgrid for gfx950 (CDNA4): the fused time-step kernel of
+// the over-decomposed grid (3D Jacobi update + column physics, Section IV and
+// Section VI Fig. 4 of the paper) with in-kernel per-chunk load measurement
+// (Section V), in two launch forms:
+//   - plain: one launch per chunk over that chunk's tiles, chunks in id order;
+//   - persistent: one launch per step whose workgroups claim tiles from
+//     per-slot queues (slots play the paper's processors) with atomic heads,
+//     optionally taking work from other slots once their own queue is empty.
+//
+// Data layout: field[((f*ny + y)*nx + x)*nz + z] (z fastest).  A work item is a
+// tile of up to TX x TY columns inside one chunk.  A workgroup has TX*nz/V
+// threads; thread t owns V consecutive levels of column t / (nz/V) of the
+// current tile row.  The tile is swept row by row (along y) through a ring of
+// four LDS rows, each holding TX+2 columns (one halo column on either side) of
+// all nz levels: rows y-1, y, y+1 are read by the stencil while row y+2 is
+// being fetched from HBM into registers.  Every cell is read from HBM once per
+// tile and written once; halo columns and halo rows are re-read by the
+// neighbouring tiles (mostly from L2 / MALL).
+//
+// Arithmetic per cell, with s the stencil value and k the column's trip count:
+//   FP32:        q <- fma(eps, fma(-(q*q), q, q), q), k times
+//   FP32 Kahan:  d = eps*(q - q^3); y = d - c; t = q + y; c = (t - q) - y; q = t
+//   FP64:        q <- q + eps*(q - (q*q)*q) with every product and sum rounded
+//                separately in the written order (no contraction), which makes
+//                the FP64 path bit-identical to a plain sequential evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbgrid_internal.h"
+
+namespace lbgrid {
+namespace {
+
+constexpr int kWave = 64;
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Vec {
+    T v[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> ld(const T* p) {
+    return *reinterpret_cast<const Vec<T, V>*>(p);
+}
+template <typename T, int V>
+__device__ __forceinline__ void st(T* p, const Vec<T, V>& x) {
+    *reinterpret_cast<Vec<T, V>*>(p) = x;
+}
+
+// ---- arithmetic of one cell ------------------------------------------------
+__device__ __forceinline__ float combine(float cc, float cn, float c, float sum) {
+    return cc * c + cn * sum;  // contracted to one fma
+}
+__device__ __forceinline__ double combine(double cc, double cn, double c, double sum) {
+#pragma clang fp contract(off)
+    return cc * c + cn * sum;
+}
+
+template <int KAHAN>
+__device__ __forceinline__ void physics(float eps, int k, float& q0) {
+    if (KAHAN) {
+        float q = q0, comp = 0.0f;
+        for (int it = 0; it < k; ++it) {
+            float d = eps * (q - (q * q) * q);
+            float y = d - comp;
+            float t = q + y;
+            comp = (t - q) - y;
+            q = t;
+        }
+        q0 = q;
+    } else {
+        float q = q0;
+        for (int it = 0; it < k; ++it) q = q + eps * (q - (q * q) * q);
+        q0 = q;
+    }
+}
+
+template <int KAHAN>
+__device__ __forceinline__ void physics(double eps, int k, double& q0) {
+#pragma clang fp contract(off)
+    double q = q0;
+    for (int it = 0; it < k; ++it) {
+        double q3 = (q * q) * q;
+        q = q + eps * (q - q3);
+    }
+    q0 = q;
+}
+
+// V cells of one thread, with all V chains interleaved for ILP.
+template <int KAHAN, typename T, int V>
+__device__ __forceinline__ void physics_vec(T eps, int k, T (&q)[V]) {
+    if constexpr (KAHAN || sizeof(T) == 8) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) physics<KAHAN>(eps, k, q[v]);
+    } else {
+        for (int it = 0; it < k; ++it) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) q[v] = q[v] + eps * (q[v] - (q[v] * q[v]) * q[v]);
+        }
+    }
+}
+
+// ---- cost field --------------------------------------------------------------
+__device__ __forceinline__ int wrap_mod(int64_t a, int n) {
+    int64_t r = a % n;
+    return static_cast<int>(r < 0 ? r + n : r);
+}
+
+__device__ __forceinline__ int column_k(const DevArgs& a, const int* hcx, const int* hcy, int x,
+                                        int y) {
+    int k = a.kmin;
+#pragma unroll
+    for (int h = 0; h < kMaxHot; ++h) {  // fixed trip count keeps hcx/hcy in registers
+        if (h < a.nhot) {
+            int dx = abs(x - hcx[h]);
+            dx = min(dx, a.nx - dx);
+            int dy = abs(y - hcy[h]);
+            dy = min(dy, a.ny - dy);
+            const int r2 = dx * dx + dy * dy;
+            k = max(k, a.ktab[min(r2, a.r2cut)]);
+        }
+    }
+    return k;
+}
+
+// ---- block reduction in a fixed order (deterministic) -------------------------
+__device__ __forceinline__ double wave_sum(double v, int active) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        double other = __shfl_xor(v, o, kWave);
+        if ((lane ^ o) < active) v += other;
+    }
+    return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  Uses red[0..nwaves).
+__device__ double block_sum(double v, double* red) {
+    const int wave = threadIdx.x / kWave;
+    const int nwaves = (blockDim.x + kWave - 1) / kWave;
+    const int active = min(kWave, static_cast<int>(blockDim.x) - wave * kWave);
+    v = wave_sum(v, active);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nwaves; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// ---- one tile -------------------------------------------------------------------
+struct TileOut {
+    double checksum;  // sum of the tile's outputs over all fields (valid in thread 0)
+    double work;      // work units of the tile (valid in thread 0)
+    int chunk;
+};
+
+template <typename T, int V, int KAHAN>
+__device__ TileOut process_tile(const DevArgs& a, int tile, const T* __restrict__ src,
+                                T* __restrict__ dst, const int* hcx, const int* hcy, T* lds,
+                                double* red) {
+    const int nz = a.nz, nx = a.nx, ny = a.ny;
+    const int NQ = nz / V;
+    const int TX = a.tile_x;
+    const int tcol = threadIdx.x / NQ;
+    const int tzq = threadIdx.x - tcol * NQ;
+    const int zoff = tzq * V;
+
+    const int x0 = a.tiles[4 * tile + 0];
+    const int y0 = a.tiles[4 * tile + 1];
+    const int wh = a.tiles[4 * tile + 2];
+    const int chunk = a.tiles[4 * tile + 3];
+    const int w = wh & 0xffff;
+    const int h = wh >> 16;
+
+    const int RL = (TX + 2) * nz;             // LDS row stride (elements)
+    const bool has0 = tcol < w + 2;           // this thread fetches halo column tcol
+    const bool has1 = tcol + TX < w + 2;      // ... and column tcol + TX
+    const bool active = tcol < w;             // this thread computes column tcol
+    int gx0 = x0 - 1 + tcol;
+    gx0 = gx0 < 0 ? gx0 + nx : (gx0 >= nx ? gx0 - nx : gx0);
+    int gx1 = x0 - 1 + tcol + TX;
+    gx1 = gx1 >= nx ? gx1 - nx : gx1;
+    const T cc = static_cast<T>(a.cc), cn = static_cast<T>(a.cn), eps = static_cast<T>(a.eps);
+
+    double chk = 0.0, work = 0.0;
+    for (int f = 0; f < a.nfields; ++f) {
+        const T* fsrc = src + static_cast<int64_t>(f) * a.ncells;
+        T* fdst = dst + static_cast<int64_t>(f) * a.ncells;
+
+        auto fetch = [&](int i, Vec<T, V>& r0, Vec<T, V>& r1) {
+            int gy = y0 + i;
+            gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+            const T* row = fsrc + static_cast<int64_t>(gy) * nx * nz;
+            if (has0) r0 = ld<T, V>(row + static_cast<int64_t>(gx0) * nz + zoff);
+            if (has1) r1 = ld<T, V>(row + static_cast<int64_t>(gx1) * nz + zoff);
+        };
+        auto put = [&](int i, const Vec<T, V>& r0, const Vec<T, V>& r1) {
+            T* row = lds + (i & (kRingRows - 1)) * RL;
+            if (has0) st<T, V>(row + tcol * nz + zoff, r0);
+            if (has1) st<T, V>(row + (tcol + TX) * nz + zoff, r1);
+        };
+
+        Vec<T, V> p0, p1;
+        for (int i = -1; i <= 1; ++i) {  // prologue: rows y0-1, y0, y0+1
+            fetch(i, p0, p1);
+            put(i, p0, p1);
+        }
+        __syncthreads();
+
+        for (int r = 0; r < h; ++r) {
+            const bool pre = r + 2 <= h;
+            if (pre) fetch(r + 2, p0, p1);  // in flight during the compute below
+            if (active) {
+                const int gy = y0 + r;
+                const int k = column_k(a, hcx, hcy, x0 + tcol, gy);
+                const T* Lm = lds + ((r - 1) & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
+                const T* Lc = lds + (r & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
+                const T* Lp = lds + ((r + 1) & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
+                const Vec<T, V> c = ld<T, V>(Lc);
+                const Vec<T, V> xm = ld<T, V>(Lc - nz);
+                const Vec<T, V> xp = ld<T, V>(Lc + nz);
+                const Vec<T, V> ym = ld<T, V>(Lm);
+                const Vec<T, V> yp = ld<T, V>(Lp);
+                const T below = Lc[-1];  // neighbouring column's data when tzq == 0
+                const T above = Lc[V];   // ... when tzq == NQ - 1 (ignored then)
+                const T zlo = (tzq == 0) ? c.v[0] : below;
+                const T zhi = (tzq == NQ - 1) ? c.v[V - 1] : above;
+                T q[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T zm = (v == 0) ? zlo : c.v[v - 1];
+                    const T zp = (v == V - 1) ? zhi : c.v[v + 1];
+                    T sum = xm.v[v] + xp.v[v];
+                    sum = sum + ym.v[v];
+                    sum = sum + yp.v[v];
+                    sum = sum + zm;
+                    sum = sum + zp;
+                    q[v] = combine(cc, cn, c.v[v], sum);
+                }
+                physics_vec<KAHAN, T, V>(eps, k, q);
+                Vec<T, V> out;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    out.v[v] = q[v];
+                    chk += static_cast<double>(q[v]);
+                }
+                st<T, V>(fdst + (static_cast<int64_t>(gy) * nx + x0 + tcol) * nz + zoff, out);
+                if (tzq == 0) work += static_cast<double>(nz) * static_cast<double>(a.alpha + k);
+            }
+            if (pre) put(r + 2, p0, p1);
+            __syncthreads();
+        }
+    }
+    TileOut o;
+    o.checksum = block_sum(chk, red);
+    o.work = block_sum(work, red);
+    o.chunk = chunk;
+    return o;
+}
+
+// ---- step context --------------------------------------------------------------
+struct StepInfo {
+    uint64_t step;
+    int hcx[kMaxHot], hcy[kMaxHot];
+};
+
+__device__ __forceinline__ StepInfo step_info(const DevArgs& a) {
+    StepInfo s;
+    s.step = a.ctrl->step;
+    const int64_t t = a.t0 + static_cast<int64_t>(s.step);
+#pragma unroll
+    for (int h = 0; h < kMaxHot; ++h) {
+        s.hcx[h] = h < a.nhot ? wrap_mod(a.hx0[h] + static_cast<int64_t>(a.hvx[h]) * t, a.nx) : 0;
+        s.hcy[h] = h < a.nhot ? wrap_mod(a.hy0[h] + static_cast<int64_t>(a.hvy[h]) * t, a.ny) : 0;
+    }
+    return s;
+}
+
+__device__ __forceinline__ void record_tile(const DevArgs& a, int tile, const TileOut& o,
+                                            double ticks) {
+    a.partials[tile] = o.checksum;
+    unsafeAtomicAdd(&a.loads_work[o.chunk], o.work);
+    unsafeAtomicAdd(&a.loads_time[o.chunk], ticks);
+    atomicAdd(&a.visits[tile], 1);
+}
+
+// Deterministic sum of the per-tile partials into the checksum ring, then the
+// step counter moves on.  Run by one whole workgroup.
+__device__ void finish_step(const DevArgs& a, uint64_t step, double* red) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) acc += a.partials[i];
+    const double total = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        a.hist[step % kHistLen] = total;
+        a.ctrl->done = 0;
+        a.ctrl->step = step + 1;
+    }
+}
+
+// ---- claiming work ----------------------------------------------------------------
+__device__ __forceinline__ int home_slot(const DevArgs& a, int wg) {
+    if (a.xcd_slots) {
+        const int per_xcd = a.nslots / 8;
+        return (wg & 7) + 8 * ((wg >> 3) % per_xcd);
+    }
+    return wg % a.nslots;
+}
+
+__device__ __forceinline__ int try_claim(const DevArgs& a, int s) {
+    const int beg = a.seg[s];
+    const int n = a.seg[s + 1] - beg;
+    if (__hip_atomic_load(&a.heads[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) return -1;
+    const int i = atomicAdd(&a.heads[s], 1);
+    return i < n ? a.worklist[beg + i] : -1;
+}
+
+// Called by all lanes of wave 0.  Home queue first; then, if stealing is on,
+// scan the other queues 64 at a time (same-XCD slots first) and claim from
+// the first one with work left.  Every failed claim means that queue is empty
+// for good (heads only grow), so the scan ends after at most S failures.
+__device__ int claim(const DevArgs& a, int home) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int item = -1;
+    if (lane == 0) item = try_claim(a, home);
+    item = __shfl(item, 0, kWave);
+    if (item >= 0 || !a.steal) return item;
+    const int S = a.nslots;
+    const int per_xcd = a.xcd_slots ? S / 8 : S;
+    int base = 0;
+    while (base < S) {
+        const int j = base + lane;
+        int s = -1, rem = 0;
+        if (j < S && lane < static_cast<int>(blockDim.x)) {
+            s = a.xcd_slots ? (home + 8 * (j % per_xcd) + j / per_xcd) % S : (home + j) % S;
+            rem = (a.seg[s + 1] - a.seg[s]) -
+                  __hip_atomic_load(&a.heads[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint64_t mask = __ballot(rem > 0);
+        if (mask == 0) {
+            base += kWave;
+            continue;
+        }
+        const int victim = __shfl(s, __ffsll(static_cast<unsigned long long>(mask)) - 1, kWave);
+        int got = -1;
+        if (lane == 0) got = try_claim(a, victim);
+        got = __shfl(got, 0, kWave);
+        if (got >= 0) return got;
+    }
+    return -1;
+}
+
+// ---- kernels ----------------------------------------------------------------------
+template <typename T, int V, int KAHAN>
+__global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
+    extern __shared__ __align__(32) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    __shared__ double red[kMaxBlock / kWave];
+    __shared__ int s_item;
+    __shared__ int s_last;
+
+    const StepInfo si = step_info(a);
+    const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);
+    T* dst = static_cast<T*>((si.step & 1) ? a.field0 : a.field1);
+    const int home = home_slot(a, blockIdx.x);
+    double busy = 0.0;
+
+    for (;;) {
+        if (threadIdx.x < kWave) {
+            const int item = claim(a, home);
+            if (threadIdx.x == 0) s_item = item;
+        }
+        __syncthreads();
+        const int tile = s_item;
+        if (tile < 0) break;
+        const uint64_t t_start = wall_clock64();
+        const TileOut o = process_tile<T, V, KAHAN>(a, tile, src, dst, si.hcx, si.hcy, lds, red);
+        if (threadIdx.x == 0) {
+            const double ticks = static_cast<double>(wall_clock64() - t_start);
+            busy += ticks;
+            record_tile(a, tile, o, ticks);
+        }
+    }
+    if (threadIdx.x == 0) {
+        a.wg_busy[blockIdx.x] += busy;
+        __threadfence();
+        const uint32_t prev = atomicAdd(&a.ctrl->done, 1u);
+        s_last = (prev == static_cast<uint32_t>(a.nwg) - 1u);
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) a.heads[s] = 0;
+        finish_step(a, si.step, red);
+    }
+}
+
+template <typename T, int V, int KAHAN>
+__global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
+    extern __shared__ __align__(32) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    __shared__ double red[kMaxBlock / kWave];
+
+    const StepInfo si = step_info(a);
+    const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);
+    T* dst = static_cast<T*>((si.step & 1) ? a.field0 : a.field1);
+    const int tile = a.tile_off[chunk] + blockIdx.x;
+    const uint64_t t_start = wall_clock64();
+    const TileOut o = process_tile<T, V, KAHAN>(a, tile, src, dst, si.hcx, si.hcy, lds, red);
+    if (threadIdx.x == 0) record_tile(a, tile, o, static_cast<double>(wall_clock64() - t_start));
+}
+
+__global__ __launch_bounds__(256) void k_finish(DevArgs a) {
+    __shared__ double red[256 / kWave];
+    finish_step(a, a.ctrl->step, red);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + (n + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void k_init(T* q, int64_t n, uint64_t seed) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t m = static_cast<int64_t>(splitmix64(seed, static_cast<uint64_t>(i)) >> 40);
+        q[i] = static_cast<T>(static_cast<double>(m - 8388608) * (1.0 / 8388608.0));
+    }
+}
+
+__global__ void k_zero(uint32_t* p, size_t nwords) {
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < nwords;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k_reset_control(DevArgs a) {
+    for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) a.heads[s] = 0;
+    if (threadIdx.x == 0) {
+        a.ctrl->done = 0;
+        a.ctrl->step = 0;
+    }
+}
+
+// Field sum, pass 1: block b sums the contiguous range [b*n/B, (b+1)*n/B).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum1(const T* q, int64_t n, double* partial) {
+    __shared__ double red[256 / kWave];
+    const int64_t b = blockIdx.x, B = gridDim.x;
+    const int64_t lo = b * n / B, hi = (b + 1) * n / B;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += static_cast<double>(q[i]);
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[b] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum2(const double* partial, int nb, double* out) {
+    __shared__ double red[256 / kWave];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partial[i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ---- dispatch ------------------------------------------------------------------
+using PersistentFn = void (*)(DevArgs);
+using PlainFn = void (*)(DevArgs, int);
+
+template <typename T, int KAHAN>
+PersistentFn persistent_for(int vec) {
+    switch (vec) {
+        case 4: return k_persistent<T, 4, KAHAN>;
+        case 2: return k_persistent<T, 2, KAHAN>;
+        default: return k_persistent<T, 1, KAHAN>;
+    }
+}
+template <typename T, int KAHAN>
+PlainFn plain_for(int vec) {
+    switch (vec) {
+        case 4: return k_plain<T, 4, KAHAN>;
+        case 2: return k_plain<T, 2, KAHAN>;
+        default: return k_plain<T, 1, KAHAN>;
+    }
+}
+
+PersistentFn pick_persistent(int prec, int vec) {
+    if (prec == 2) return persistent_for<double, 0>(vec);
+    if (prec == 1) return persistent_for<float, 1>(vec);
+    return persistent_for<float, 0>(vec);
+}
+PlainFn pick_plain(int prec, int vec) {
+    if (prec == 2) return plain_for<double, 0>(vec);
+    if (prec == 1) return plain_for<float, 1>(vec);
+    return plain_for<float, 0>(vec);
+}
+
+}  // namespace
+
+int launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, size_t lds,
+                      void* stream) {
+    hipLaunchKernelGGL(pick_persistent(prec, vec), dim3(nwg), dim3(block), lds,
+                       static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int ntiles_chunk,
+                       int block, size_t lds, void* stream) {
+    hipLaunchKernelGGL(pick_plain(prec, vec), dim3(ntiles_chunk), dim3(block), lds,
+                       static_cast<hipStream_t>(stream), a, chunk);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_finish(const DevArgs& a, void* stream) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_reset_control(const DevArgs& a, void* stream) {
+    hipLaunchKernelGGL(k_reset_control, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_init_field(void* q, int prec, int64_t n, uint64_t seed, void* stream) {
+    const int64_t want = (n + 255) / 256;
+    const dim3 grid(static_cast<unsigned>(want < 65536 ? (want > 0 ? want : 1) : 65536));
+    if (prec == 2)
+        hipLaunchKernelGGL(k_init<double>, grid, dim3(256), 0, static_cast<hipStream_t>(stream),
+                           static_cast<double*>(q), n, seed);
+    else
+        hipLaunchKernelGGL(k_init<float>, grid, dim3(256), 0, static_cast<hipStream_t>(stream),
+                           static_cast<float*>(q), n, seed);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_zero(void* p, size_t bytes, void* stream) {
+    const size_t nwords = bytes / 4;
+    if (nwords == 0) return 0;
+    const size_t want = (nwords + 255) / 256;
+    const dim3 grid(static_cast<unsigned>(want < 4096 ? want : 4096));
+    hipLaunchKernelGGL(k_zero, grid, dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<uint32_t*>(p), nwords);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_field_sum(const void* q, int prec, int64_t n, double* partial, double* out,
+                     void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (prec == 2)
+        hipLaunchKernelGGL(k_sum1<double>, dim3(kSumBlocks), dim3(256), 0, s,
+                           static_cast<const double*>(q), n, partial);
+    else
+        hipLaunchKernelGGL(k_sum1<float>, dim3(kSumBlocks), dim3(256), 0, s,
+                           static_cast<const float*>(q), n, partial);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, partial, kSumBlocks, out);
+    return static_cast<int>(hipGetLastError());
+}
+
+}  // namespace lbgrid

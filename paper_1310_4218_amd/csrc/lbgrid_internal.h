@@ -1,0 +1,76 @@
+// Internal declarations shared by the kernels (kernels.hip), the host runtime
+// (runtime.cpp) and the host balancer (balance.cpp).  Not part of the ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace lbgrid {
+
+constexpr int kMaxHot = 4;
+constexpr int kHistLen = 1024;      // per-step checksum ring
+constexpr int kSumBlocks = 1024;    // first pass of the field sum
+constexpr int kRingRows = 4;        // LDS row ring of the tile kernel
+constexpr int kMaxBlock = 1024;
+constexpr size_t kMaxLds = 64 * 1024;
+
+// Device control block (first bytes of the workspace).
+struct Ctrl {
+    uint32_t done;          // workgroups finished in the current persistent launch
+    uint32_t pad0;
+    uint64_t step;          // steps completed since init
+    uint64_t pad1[6];
+};
+
+// Kernel arguments: every pointer is device memory inside the caller's buffers.
+struct DevArgs {
+    void* field0;
+    void* field1;
+    const int32_t* ktab;
+    const int32_t* tiles;      // 4 ints per tile: x0, y0, w | h << 16, chunk
+    const int32_t* tile_off;   // C + 1
+    const int32_t* worklist;   // ntiles tile ids, grouped by slot
+    const int32_t* seg;        // S + 1 offsets into worklist
+    int32_t* heads;            // S claim counters
+    Ctrl* ctrl;
+    double* loads_work;        // C
+    double* loads_time;        // C
+    double* partials;          // ntiles: sum of the tile's outputs in the last step
+    double* hist;              // kHistLen per-step sums
+    double* wg_busy;           // nwg
+    int32_t* visits;           // ntiles
+    int64_t ncells;            // cells per field
+    int32_t nx, ny, nz, nfields;
+    int32_t ntiles, nslots, nwg, steal;
+    int32_t tile_x;            // TX; block = TX * nz / V threads
+    int32_t r2cut;
+    int32_t kmin;
+    int32_t alpha;
+    int32_t nhot;
+    int32_t xcd_slots;         // 1: slot s is served by workgroups on XCD s % 8
+    int32_t hx0[kMaxHot], hy0[kMaxHot], hvx[kMaxHot], hvy[kMaxHot];
+    int64_t t0;
+    double cc, cn, eps;
+};
+
+// Kernel launchers (kernels.hip).  prec: 0 FP32, 1 FP32 Kahan, 2 FP64.
+int  launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, size_t lds,
+                       void* stream);
+int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int ntiles_chunk,
+                        int block, size_t lds, void* stream);
+int  launch_finish(const DevArgs& a, void* stream);
+int  launch_init_field(void* q, int prec, int64_t n, uint64_t seed, void* stream);
+int  launch_zero(void* p, size_t bytes, void* stream);
+int  launch_field_sum(const void* q, int prec, int64_t n, double* partial, double* out,
+                      void* stream);
+int  launch_reset_control(const DevArgs& a, void* stream);
+
+// Host balancer (balance.cpp).  Return 0 on success, -1 on bad arguments.
+enum Strategy { kGreedy = 0, kRefine = 1, kRefineSwap = 2 };
+int balance(const double* w, const int32_t* old_map, int32_t C, int32_t S, int strategy,
+            double threshold, int32_t* map_out);
+void block_map(int32_t C, int32_t S, int32_t* map_out);
+double imbalance(const double* w, const int32_t* map, int32_t C, int32_t S);
+
+}  // namespace lbgrid

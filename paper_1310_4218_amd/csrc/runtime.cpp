@@ -1,0 +1,704 @@
+// Host runtime of liblbgrid: the C ABI declared in include/lbgrid.h.
+//
+// A context owns the chunk table, the tiles (work items), the cost-field
+// table, the chunk->slot map and the per-slot work queues, and replays the
+// time step on the caller's stream.  The paper's migration loop (Fig. 2:
+// steps, then measure, then MPI_Migrate) maps onto
+//   lb_step (n steps)  ->  lb_measure (read the window's per-chunk loads)
+//   ->  lb_rebalance (new chunk->slot map; the queues are rebuilt in place, so
+//   captured graphs stay valid because only buffer contents change).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbgrid.h"
+#include "lbgrid_internal.h"
+
+using namespace lbgrid;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(std::string* where, int code, const std::string& msg) {
+    if (where) *where = msg;
+    g_err = msg;
+    return code;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Everything lb_query / lb_grid_init derive from a configuration.
+struct Plan {
+    int32_t nx = 0, ny = 0, nz = 0, nfields = 1, px = 0, py = 0, C = 0, S = 0, G = 0, nwg = 0;
+    int32_t prec = 0, vec = 1, elem = 4, TX = 16, TY = 16, block = 0, ntiles = 0;
+    int32_t r2cut = 0;
+    size_t lds = 0;
+    int64_t ncells = 0;
+    std::vector<int32_t> xs, ys;
+    // workspace layout (byte offsets)
+    size_t off_ctrl = 0, off_ktab = 0, off_tiles = 0, off_tileoff = 0, off_work = 0, off_seg = 0,
+           off_heads = 0, off_lw = 0, off_lt = 0, off_part = 0, off_hist = 0, off_busy = 0,
+           off_visits = 0, off_sum = 0, ws_bytes = 0;
+    size_t field_bytes = 0;
+};
+
+bool strictly_increasing(const std::vector<int32_t>& s, int32_t n) {
+    if (s.front() != 0 || s.back() != n) return false;
+    for (size_t i = 1; i < s.size(); ++i)
+        if (s[i] <= s[i - 1]) return false;
+    return true;
+}
+
+// Largest r^2 whose table entry can exceed kmin, plus one: beyond it
+// (kmax-kmin)*exp(-r^2/(2 sigma^2)) < exp(-1/(2 sigma^2)) < 1.
+int64_t cost_table_cut(double sigma, int32_t kmin, int32_t kmax) {
+    const int32_t span = kmax - kmin;
+    if (span <= 0) return 0;
+    return static_cast<int64_t>(std::ceil(2.0 * sigma * sigma * std::log(static_cast<double>(span)))) + 1;
+}
+
+int make_plan(const lb_config* c, Plan& p, std::string* err) {
+    if (!c) return fail(err, LB_E_INVAL, "config is NULL");
+    auto bad = [&](const char* what) { return fail(err, LB_E_INVAL, std::string("invalid config: ") + what); };
+    if (c->nx < 1 || c->ny < 1 || c->nx > 32768 || c->ny > 32768) return bad("nx, ny must be in [1, 32768]");
+    if (c->nz < 1 || c->nz > 4096) return bad("nz must be in [1, 4096]");
+    if (c->nfields < 1 || c->nfields > 1024) return bad("nfields must be in [1, 1024]");
+    if (c->px < 1 || c->px > c->nx || c->py < 1 || c->py > c->ny) return bad("px, py must be in [1, nx], [1, ny]");
+    if (c->precision < LB_FP32 || c->precision > LB_FP64) return bad("precision");
+    if (!std::isfinite(c->c_center) || !std::isfinite(c->c_nbr) || !std::isfinite(c->eps)) return bad("coefficients must be finite");
+    if (c->nhot < 0 || c->nhot > LB_MAX_HOT) return bad("nhot must be in [0, 4]");
+    if (c->kmin < 0 || c->kmax < c->kmin || c->kmax > 1000000) return bad("need 0 <= kmin <= kmax <= 1e6");
+    if (c->nhot > 0 && c->kmax > c->kmin && !(c->sigma > 0.0 && c->sigma <= 1e5)) return bad("sigma must be in (0, 1e5]");
+    if (c->alpha_work < 0) return bad("alpha_work must be >= 0");
+    if (c->nslots < 1 || c->nslots > 65536) return bad("nslots must be in [1, 65536]");
+    if (c->wg_per_slot < 0) return bad("wg_per_slot must be >= 0");
+    if (c->tile_x < 0 || c->tile_y < 0) return bad("tile sizes must be >= 0");
+    if (c->graph_steps < 1 || c->graph_steps > 1000) return bad("graph_steps must be in [1, 1000]");
+    if (c->steal != 0 && c->steal != 1) return bad("steal must be 0 or 1");
+
+    p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
+    p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
+    p.prec = c->precision;
+    p.elem = (p.prec == LB_FP64) ? 8 : 4;
+    p.vec = (p.nz % 4 == 0) ? 4 : (p.nz % 2 == 0) ? 2 : 1;
+    p.ncells = static_cast<int64_t>(p.nx) * p.ny * p.nz;
+
+    p.xs.resize(p.px + 1);
+    p.ys.resize(p.py + 1);
+    for (int i = 0; i <= p.px; ++i)
+        p.xs[i] = c->xsplit ? c->xsplit[i] : static_cast<int32_t>((static_cast<int64_t>(i) * p.nx) / p.px);
+    for (int j = 0; j <= p.py; ++j)
+        p.ys[j] = c->ysplit ? c->ysplit[j] : static_cast<int32_t>((static_cast<int64_t>(j) * p.ny) / p.py);
+    if (!strictly_increasing(p.xs, p.nx)) return bad("xsplit must rise strictly from 0 to nx");
+    if (!strictly_increasing(p.ys, p.ny)) return bad("ysplit must rise strictly from 0 to ny");
+
+    const int NQ = p.nz / p.vec;
+    const size_t row_elems_per_col = static_cast<size_t>(p.nz) * p.elem * kRingRows;
+    if (c->tile_x > 0) {
+        p.TX = c->tile_x;
+    } else {
+        p.TX = 16;
+        while (p.TX > 1 && (p.TX * NQ > kMaxBlock || (p.TX + 2) * row_elems_per_col > kMaxLds)) --p.TX;
+    }
+    p.TY = c->tile_y > 0 ? c->tile_y : 16;
+    if (p.TX > 32767 || p.TY > 32767) return bad("tile sizes must be < 32768");
+    p.block = p.TX * NQ;
+    if (p.block > kMaxBlock) return bad("tile_x * nz / vector width exceeds 1024 threads");
+    p.lds = (p.TX + 2) * row_elems_per_col;
+    if (p.lds > kMaxLds) return bad("tile_x too large: the LDS row ring exceeds 64 KiB");
+
+    // tiles of every chunk, chunks in id order, tiles in raster order
+    int64_t nt = 0;
+    for (int j = 0; j < p.py; ++j)
+        for (int i = 0; i < p.px; ++i) {
+            const int64_t w = p.xs[i + 1] - p.xs[i], h = p.ys[j + 1] - p.ys[j];
+            nt += ((w + p.TX - 1) / p.TX) * ((h + p.TY - 1) / p.TY);
+        }
+    if (nt > (int64_t{1} << 30)) return bad("too many tiles");
+    p.ntiles = static_cast<int32_t>(nt);
+
+    p.G = c->wg_per_slot > 0 ? c->wg_per_slot : std::max(1, 2048 / p.S);
+    const int64_t nwg = static_cast<int64_t>(p.S) * p.G;
+    if (nwg > 65536) return bad("nslots * wg_per_slot must be <= 65536");
+    p.nwg = static_cast<int32_t>(nwg);
+
+    const int64_t cut = (c->nhot > 0) ? cost_table_cut(c->sigma, c->kmin, c->kmax) : 0;
+    if (cut > (int64_t{1} << 26)) return bad("cost table too large (sigma too wide for kmax - kmin)");
+    p.r2cut = static_cast<int32_t>(cut);
+
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+    p.off_ctrl = take(sizeof(Ctrl));
+    p.off_ktab = take(sizeof(int32_t) * (static_cast<size_t>(p.r2cut) + 1));
+    p.off_tiles = take(sizeof(int32_t) * 4 * static_cast<size_t>(p.ntiles));
+    p.off_tileoff = take(sizeof(int32_t) * (static_cast<size_t>(p.C) + 1));
+    p.off_work = take(sizeof(int32_t) * static_cast<size_t>(p.ntiles));
+    p.off_seg = take(sizeof(int32_t) * (static_cast<size_t>(p.S) + 1));
+    p.off_heads = take(sizeof(int32_t) * static_cast<size_t>(p.S));
+    p.off_lw = take(sizeof(double) * static_cast<size_t>(p.C));
+    p.off_lt = take(sizeof(double) * static_cast<size_t>(p.C));
+    p.off_part = take(sizeof(double) * static_cast<size_t>(p.ntiles));
+    p.off_hist = take(sizeof(double) * kHistLen);
+    p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg));
+    p.off_visits = take(sizeof(int32_t) * static_cast<size_t>(p.ntiles));
+    p.off_sum = take(sizeof(double) * (kSumBlocks + 1));
+    p.ws_bytes = o;
+    p.field_bytes = static_cast<size_t>(p.ncells) * p.nfields * p.elem;
+    return LB_OK;
+}
+
+}  // namespace
+
+struct lb_ctx {
+    lb_config cfg{};
+    Plan plan;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    void* field[2] = {nullptr, nullptr};
+    char* ws = nullptr;
+    DevArgs args{};
+    std::vector<int32_t> tiles;       // 4 per tile
+    std::vector<int32_t> tile_off;    // C + 1
+    std::vector<int32_t> map;         // C
+    std::vector<double> measured;     // loads kept by the last lb_measure
+    bool have_measured = false;
+    int64_t steps = 0;
+    int64_t window_steps = 0;
+    double clock_hz = 100e6;
+    int32_t* staging = nullptr;       // pinned: worklist + seg for uploads
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
+    hipGraphExec_t g_pers1 = nullptr; // one persistent step
+    hipGraphExec_t g_plain = nullptr; // one plain step
+    std::string err;
+};
+
+namespace {
+
+#define HIP_TRY(ctx, expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx) ? &(ctx)->err : nullptr, LB_E_HIP,                                \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+    } while (0)
+
+#define LAUNCH_TRY(ctx, expr)                                                                   \
+    do {                                                                                        \
+        int e_ = (expr);                                                                        \
+        if (e_ != 0)                                                                            \
+            return fail(&(ctx)->err, LB_E_HIP,                                                  \
+                        std::string(#expr) + ": " +                                            \
+                            hipGetErrorString(static_cast<hipError_t>(e_)));                   \
+    } while (0)
+
+const char* fail_site() { return std::getenv("LBGRID_FAIL_AT"); }
+bool forced_failure(const char* site) {
+    const char* f = fail_site();
+    return f && std::strcmp(f, site) == 0;
+}
+
+void build_tiles(lb_ctx* x) {
+    const Plan& p = x->plan;
+    x->tiles.clear();
+    x->tiles.reserve(static_cast<size_t>(p.ntiles) * 4);
+    x->tile_off.assign(static_cast<size_t>(p.C) + 1, 0);
+    int32_t t = 0;
+    for (int j = 0; j < p.py; ++j)
+        for (int i = 0; i < p.px; ++i) {
+            const int c = j * p.px + i;
+            x->tile_off[c] = t;
+            for (int y = p.ys[j]; y < p.ys[j + 1]; y += p.TY)
+                for (int xx = p.xs[i]; xx < p.xs[i + 1]; xx += p.TX) {
+                    const int w = std::min(p.TX, p.xs[i + 1] - xx);
+                    const int h = std::min(p.TY, p.ys[j + 1] - y);
+                    x->tiles.insert(x->tiles.end(), {xx, y, w | (h << 16), c});
+                    ++t;
+                }
+        }
+    x->tile_off[p.C] = t;
+}
+
+std::vector<int32_t> build_cost_table(const lb_config& c, int32_t r2cut) {
+    std::vector<int32_t> tab(static_cast<size_t>(r2cut) + 1);
+    const double span = static_cast<double>(c.kmax - c.kmin);
+    for (int32_t r2 = 0; r2 <= r2cut; ++r2) {
+        const double g = std::exp(-static_cast<double>(r2) / (2.0 * c.sigma * c.sigma));
+        tab[r2] = c.kmin + static_cast<int32_t>(std::floor(span * g));
+    }
+    if (c.nhot == 0 || c.kmax == c.kmin) tab.assign(tab.size(), c.kmin);
+    return tab;
+}
+
+// Per-slot queues: the tiles of each slot's chunks, chunks in descending
+// per-tile cost (cost_c / ntiles_c), ties by chunk id, tiles in raster order.
+int upload_queues(lb_ctx* x, const double* cost) {
+    const Plan& p = x->plan;
+    std::vector<std::vector<int32_t>> by_slot(static_cast<size_t>(p.S));
+    for (int32_t c = 0; c < p.C; ++c) by_slot[x->map[c]].push_back(c);
+    std::vector<double> per_tile(static_cast<size_t>(p.C), 0.0);
+    for (int32_t c = 0; c < p.C; ++c) {
+        const int32_t nt = x->tile_off[c + 1] - x->tile_off[c];
+        per_tile[c] = cost ? cost[c] / static_cast<double>(nt) : 0.0;
+    }
+    if (x->upload_pending) {
+        HIP_TRY(x, hipEventSynchronize(x->upload_done));
+        x->upload_pending = false;
+    }
+    int32_t* work = x->staging;
+    int32_t* seg = x->staging + p.ntiles;
+    int32_t n = 0;
+    for (int32_t s = 0; s < p.S; ++s) {
+        seg[s] = n;
+        auto& v = by_slot[s];
+        std::stable_sort(v.begin(), v.end(),
+                         [&](int32_t a, int32_t b) { return per_tile[a] > per_tile[b]; });
+        for (int32_t c : v)
+            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) work[n++] = t;
+    }
+    seg[p.S] = n;
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_work, work, sizeof(int32_t) * p.ntiles,
+                              hipMemcpyHostToDevice, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_seg, seg, sizeof(int32_t) * (p.S + 1),
+                              hipMemcpyHostToDevice, x->stream));
+    HIP_TRY(x, hipEventRecord(x->upload_done, x->stream));
+    x->upload_pending = true;
+    return LB_OK;
+}
+
+int capture(lb_ctx* x, int mode, int nsteps, hipGraphExec_t* out) {
+    const Plan& p = x->plan;
+    hipGraph_t g = nullptr;
+    HIP_TRY(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
+    int rc = 0;
+    for (int i = 0; i < nsteps && rc == 0; ++i) {
+        if (mode == LB_PERSISTENT) {
+            rc = launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, x->cap);
+        } else {
+            for (int32_t c = 0; c < p.C && rc == 0; ++c)
+                rc = launch_plain_chunk(x->args, p.prec, p.vec, c, x->tile_off[c + 1] - x->tile_off[c],
+                                        p.block, p.lds, x->cap);
+            if (rc == 0) rc = launch_finish(x->args, x->cap);
+        }
+    }
+    hipError_t e = hipStreamEndCapture(x->cap, &g);
+    if (rc != 0 || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        const hipError_t shown = rc != 0 ? static_cast<hipError_t>(rc) : e;
+        return fail(&x->err, LB_E_HIP, std::string("graph capture: ") + hipGetErrorString(shown));
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(&x->err, LB_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return LB_OK;
+}
+
+int sync(lb_ctx* x) {
+    HIP_TRY(x, hipSetDevice(x->device));
+    if (forced_failure("sync")) return fail(&x->err, LB_E_HIP, "forced failure at sync (LBGRID_FAIL_AT)");
+    HIP_TRY(x, hipStreamSynchronize(x->stream));
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_abi_version(void) { return LB_ABI_VERSION; }
+size_t lb_config_bytes(void) { return sizeof(lb_config); }
+size_t lb_stats_bytes(void) { return sizeof(lb_stats_t); }
+
+void lb_config_default(lb_config* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->nx = c->ny = 64;
+    c->nz = 32;
+    c->nfields = 1;
+    c->px = c->py = 4;
+    c->precision = LB_FP32;
+    c->c_center = 0.4;
+    c->c_nbr = 0.1;
+    c->eps = 0.01;
+    c->nhot = 0;
+    c->sigma = 8.0;
+    c->kmin = 1;
+    c->kmax = 1;
+    c->alpha_work = 32;
+    c->nslots = 256;
+    c->wg_per_slot = 0;
+    c->tile_x = 0;
+    c->tile_y = 0;
+    c->steal = 1;
+    c->graph_steps = 10;
+}
+
+int lb_query(const lb_config* cfg, lb_buffers* out) {
+    if (!out) return fail(nullptr, LB_E_INVAL, "sizes_out is NULL");
+    Plan p;
+    int rc = make_plan(cfg, p, nullptr);
+    if (rc != LB_OK) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->bytes[0] = p.field_bytes;
+    out->bytes[1] = p.field_bytes;
+    out->bytes[2] = p.ws_bytes;
+    return LB_OK;
+}
+
+int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
+                 const void* init_field, lb_ctx** out) {
+    if (!out) return fail(nullptr, LB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!bufs) return fail(nullptr, LB_E_INVAL, "buffers are NULL");
+    Plan p;
+    int rc = make_plan(cfg, p, nullptr);
+    if (rc != LB_OK) return rc;
+    const size_t need[3] = {p.field_bytes, p.field_bytes, p.ws_bytes};
+    for (int i = 0; i < LB_NBUF; ++i) {
+        if (!bufs->ptr[i]) return fail(nullptr, LB_E_INVAL, "buffer " + std::to_string(i) + " is NULL");
+        if (bufs->bytes[i] < need[i])
+            return fail(nullptr, LB_E_NOMEM, "buffer " + std::to_string(i) + " too small: " +
+                                                 std::to_string(bufs->bytes[i]) + " < " + std::to_string(need[i]));
+        if (reinterpret_cast<uintptr_t>(bufs->ptr[i]) % kAlign != 0)
+            return fail(nullptr, LB_E_INVAL, "buffer " + std::to_string(i) + " is not 256-byte aligned");
+    }
+    if (forced_failure("init")) return fail(nullptr, LB_E_HIP, "forced failure at init (LBGRID_FAIL_AT)");
+
+    lb_ctx* x = new (std::nothrow) lb_ctx();
+    if (!x) return fail(nullptr, LB_E_NOMEM, "out of host memory");
+    x->cfg = *cfg;
+    x->cfg.xsplit = nullptr;  // copied into the plan
+    x->cfg.ysplit = nullptr;
+    x->plan = std::move(p);
+    const Plan& P = x->plan;
+    x->stream = static_cast<hipStream_t>(hip_stream);
+    x->field[0] = bufs->ptr[0];
+    x->field[1] = bufs->ptr[1];
+    x->ws = static_cast<char*>(bufs->ptr[2]);
+
+    auto bail = [&](int code) {
+        lb_destroy(x);
+        return code;
+    };
+    auto hip_bail = [&](hipError_t e, const char* what) {
+        fail(nullptr, LB_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+        return bail(LB_E_HIP);
+    };
+    hipError_t e;
+    if ((e = hipGetDevice(&x->device)) != hipSuccess) return hip_bail(e, "hipGetDevice");
+    int wall_khz = 0;
+    if ((e = hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, x->device)) != hipSuccess)
+        return hip_bail(e, "hipDeviceGetAttribute(WallClockRate)");
+    if (wall_khz > 0) x->clock_hz = 1e3 * wall_khz;
+    if ((e = hipStreamCreateWithFlags(&x->cap, hipStreamNonBlocking)) != hipSuccess)
+        return hip_bail(e, "hipStreamCreateWithFlags");
+    if ((e = hipEventCreateWithFlags(&x->upload_done, hipEventDisableTiming)) != hipSuccess)
+        return hip_bail(e, "hipEventCreateWithFlags");
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&x->staging),
+                           sizeof(int32_t) * (static_cast<size_t>(P.ntiles) + P.S + 1))) != hipSuccess)
+        return hip_bail(e, "hipHostMalloc");
+
+    build_tiles(x);
+    const std::vector<int32_t> ktab = build_cost_table(*cfg, P.r2cut);
+
+    DevArgs& a = x->args;
+    a.field0 = x->field[0];
+    a.field1 = x->field[1];
+    a.ktab = reinterpret_cast<const int32_t*>(x->ws + P.off_ktab);
+    a.tiles = reinterpret_cast<const int32_t*>(x->ws + P.off_tiles);
+    a.tile_off = reinterpret_cast<const int32_t*>(x->ws + P.off_tileoff);
+    a.worklist = reinterpret_cast<const int32_t*>(x->ws + P.off_work);
+    a.seg = reinterpret_cast<const int32_t*>(x->ws + P.off_seg);
+    a.heads = reinterpret_cast<int32_t*>(x->ws + P.off_heads);
+    a.ctrl = reinterpret_cast<Ctrl*>(x->ws + P.off_ctrl);
+    a.loads_work = reinterpret_cast<double*>(x->ws + P.off_lw);
+    a.loads_time = reinterpret_cast<double*>(x->ws + P.off_lt);
+    a.partials = reinterpret_cast<double*>(x->ws + P.off_part);
+    a.hist = reinterpret_cast<double*>(x->ws + P.off_hist);
+    a.wg_busy = reinterpret_cast<double*>(x->ws + P.off_busy);
+    a.visits = reinterpret_cast<int32_t*>(x->ws + P.off_visits);
+    a.ncells = P.ncells;
+    a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.nfields = P.nfields;
+    a.ntiles = P.ntiles; a.nslots = P.S; a.nwg = P.nwg; a.steal = cfg->steal;
+    a.tile_x = P.TX;
+    a.r2cut = P.r2cut;
+    a.kmin = cfg->kmin;
+    a.alpha = cfg->alpha_work;
+    a.nhot = cfg->nhot;
+    a.xcd_slots = (P.S % 8 == 0 && P.nwg % 8 == 0) ? 1 : 0;
+    for (int h = 0; h < kMaxHot; ++h) {
+        a.hx0[h] = cfg->hx0[h]; a.hy0[h] = cfg->hy0[h];
+        a.hvx[h] = cfg->hvx[h]; a.hvy[h] = cfg->hvy[h];
+    }
+    a.t0 = cfg->t0;
+    a.cc = cfg->c_center; a.cn = cfg->c_nbr; a.eps = cfg->eps;
+
+    x->err.clear();
+    int r;
+    // zero the whole workspace, then fill tables
+    if ((r = launch_zero(x->ws, P.ws_bytes, x->stream)) != 0) return hip_bail(static_cast<hipError_t>(r), "zero workspace");
+    if ((e = hipMemcpyAsync(x->ws + P.off_ktab, ktab.data(), sizeof(int32_t) * ktab.size(),
+                            hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload cost table");
+    if ((e = hipMemcpyAsync(x->ws + P.off_tiles, x->tiles.data(), sizeof(int32_t) * x->tiles.size(),
+                            hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload tiles");
+    if ((e = hipMemcpyAsync(x->ws + P.off_tileoff, x->tile_off.data(), sizeof(int32_t) * x->tile_off.size(),
+                            hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload tile offsets");
+    if ((r = launch_reset_control(a, x->stream)) != 0) return hip_bail(static_cast<hipError_t>(r), "reset control");
+    if (init_field) {
+        if ((e = hipMemcpyAsync(x->field[0], init_field, P.field_bytes, hipMemcpyDefault, x->stream)) != hipSuccess)
+            return hip_bail(e, "copy initial field");
+    } else {
+        if ((r = launch_init_field(x->field[0], P.prec, P.ncells * P.nfields, cfg->seed, x->stream)) != 0)
+            return hip_bail(static_cast<hipError_t>(r), "init field");
+    }
+    x->map.assign(static_cast<size_t>(P.C), 0);
+    block_map(P.C, P.S, x->map.data());
+    if ((r = upload_queues(x, nullptr)) != LB_OK) {
+        g_err = x->err;
+        return bail(r);
+    }
+    if ((e = hipStreamSynchronize(x->stream)) != hipSuccess) return hip_bail(e, "hipStreamSynchronize");
+    *out = x;
+    return LB_OK;
+}
+
+int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
+    if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(&x->err, LB_E_INVAL, "nsteps must be >= 0");
+    if (mode < LB_PLAIN || mode > LB_PERSISTENT_EAGER) return fail(&x->err, LB_E_INVAL, "unknown mode");
+    if (forced_failure("step")) return fail(&x->err, LB_E_HIP, "forced failure at step (LBGRID_FAIL_AT)");
+    HIP_TRY(x, hipSetDevice(x->device));
+    const Plan& p = x->plan;
+    if (nsteps == 0) return LB_OK;
+    int rc;
+    switch (mode) {
+        case LB_PERSISTENT: {
+            const int R = x->cfg.graph_steps;
+            if (nsteps >= R && !x->g_pers && (rc = capture(x, LB_PERSISTENT, R, &x->g_pers)) != LB_OK) return rc;
+            if (nsteps % R && !x->g_pers1 && (rc = capture(x, LB_PERSISTENT, 1, &x->g_pers1)) != LB_OK) return rc;
+            for (int i = 0; i < nsteps / R; ++i) HIP_TRY(x, hipGraphLaunch(x->g_pers, x->stream));
+            for (int i = 0; i < nsteps % R; ++i) HIP_TRY(x, hipGraphLaunch(x->g_pers1, x->stream));
+            break;
+        }
+        case LB_PERSISTENT_EAGER:
+            for (int i = 0; i < nsteps; ++i)
+                LAUNCH_TRY(x, launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, x->stream));
+            break;
+        case LB_PLAIN_GRAPH:
+            if (!x->g_plain && (rc = capture(x, LB_PLAIN, 1, &x->g_plain)) != LB_OK) return rc;
+            for (int i = 0; i < nsteps; ++i) HIP_TRY(x, hipGraphLaunch(x->g_plain, x->stream));
+            break;
+        default:  // LB_PLAIN
+            for (int i = 0; i < nsteps; ++i) {
+                for (int32_t c = 0; c < p.C; ++c)
+                    LAUNCH_TRY(x, launch_plain_chunk(x->args, p.prec, p.vec, c,
+                                                     x->tile_off[c + 1] - x->tile_off[c], p.block, p.lds,
+                                                     x->stream));
+                LAUNCH_TRY(x, launch_finish(x->args, x->stream));
+            }
+    }
+    x->steps += nsteps;
+    x->window_steps += nsteps;
+    return LB_OK;
+}
+
+int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
+    if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (source != LB_LOAD_WORK && source != LB_LOAD_TIME) return fail(&x->err, LB_E_INVAL, "unknown load source");
+    int rc = sync(x);
+    if (rc != LB_OK) return rc;
+    const Plan& p = x->plan;
+    x->measured.resize(static_cast<size_t>(p.C));
+    HIP_TRY(x, hipMemcpy(x->measured.data(), x->ws + (source == LB_LOAD_WORK ? p.off_lw : p.off_lt),
+                         sizeof(double) * p.C, hipMemcpyDeviceToHost));
+    x->have_measured = true;
+    if (loads_out) std::memcpy(loads_out, x->measured.data(), sizeof(double) * p.C);
+    if (reset) {
+        LAUNCH_TRY(x, launch_zero(x->ws + p.off_lw, sizeof(double) * p.C, x->stream));
+        LAUNCH_TRY(x, launch_zero(x->ws + p.off_lt, sizeof(double) * p.C, x->stream));
+        LAUNCH_TRY(x, launch_zero(x->ws + p.off_busy, sizeof(double) * p.nwg, x->stream));
+        x->window_steps = 0;
+    }
+    return LB_OK;
+}
+
+int lb_balance_host(const double* loads, const int32_t* old_map, int32_t C, int32_t S,
+                    int32_t strategy, double threshold, int32_t* map_out, int32_t* nmigrated) {
+    if (C < 0 || S < 1) return fail(nullptr, LB_E_INVAL, "need C >= 0 and S >= 1");
+    if (C > 0 && (!loads || !map_out)) return fail(nullptr, LB_E_INVAL, "loads and map_out are required");
+    if (strategy != LB_GREEDY && strategy != LB_REFINE && strategy != LB_REFINESWAP)
+        return fail(nullptr, LB_E_INVAL, "unknown strategy");
+    std::vector<int32_t> base(static_cast<size_t>(C));
+    if (old_map) {
+        for (int32_t c = 0; c < C; ++c) {
+            if (old_map[c] < 0 || old_map[c] >= S) return fail(nullptr, LB_E_INVAL, "old_map entry out of range");
+            base[c] = old_map[c];
+        }
+    } else {
+        if (strategy != LB_GREEDY) return fail(nullptr, LB_E_INVAL, "refinement needs old_map");
+        block_map(C, S, base.data());
+    }
+    int rc = balance(loads, base.data(), C, S, strategy, threshold, map_out);
+    if (rc == -2) return fail(nullptr, LB_E_UNSUPPORTED, "strategy not implemented");
+    if (rc != 0) return fail(nullptr, LB_E_INVAL, "invalid loads or threshold (loads must be >= 0, threshold > 0)");
+    if (nmigrated) {
+        int32_t n = 0;
+        for (int32_t c = 0; c < C; ++c) n += (map_out[c] != base[c]);
+        *nmigrated = n;
+    }
+    return LB_OK;
+}
+
+int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* loads,
+                 int32_t* map_out, int32_t* nmigrated, double* lam) {
+    if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    const Plan& p = x->plan;
+    const double* w = loads;
+    if (!w) {
+        if (!x->have_measured) return fail(&x->err, LB_E_STATE, "no measured loads: call lb_measure first or pass loads");
+        w = x->measured.data();
+    }
+    std::vector<int32_t> nm(static_cast<size_t>(p.C));
+    int32_t mig = 0;
+    int rc = lb_balance_host(w, x->map.data(), p.C, p.S, strategy, threshold, nm.data(), &mig);
+    if (rc != LB_OK) {
+        x->err = g_err;
+        return rc;
+    }
+    const double before = imbalance(w, x->map.data(), p.C, p.S);
+    const double after = imbalance(w, nm.data(), p.C, p.S);
+    x->map = nm;
+    HIP_TRY(x, hipSetDevice(x->device));
+    if ((rc = upload_queues(x, w)) != LB_OK) return rc;
+    if (map_out) std::memcpy(map_out, nm.data(), sizeof(int32_t) * p.C);
+    if (nmigrated) *nmigrated = mig;
+    if (lam) {
+        lam[0] = before;
+        lam[1] = after;
+    }
+    return LB_OK;
+}
+
+int lb_set_map(lb_ctx* x, const int32_t* map, const double* cost) {
+    if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (!map) return fail(&x->err, LB_E_INVAL, "map is NULL");
+    const Plan& p = x->plan;
+    for (int32_t c = 0; c < p.C; ++c)
+        if (map[c] < 0 || map[c] >= p.S) return fail(&x->err, LB_E_INVAL, "map entry out of range");
+    if (cost)
+        for (int32_t c = 0; c < p.C; ++c)
+            if (!(cost[c] >= 0.0)) return fail(&x->err, LB_E_INVAL, "costs must be >= 0");
+    x->map.assign(map, map + p.C);
+    HIP_TRY(x, hipSetDevice(x->device));
+    return upload_queues(x, cost);
+}
+
+int lb_fields(lb_ctx* x, int32_t field, void* dst, size_t dst_bytes, double* checksum_out) {
+    if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    const Plan& p = x->plan;
+    if (field < 0 || field >= p.nfields) return fail(&x->err, LB_E_INVAL, "field index out of range");
+    const size_t bytes = static_cast<size_t>(p.ncells) * p.elem;
+    if (dst && dst_bytes < bytes) return fail(&x->err, LB_E_NOMEM, "dst too small");
+    HIP_TRY(x, hipSetDevice(x->device));
+    const char* cur = static_cast<const char*>(x->field[x->steps & 1]) + static_cast<size_t>(field) * bytes;
+    if (checksum_out) {
+        double* part = reinterpret_cast<double*>(x->ws + p.off_sum);
+        LAUNCH_TRY(x, launch_field_sum(cur, p.prec, p.ncells, part, part + kSumBlocks, x->stream));
+    }
+    if (dst) HIP_TRY(x, hipMemcpyAsync(dst, cur, bytes, hipMemcpyDefault, x->stream));
+    int rc = sync(x);
+    if (rc != LB_OK) return rc;
+    if (checksum_out)
+        HIP_TRY(x, hipMemcpy(checksum_out, x->ws + p.off_sum + sizeof(double) * kSumBlocks, sizeof(double),
+                             hipMemcpyDeviceToHost));
+    return LB_OK;
+}
+
+int lb_stats(lb_ctx* x, lb_stats_t* out) {
+    if (!x || !out) return fail(x ? &x->err : nullptr, LB_E_INVAL, "ctx and out are required");
+    int rc = sync(x);
+    if (rc != LB_OK) return rc;
+    const Plan& p = x->plan;
+    std::memset(out, 0, sizeof(*out));
+    out->steps = x->steps;
+    out->nchunks = p.C;
+    out->ntiles = p.ntiles;
+    out->nslots = p.S;
+    out->nwg = p.nwg;
+    out->block = p.block;
+    out->tile_x = p.TX;
+    out->tile_y = p.TY;
+    out->clock_hz = x->clock_hz;
+    out->measured_steps = x->window_steps;
+    if (x->steps > 0)
+        HIP_TRY(x, hipMemcpy(&out->last_checksum,
+                             x->ws + p.off_hist + sizeof(double) * ((x->steps - 1) % kHistLen),
+                             sizeof(double), hipMemcpyDeviceToHost));
+    return LB_OK;
+}
+
+int lb_wg_busy(lb_ctx* x, double* out, int32_t n) {
+    if (!x || !out) return fail(x ? &x->err : nullptr, LB_E_INVAL, "ctx and out are required");
+    if (n < x->plan.nwg) return fail(&x->err, LB_E_NOMEM, "out too small for nwg entries");
+    int rc = sync(x);
+    if (rc != LB_OK) return rc;
+    HIP_TRY(x, hipMemcpy(out, x->ws + x->plan.off_busy, sizeof(double) * x->plan.nwg, hipMemcpyDeviceToHost));
+    return LB_OK;
+}
+
+int lb_visits(lb_ctx* x, int32_t* out, int32_t n, int32_t reset) {
+    if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    const Plan& p = x->plan;
+    if (out && n < p.ntiles) return fail(&x->err, LB_E_NOMEM, "out too small for ntiles entries");
+    int rc = sync(x);
+    if (rc != LB_OK) return rc;
+    if (out) HIP_TRY(x, hipMemcpy(out, x->ws + p.off_visits, sizeof(int32_t) * p.ntiles, hipMemcpyDeviceToHost));
+    if (reset) {
+        LAUNCH_TRY(x, launch_zero(x->ws + p.off_visits, sizeof(int32_t) * p.ntiles, x->stream));
+        return sync(x);
+    }
+    return LB_OK;
+}
+
+int lb_checksums(lb_ctx* x, double* out, int32_t n, int32_t* got) {
+    if (!x || !out || !got) return fail(x ? &x->err : nullptr, LB_E_INVAL, "ctx, out and got are required");
+    int rc = sync(x);
+    if (rc != LB_OK) return rc;
+    const int64_t avail = std::min<int64_t>(x->steps, kHistLen);
+    const int64_t m = std::min<int64_t>(avail, std::max(n, 0));
+    std::vector<double> ring(kHistLen);
+    HIP_TRY(x, hipMemcpy(ring.data(), x->ws + x->plan.off_hist, sizeof(double) * kHistLen, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) out[i] = ring[(x->steps - m + i) % kHistLen];
+    *got = static_cast<int32_t>(m);
+    return LB_OK;
+}
+
+void lb_destroy(lb_ctx* x) {
+    if (!x) return;
+    (void)hipSetDevice(x->device);
+    if (x->stream || x->cap) (void)hipStreamSynchronize(x->stream);
+    if (x->g_pers) (void)hipGraphExecDestroy(x->g_pers);
+    if (x->g_pers1) (void)hipGraphExecDestroy(x->g_pers1);
+    if (x->g_plain) (void)hipGraphExecDestroy(x->g_plain);
+    if (x->upload_done) (void)hipEventDestroy(x->upload_done);
+    if (x->staging) (void)hipHostFree(x->staging);
+    if (x->cap) (void)hipStreamDestroy(x->cap);
+    delete x;
+}
+
+const char* lb_last_error(const lb_ctx* x) {
+    if (x) return x->err.c_str();
+    return g_err.c_str();
+}
+
+}  // extern "C"

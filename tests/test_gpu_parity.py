@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same
+seeded inputs.  Bars: FP32 fields within 1e-5 of the FP64 oracle, measured as
+max|gpu - oracle| / max|oracle| over the whole field; FP64 fields bit-identical
+(no contraction and the same operation order on both sides, no transcendental
+on the device); work loads and chunk maps bit-identical; every launch form,
+slot count, workgroup count, tile shape and map bit-identical to each other."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_4218_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1310_4218_amd.grid import Grid  # noqa: F401  (fails loudly without the library)
+    yield
+
+
+def Grid(*a, **k):
+    from paper_1310_4218_amd.grid import Grid as G
+    return G(*a, **k)
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def rel_err(a, ref):
+    a = np.asarray(a, dtype=np.float64)
+    return float(np.max(np.abs(a - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def gpu_fields(g):
+    return np.stack([g.field(f).numpy().astype(np.float64) for f in range(g.wl.nfields)])
+
+
+def mk(nx, ny, nz, px, py, *, hot=((5, 4, 0, 0),), sigma=4.0, kmin=1, kmax=30, steps=3,
+       split="equal", seed=11, nslots=4, **kw):
+    xs, ys = W.make_splits(nx, ny, px, py, split, 3.0, seed + 1000)
+    return W.Workload(name="t", nx=nx, ny=ny, nz=nz, px=px, py=py, xsplit=xs, ysplit=ys,
+                      hot=list(hot), sigma=sigma, kmin=kmin, kmax=kmax, steps=steps, seed=seed,
+                      nslots=nslots, **kw)
+
+
+def run_gpu(wl, steps, mode="persistent", **over):
+    g = Grid(wl, **over)
+    g.step(steps, mode)
+    q = gpu_fields(g)
+    w = g.measure("work")
+    return g, q, w
+
+
+# ------------------------------------------------------------------ small workload
+@pytest.mark.parametrize("mode", ["persistent", "plain"])
+def test_small_fp32_matches_oracle(mode):
+    wl = W.small()
+    say("small fp32", mode)
+    g, q, w = run_gpu(wl, wl.steps, mode)
+    ref, work, ck, _ = oracle.run(wl)
+    err = rel_err(q, ref)
+    say("  rel err", err)
+    assert err <= TOL
+    np.testing.assert_array_equal(w, work.sum(axis=0))
+    cks = g.checksums(wl.steps)
+    np.testing.assert_allclose(cks, ck, rtol=0, atol=TOL * np.abs(ref).sum() / ref.size * 100)
+    assert abs(g.checksum() - float(q.sum())) <= 1e-9 * np.abs(q).sum()
+    g.close()
+
+
+def test_small_fp64_bit_exact():
+    wl = W.small()
+    g, q, w = run_gpu(wl, wl.steps, precision="fp64")
+    ref, work, ck, _ = oracle.run(wl)
+    np.testing.assert_array_equal(q, ref)
+    np.testing.assert_array_equal(w, work.sum(axis=0))
+    g.close()
+
+
+def test_kahan_within_tolerance_and_not_worse():
+    wl = W.small().replace(kmax=200, sigma=12.0)
+    ref, _, _, _ = oracle.run(wl)
+    _, q32, _ = run_gpu(wl, wl.steps)
+    _, qk, _ = run_gpu(wl, wl.steps, precision="fp32_kahan")
+    e32, ek = rel_err(q32, ref), rel_err(qk, ref)
+    say("fp32", e32, "kahan", ek)
+    assert ek <= TOL
+    assert np.sqrt(np.mean((qk - ref) ** 2)) <= np.sqrt(np.mean((q32 - ref) ** 2)) * 1.05
+
+
+# ------------------------------------------------------------------ schedule invariance
+def test_launch_forms_bit_identical():
+    wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=4, nslots=5)
+    base = None
+    for mode in ("plain", "persistent", "plain_graph", "persistent_eager"):
+        say("mode", mode)
+        g, q, w = run_gpu(wl, 4, mode, graph_steps=3)
+        if base is None:
+            base = (q, w)
+        else:
+            np.testing.assert_array_equal(q, base[0])
+            np.testing.assert_array_equal(w, base[1])
+        g.close()
+    ref, work, _, _ = oracle.run(wl, nsteps=4)
+    assert rel_err(base[0], ref) <= TOL
+    np.testing.assert_array_equal(base[1], work.sum(axis=0))
+
+
+@pytest.mark.parametrize("over", [
+    dict(nslots=1, wg_per_slot=8), dict(nslots=3, wg_per_slot=2, steal=0),
+    dict(nslots=16, wg_per_slot=1, steal=1), dict(nslots=8, wg_per_slot=4, steal=0),
+    dict(tile_x=4, tile_y=3), dict(tile_x=7, tile_y=5, nslots=2), dict(tile_x=16, tile_y=1),
+])
+def test_schedule_invariance(over):
+    wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=3)
+    _, base, wb = run_gpu(wl, 3, "plain")
+    say("over", over)
+    g, q, w = run_gpu(wl, 3, "persistent", **over)
+    np.testing.assert_array_equal(q, base)
+    np.testing.assert_array_equal(w, wb)
+    v = g.visits()
+    assert np.all(v == 3)
+
+
+def test_map_does_not_change_fields():
+    wl = mk(48, 40, 8, 6, 5, split="dirichlet", steps=4, nslots=7)
+    _, base, _ = run_gpu(wl, 4, "plain")
+    rng = np.random.default_rng(0)
+    g = Grid(wl)
+    for _ in range(4):
+        g.set_map(rng.integers(0, 7, size=wl.nchunks), rng.uniform(0, 10, size=wl.nchunks))
+        g.step(1)
+    np.testing.assert_array_equal(gpu_fields(g), base)
+    assert np.all(g.visits() == 4)
+
+
+# ------------------------------------------------------------------ ragged shapes, FP64 exact
+@pytest.mark.parametrize("shape", [
+    (37, 29, 5, 5, 4), (37, 29, 6, 3, 7), (33, 17, 12, 33, 1), (16, 16, 1, 2, 2),
+    (1, 9, 4, 1, 3), (9, 1, 8, 2, 1), (50, 45, 80, 6, 5), (20, 24, 3, 1, 1),
+])
+def test_ragged_fp64_bit_exact(shape):
+    nx, ny, nz, px, py = shape
+    say("ragged", shape)
+    wl = mk(nx, ny, nz, px, py, hot=((nx // 3, ny // 2, 1, -1), (0, 0, 0, 0)), sigma=3.0,
+            kmax=25, split="dirichlet" if px > 1 else "equal", steps=3, nslots=3)
+    for tiles in (dict(), dict(tile_x=3, tile_y=2)):
+        g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **tiles)
+        ref, work, _, _ = oracle.run(wl, nsteps=3)
+        np.testing.assert_array_equal(q, ref)
+        np.testing.assert_array_equal(w, work.sum(axis=0))
+        g.close()
+
+
+def test_multi_field_fp64_bit_exact():
+    wl = mk(24, 20, 8, 3, 2, steps=3).replace(nfields=3)
+    g, q, w = run_gpu(wl, 3, "persistent", precision="fp64")
+    ref, work, _, _ = oracle.run(wl, nsteps=3)
+    np.testing.assert_array_equal(q, ref)
+    np.testing.assert_array_equal(w, work.sum(axis=0))
+
+
+# ------------------------------------------------------------------ invariants
+def test_zero_column_cost_is_pure_stencil():
+    wl = mk(32, 24, 16, 4, 2, kmin=0, kmax=0, steps=1)
+    q0 = oracle.init_field(32, 24, 16, seed=3)
+    g = Grid(wl, init_field=q0.astype(np.float32), precision="fp32")
+    g.step(1)
+    s = oracle.stencil(q0[0].astype(np.float32).astype(np.float64))
+    assert rel_err(g.field().numpy(), s) <= 1e-6
+    g64 = Grid(wl, init_field=q0, precision="fp64")
+    g64.step(1)
+    np.testing.assert_array_equal(g64.field().numpy(), oracle.stencil(q0[0]))
+
+
+@pytest.mark.parametrize("c", [-1.0, 0.0, 1.0])
+def test_fixed_points_stay_fixed(c):
+    wl = mk(32, 24, 16, 4, 2, kmax=60, steps=5)
+    g = Grid(wl, init_field=np.full((1, 24, 32, 16), c, np.float32))
+    g.step(5)
+    assert np.all(g.field().numpy() == c)
+
+
+def test_odd_symmetry_bit_exact():
+    wl = mk(32, 24, 16, 4, 2, kmax=60, steps=4)
+    q0 = oracle.init_field(32, 24, 16, seed=5).astype(np.float32)
+    a = Grid(wl, init_field=q0)
+    b = Grid(wl, init_field=-q0)
+    a.step(4)
+    b.step(4)
+    np.testing.assert_array_equal(a.field().numpy(), -b.field().numpy())
+
+
+def test_resume_from_exported_field_bit_exact():
+    wl = mk(40, 36, 12, 4, 3, hot=((7, 9, 2, 1),), steps=8)
+    full = Grid(wl)
+    full.step(8)
+    a = Grid(wl)
+    a.step(4)
+    mid = a.field().numpy()
+    b = Grid(wl.replace(t0=4), init_field=mid)
+    b.step(4)
+    np.testing.assert_array_equal(b.field().numpy(), full.field().numpy())
+
+
+# ------------------------------------------------------------------ measurement and balancing
+def test_measure_rebalance_map_parity():
+    """Loads measured on the GPU equal the oracle's; the maps the library installs equal
+    the oracle's balancers applied to the oracle's loads (no loads fed across)."""
+    wl = W.shrink(W.moving(), 64, 64, nz=16, steps=30, px=8, py=8).replace(nslots=16)
+    ref_q, work, _, _ = oracle.run(wl)
+    g = Grid(wl)
+    old = oracle.block_map(wl.nchunks, 16)
+    for window, strategy in ((0, "greedy"), (1, "refine"), (2, None)):
+        g.step(10)
+        w = g.measure("work")
+        wref = work[10 * window:10 * (window + 1)].sum(axis=0)
+        np.testing.assert_array_equal(w, wref)
+        if strategy is None:
+            break
+        m, nm, (lb, la) = g.rebalance(strategy, 1.05)
+        mref = oracle.greedy(wref, 16) if strategy == "greedy" else oracle.refine(wref, old, 16, 1.05)
+        np.testing.assert_array_equal(m, mref)
+        assert nm == int((mref != old).sum())
+        assert lb == pytest.approx(oracle.imbalance(wref, old, 16), rel=1e-12)
+        assert la == pytest.approx(oracle.imbalance(wref, mref, 16), rel=1e-12)
+        say(strategy, "lambda", lb, "->", la, "migrated", nm)
+        old = mref
+    assert rel_err(gpu_fields(g), ref_q) <= TOL
+
+
+def test_time_loads_and_busy_counters():
+    wl = W.small()
+    g = Grid(wl, nslots=4, wg_per_slot=8)
+    g.step(5)
+    t = g.measure("time", reset=False)
+    w = g.measure("work", reset=False)
+    busy = g.wg_busy()
+    assert np.all(t > 0) and np.all(w > 0)
+    assert busy.sum() == pytest.approx(t.sum(), rel=1e-9)  # same ticks, two groupings
+    st = g.stats()
+    assert st["clock_hz"] > 1e6 and st["measured_steps"] == 5
+    g.measure("work", reset=True)
+    assert g.stats()["measured_steps"] == 0
+    assert np.all(g.measure("work") == 0)
+
+
+def test_rebalance_needs_measurement():
+    from paper_1310_4218_amd._abi import LbError, LB_E_STATE
+    g = Grid(W.small())
+    with pytest.raises(LbError) as e:
+        g.rebalance("greedy")
+    assert e.value.code == LB_E_STATE
+
+
+# ------------------------------------------------------------------ full-size moving-hotspot run
+def test_moving_full_size_fields_loads_maps():
+    """256x256x64, 8x8 chunks, hotspot moving +1 cell/step, GreedyLB onto 256 slots after
+    10 steps, 20 steps, in the launch configuration the benchmark uses."""
+    wl = W.moving()
+    T = 20
+    ref, work, ck, _ = oracle.run(wl, nsteps=T)
+    g = Grid(wl)
+    g.step(10)
+    w1 = g.measure("work")
+    np.testing.assert_array_equal(w1, work[:10].sum(axis=0))
+    m, _, _ = g.rebalance("greedy")
+    np.testing.assert_array_equal(m, oracle.greedy(work[:10].sum(axis=0), 256))
+    g.step(10)
+    np.testing.assert_array_equal(g.measure("work"), work[10:].sum(axis=0))
+    err = rel_err(gpu_fields(g), ref)
+    say("moving full size rel err", err)
+    assert err <= TOL
+    assert np.all(g.visits() == T)
