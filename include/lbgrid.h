@@ -104,6 +104,9 @@ typedef struct {
     int32_t steal;           /* 1: a workgroup whose slot queue is empty takes
                                 items from other slots (default 1)            */
     int32_t graph_steps;     /* persistent steps per captured graph (10)      */
+    int32_t item_split;      /* after a rebalance, tiles whose measured cost
+                                exceeds W/(S*G*item_split) are cut into row
+                                ranges; 0 = never (2)                          */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;
@@ -119,7 +122,9 @@ typedef struct {
 typedef struct {
     int64_t steps;           /* steps enqueued since init                     */
     int32_t nchunks;         /* C                                             */
-    int32_t ntiles;          /* work items (tiles of chunks)                  */
+    int32_t ntiles;          /* tiles of chunks                               */
+    int32_t nrows;           /* tile rows (the finest possible items)         */
+    int32_t nitems;          /* work items of the installed plan              */
     int32_t nslots;          /* S                                             */
     int32_t nwg;             /* workgroups of the persistent launch (S*G)     */
     int32_t block;           /* threads per workgroup                         */
@@ -193,8 +198,9 @@ int lb_stats(lb_ctx *ctx, lb_stats_t *out);
  * imbalance of the persistent kernel. */
 int lb_wg_busy(lb_ctx *ctx, double *out, int32_t n);
 
-/* Synchronize and copy per-tile claim counts since the last reset (n >= ntiles
- * int32); every tile is processed exactly once per step.  reset != 0 zeroes them. */
+/* Synchronize and copy per-tile-row visit counts since the last reset (n >= nrows
+ * int32, tiles in chunk order, rows top to bottom); every row is computed
+ * exactly once per step.  reset != 0 zeroes them. */
 int lb_visits(lb_ctx *ctx, int32_t *out, int32_t n, int32_t reset);
 
 /* Synchronize and copy the per-step FP64 sums of all cells of the last

@@ -2,20 +2,21 @@
 // the over-decomposed grid (3D Jacobi update + column physics, Section IV and
 // Section VI Fig. 4 of the paper) with in-kernel per-chunk load measurement
 // (Section V), in two launch forms:
-//   - plain: one launch per chunk over that chunk's tiles, chunks in id order;
-//   - persistent: one launch per step whose workgroups claim tiles from
+//   - plain: one launch per chunk over that chunk's items, chunks in id order;
+//   - persistent: one launch per step whose workgroups claim items from
 //     per-slot queues (slots play the paper's processors) with atomic heads,
 //     optionally taking work from other slots once their own queue is empty.
 //
-// Data layout: field[((f*ny + y)*nx + x)*nz + z] (z fastest).  A work item is a
-// tile of up to TX x TY columns inside one chunk.  A workgroup has TX*nz/V
-// threads; thread t owns V consecutive levels of column t / (nz/V) of the
-// current tile row.  The tile is swept row by row (along y) through a ring of
-// four LDS rows, each holding TX+2 columns (one halo column on either side) of
-// all nz levels: rows y-1, y, y+1 are read by the stencil while row y+2 is
-// being fetched from HBM into registers.  Every cell is read from HBM once per
-// tile and written once; halo columns and halo rows are re-read by the
-// neighbouring tiles (mostly from L2 / MALL).
+// Data layout: field[((f*ny + y)*nx + x)*nz + z] (z fastest).  Chunks are cut
+// into tiles of up to TX x TY columns; a work item is a range of rows of one
+// tile (the whole tile unless the host split a costly tile into row ranges).
+// A workgroup has TX*nz/V threads; thread t owns V consecutive levels of
+// column t / (nz/V) of the current row.  The item is swept row by row (along
+// y) through a ring of four LDS rows, each holding TX+2 columns (one halo
+// column on either side) of all nz levels: rows y-1, y, y+1 are read by the
+// stencil while row y+2 is being fetched from HBM into registers.  Every cell
+// is read from HBM once per item and written once; halo columns and halo rows
+// are re-read by the neighbouring items (mostly from L2 / MALL).
 //
 // Arithmetic per cell, with s the stencil value and k the column's trip count:
 //   FP32:        q <- fma(eps, fma(-(q*q), q, q), q), k times
@@ -150,15 +151,15 @@ __device__ double block_sum(double v, double* red) {
     return s;
 }
 
-// ---- one tile -------------------------------------------------------------------
-struct TileOut {
-    double checksum;  // sum of the tile's outputs over all fields (valid in thread 0)
-    double work;      // work units of the tile (valid in thread 0)
+// ---- one work item ----------------------------------------------------------------
+struct ItemOut {
+    double checksum;  // sum of the item's outputs over all fields (valid in thread 0)
+    double work;      // work units of the item (valid in thread 0)
     int chunk;
 };
 
 template <typename T, int V, int KAHAN>
-__device__ TileOut process_tile(const DevArgs& a, int tile, const T* __restrict__ src,
+__device__ ItemOut process_item(const DevArgs& a, int item, const T* __restrict__ src,
                                 T* __restrict__ dst, const int* hcx, const int* hcy, T* lds,
                                 double* red) {
     const int nz = a.nz, nx = a.nx, ny = a.ny;
@@ -168,12 +169,13 @@ __device__ TileOut process_tile(const DevArgs& a, int tile, const T* __restrict_
     const int tzq = threadIdx.x - tcol * NQ;
     const int zoff = tzq * V;
 
+    const int tile = a.items[2 * item];
+    const int rows = a.items[2 * item + 1];
     const int x0 = a.tiles[4 * tile + 0];
-    const int y0 = a.tiles[4 * tile + 1];
-    const int wh = a.tiles[4 * tile + 2];
+    const int y0 = a.tiles[4 * tile + 1] + (rows & 0xffff);  // first row of the item
+    const int w = a.tiles[4 * tile + 2] & 0xffff;
     const int chunk = a.tiles[4 * tile + 3];
-    const int w = wh & 0xffff;
-    const int h = wh >> 16;
+    const int h = (rows >> 16) - (rows & 0xffff);              // rows in the item
 
     const int RL = (TX + 2) * nz;             // LDS row stride (elements)
     const bool has0 = tcol < w + 2;           // this thread fetches halo column tcol
@@ -254,7 +256,7 @@ __device__ TileOut process_tile(const DevArgs& a, int tile, const T* __restrict_
             __syncthreads();
         }
     }
-    TileOut o;
+    ItemOut o;
     o.checksum = block_sum(chk, red);
     o.work = block_sum(work, red);
     o.chunk = chunk;
@@ -279,19 +281,26 @@ __device__ __forceinline__ StepInfo step_info(const DevArgs& a) {
     return s;
 }
 
-__device__ __forceinline__ void record_tile(const DevArgs& a, int tile, const TileOut& o,
+// Called by thread 0 after an item: its checksum partial, the chunk's loads, and
+// one visit for each tile row the item covered (plain increments: exactly one
+// workgroup owns a row in a step, so a second claim would show as a miscount).
+__device__ __forceinline__ void record_item(const DevArgs& a, int item, const ItemOut& o,
                                             double ticks) {
-    a.partials[tile] = o.checksum;
+    a.partials[item] = o.checksum;
     unsafeAtomicAdd(&a.loads_work[o.chunk], o.work);
     unsafeAtomicAdd(&a.loads_time[o.chunk], ticks);
-    atomicAdd(&a.visits[tile], 1);
+    const int tile = a.items[2 * item];
+    const int rows = a.items[2 * item + 1];
+    int32_t* v = a.visits + a.row_base[tile];
+    for (int r = rows & 0xffff; r < (rows >> 16); ++r) v[r] += 1;
 }
 
-// Deterministic sum of the per-tile partials into the checksum ring, then the
-// step counter moves on.  Run by one whole workgroup.
+// Deterministic sum of the per-item partials (item order) into the checksum ring,
+// then the step counter moves on.  Run by one whole workgroup.
 __device__ void finish_step(const DevArgs& a, uint64_t step, double* red) {
+    const int n = static_cast<int>(a.ctrl->nitems);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) acc += a.partials[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += a.partials[i];
     const double total = block_sum(acc, red);
     if (threadIdx.x == 0) {
         a.hist[step % kHistLen] = total;
@@ -373,14 +382,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
             if (threadIdx.x == 0) s_item = item;
         }
         __syncthreads();
-        const int tile = s_item;
-        if (tile < 0) break;
+        const int item = s_item;
+        if (item < 0) break;
         const uint64_t t_start = wall_clock64();
-        const TileOut o = process_tile<T, V, KAHAN>(a, tile, src, dst, si.hcx, si.hcy, lds, red);
+        const ItemOut o = process_item<T, V, KAHAN>(a, item, src, dst, si.hcx, si.hcy, lds, red);
         if (threadIdx.x == 0) {
             const double ticks = static_cast<double>(wall_clock64() - t_start);
             busy += ticks;
-            record_tile(a, tile, o, ticks);
+            record_item(a, item, o, ticks);
         }
     }
     if (threadIdx.x == 0) {
@@ -406,10 +415,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
     const StepInfo si = step_info(a);
     const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);
     T* dst = static_cast<T*>((si.step & 1) ? a.field0 : a.field1);
-    const int tile = a.tile_off[chunk] + blockIdx.x;
+    const int item = a.item_off[chunk] + blockIdx.x;
+    if (item >= a.item_off[chunk + 1]) return;  // grid sized for the largest plan
     const uint64_t t_start = wall_clock64();
-    const TileOut o = process_tile<T, V, KAHAN>(a, tile, src, dst, si.hcx, si.hcy, lds, red);
-    if (threadIdx.x == 0) record_tile(a, tile, o, static_cast<double>(wall_clock64() - t_start));
+    const ItemOut o = process_item<T, V, KAHAN>(a, item, src, dst, si.hcx, si.hcy, lds, red);
+    if (threadIdx.x == 0) record_item(a, item, o, static_cast<double>(wall_clock64() - t_start));
 }
 
 __global__ __launch_bounds__(256) void k_finish(DevArgs a) {
@@ -508,9 +518,9 @@ int launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, s
     return static_cast<int>(hipGetLastError());
 }
 
-int launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int ntiles_chunk,
+int launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitems_chunk,
                        int block, size_t lds, void* stream) {
-    hipLaunchKernelGGL(pick_plain(prec, vec), dim3(ntiles_chunk), dim3(block), lds,
+    hipLaunchKernelGGL(pick_plain(prec, vec), dim3(nitems_chunk), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a, chunk);
     return static_cast<int>(hipGetLastError());
 }

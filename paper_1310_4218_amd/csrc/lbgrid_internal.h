@@ -18,7 +18,7 @@ constexpr size_t kMaxLds = 64 * 1024;
 // Device control block (first bytes of the workspace).
 struct Ctrl {
     uint32_t done;          // workgroups finished in the current persistent launch
-    uint32_t pad0;
+    uint32_t nitems;        // work items of the installed plan
     uint64_t step;          // steps completed since init
     uint64_t pad1[6];
 };
@@ -29,17 +29,19 @@ struct DevArgs {
     void* field1;
     const int32_t* ktab;
     const int32_t* tiles;      // 4 ints per tile: x0, y0, w | h << 16, chunk
-    const int32_t* tile_off;   // C + 1
-    const int32_t* worklist;   // ntiles tile ids, grouped by slot
+    const int32_t* row_base;   // per tile: index of its first row in visits
+    const int32_t* items;      // 2 ints per item: tile, first row | end row << 16
+    const int32_t* item_off;   // C + 1: items of chunk c are [item_off[c], item_off[c+1])
+    const int32_t* worklist;   // item ids, grouped by slot
     const int32_t* seg;        // S + 1 offsets into worklist
     int32_t* heads;            // S claim counters
     Ctrl* ctrl;
     double* loads_work;        // C
     double* loads_time;        // C
-    double* partials;          // ntiles: sum of the tile's outputs in the last step
+    double* partials;          // per item: sum of the item's outputs in the last step
     double* hist;              // kHistLen per-step sums
     double* wg_busy;           // nwg
-    int32_t* visits;           // ntiles
+    int32_t* visits;           // per tile row: times it was computed
     int64_t ncells;            // cells per field
     int32_t nx, ny, nz, nfields;
     int32_t ntiles, nslots, nwg, steal;
@@ -57,7 +59,7 @@ struct DevArgs {
 // Kernel launchers (kernels.hip).  prec: 0 FP32, 1 FP32 Kahan, 2 FP64.
 int  launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, size_t lds,
                        void* stream);
-int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int ntiles_chunk,
+int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitems_chunk,
                         int block, size_t lds, void* stream);
 int  launch_finish(const DevArgs& a, void* stream);
 int  launch_init_field(void* q, int prec, int64_t n, uint64_t seed, void* stream);

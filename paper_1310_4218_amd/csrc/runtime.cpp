@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -40,14 +41,15 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Plan {
     int32_t nx = 0, ny = 0, nz = 0, nfields = 1, px = 0, py = 0, C = 0, S = 0, G = 0, nwg = 0;
     int32_t prec = 0, vec = 1, elem = 4, TX = 16, TY = 16, block = 0, ntiles = 0;
+    int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
     int32_t r2cut = 0;
     size_t lds = 0;
     int64_t ncells = 0;
     std::vector<int32_t> xs, ys;
     // workspace layout (byte offsets)
-    size_t off_ctrl = 0, off_ktab = 0, off_tiles = 0, off_tileoff = 0, off_work = 0, off_seg = 0,
-           off_heads = 0, off_lw = 0, off_lt = 0, off_part = 0, off_hist = 0, off_busy = 0,
-           off_visits = 0, off_sum = 0, ws_bytes = 0;
+    size_t off_ctrl = 0, off_ktab = 0, off_tiles = 0, off_rowbase = 0, off_items = 0,
+           off_itemoff = 0, off_work = 0, off_seg = 0, off_heads = 0, off_lw = 0, off_lt = 0,
+           off_part = 0, off_hist = 0, off_busy = 0, off_visits = 0, off_sum = 0, ws_bytes = 0;
     size_t field_bytes = 0;
 };
 
@@ -84,6 +86,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->tile_x < 0 || c->tile_y < 0) return bad("tile sizes must be >= 0");
     if (c->graph_steps < 1 || c->graph_steps > 1000) return bad("graph_steps must be in [1, 1000]");
     if (c->steal != 0 && c->steal != 1) return bad("steal must be 0 or 1");
+    if (c->item_split < 0 || c->item_split > 64) return bad("item_split must be in [0, 64]");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
     p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
@@ -116,15 +119,19 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.lds = (p.TX + 2) * row_elems_per_col;
     if (p.lds > kMaxLds) return bad("tile_x too large: the LDS row ring exceeds 64 KiB");
 
-    // tiles of every chunk, chunks in id order, tiles in raster order
-    int64_t nt = 0;
+    // tiles of every chunk, chunks in id order, tiles in raster order; every tile
+    // row can become an item of its own
+    int64_t nt = 0, nr = 0;
     for (int j = 0; j < p.py; ++j)
         for (int i = 0; i < p.px; ++i) {
             const int64_t w = p.xs[i + 1] - p.xs[i], h = p.ys[j + 1] - p.ys[j];
-            nt += ((w + p.TX - 1) / p.TX) * ((h + p.TY - 1) / p.TY);
+            const int64_t tx = (w + p.TX - 1) / p.TX;
+            nt += tx * ((h + p.TY - 1) / p.TY);
+            nr += tx * h;
         }
-    if (nt > (int64_t{1} << 30)) return bad("too many tiles");
+    if (nr > (int64_t{1} << 28)) return bad("too many tiles");
     p.ntiles = static_cast<int32_t>(nt);
+    p.nrows = static_cast<int32_t>(nr);
 
     p.G = c->wg_per_slot > 0 ? c->wg_per_slot : std::max(1, 2048 / p.S);
     const int64_t nwg = static_cast<int64_t>(p.S) * p.G;
@@ -140,16 +147,18 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_ctrl = take(sizeof(Ctrl));
     p.off_ktab = take(sizeof(int32_t) * (static_cast<size_t>(p.r2cut) + 1));
     p.off_tiles = take(sizeof(int32_t) * 4 * static_cast<size_t>(p.ntiles));
-    p.off_tileoff = take(sizeof(int32_t) * (static_cast<size_t>(p.C) + 1));
-    p.off_work = take(sizeof(int32_t) * static_cast<size_t>(p.ntiles));
+    p.off_rowbase = take(sizeof(int32_t) * static_cast<size_t>(p.ntiles));
+    p.off_items = take(sizeof(int32_t) * 2 * static_cast<size_t>(p.nrows));
+    p.off_itemoff = take(sizeof(int32_t) * (static_cast<size_t>(p.C) + 1));
+    p.off_work = take(sizeof(int32_t) * static_cast<size_t>(p.nrows));
     p.off_seg = take(sizeof(int32_t) * (static_cast<size_t>(p.S) + 1));
     p.off_heads = take(sizeof(int32_t) * static_cast<size_t>(p.S));
     p.off_lw = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_lt = take(sizeof(double) * static_cast<size_t>(p.C));
-    p.off_part = take(sizeof(double) * static_cast<size_t>(p.ntiles));
+    p.off_part = take(sizeof(double) * static_cast<size_t>(p.nrows));
     p.off_hist = take(sizeof(double) * kHistLen);
     p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg));
-    p.off_visits = take(sizeof(int32_t) * static_cast<size_t>(p.ntiles));
+    p.off_visits = take(sizeof(int32_t) * static_cast<size_t>(p.nrows));
     p.off_sum = take(sizeof(double) * (kSumBlocks + 1));
     p.ws_bytes = o;
     p.field_bytes = static_cast<size_t>(p.ncells) * p.nfields * p.elem;
@@ -168,14 +177,19 @@ struct lb_ctx {
     char* ws = nullptr;
     DevArgs args{};
     std::vector<int32_t> tiles;       // 4 per tile
-    std::vector<int32_t> tile_off;    // C + 1
+    std::vector<int32_t> tile_off;    // C + 1: tiles of chunk c
+    std::vector<int32_t> row_base;    // per tile: its first row in the visit counters
+    std::vector<int32_t> items;       // 2 per item of the installed plan
+    std::vector<int32_t> item_off;    // C + 1
+    int64_t plan_version = 0;
+    int64_t plain_graph_version = -1;
     std::vector<int32_t> map;         // C
     std::vector<double> measured;     // loads kept by the last lb_measure
     bool have_measured = false;
     int64_t steps = 0;
     int64_t window_steps = 0;
     double clock_hz = 100e6;
-    int32_t* staging = nullptr;       // pinned: worklist + seg for uploads
+    int32_t* staging = nullptr;       // pinned: items, item_off, worklist, seg, nitems
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
@@ -228,6 +242,12 @@ void build_tiles(lb_ctx* x) {
                 }
         }
     x->tile_off[p.C] = t;
+    x->row_base.resize(static_cast<size_t>(p.ntiles));
+    int32_t r = 0;
+    for (int32_t i = 0; i < p.ntiles; ++i) {
+        x->row_base[i] = r;
+        r += x->tiles[4 * i + 2] >> 16;
+    }
 }
 
 std::vector<int32_t> build_cost_table(const lb_config& c, int32_t r2cut) {
@@ -241,39 +261,83 @@ std::vector<int32_t> build_cost_table(const lb_config& c, int32_t r2cut) {
     return tab;
 }
 
-// Per-slot queues: the tiles of each slot's chunks, chunks in descending
-// per-tile cost (cost_c / ntiles_c), ties by chunk id, tiles in raster order.
-int upload_queues(lb_ctx* x, const double* cost) {
+// Work plan for a map and per-chunk costs (NULL: equal costs, no splitting).
+//  - Items: a tile whose estimated cost exceeds W / (nwg * item_split) is cut into
+//    that many row ranges (at most one per row), so that no single item outlasts
+//    the rest of the step; cheap tiles stay whole, which keeps their halo
+//    overhead low.  Tile cost = chunk cost * tile area / chunk area.
+//  - Queues: each slot gets the items of its chunks in descending item cost,
+//    ties in item order (chunk id, tile raster, first row).
+int upload_plan(lb_ctx* x, const double* cost) {
     const Plan& p = x->plan;
-    std::vector<std::vector<int32_t>> by_slot(static_cast<size_t>(p.S));
-    for (int32_t c = 0; c < p.C; ++c) by_slot[x->map[c]].push_back(c);
-    std::vector<double> per_tile(static_cast<size_t>(p.C), 0.0);
+    double W = 0.0;
+    if (cost)
+        for (int32_t c = 0; c < p.C; ++c) W += cost[c];
+    const int split = x->cfg.item_split;
+    const double target = (cost && split > 0 && W > 0.0) ? W / (static_cast<double>(p.nwg) * split) : 0.0;
+
+    x->items.clear();
+    x->item_off.assign(static_cast<size_t>(p.C) + 1, 0);
+    std::vector<double> item_cost;
     for (int32_t c = 0; c < p.C; ++c) {
-        const int32_t nt = x->tile_off[c + 1] - x->tile_off[c];
-        per_tile[c] = cost ? cost[c] / static_cast<double>(nt) : 0.0;
+        x->item_off[c] = static_cast<int32_t>(item_cost.size());
+        const int i = c % p.px, j = c / p.px;
+        const double area_c = static_cast<double>(p.xs[i + 1] - p.xs[i]) * (p.ys[j + 1] - p.ys[j]);
+        for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) {
+            const int w = x->tiles[4 * t + 2] & 0xffff, h = x->tiles[4 * t + 2] >> 16;
+            const double tc = cost ? cost[c] * (static_cast<double>(w) * h / area_c) : 0.0;
+            int pieces = 1;
+            if (target > 0.0 && tc > target)
+                pieces = static_cast<int>(std::min<double>(h, std::ceil(tc / target)));
+            for (int k = 0; k < pieces; ++k) {
+                const int r0 = (k * h) / pieces, r1 = ((k + 1) * h) / pieces;
+                x->items.push_back(t);
+                x->items.push_back(r0 | (r1 << 16));
+                item_cost.push_back(tc * (r1 - r0) / h);
+            }
+        }
     }
+    const int32_t n = static_cast<int32_t>(item_cost.size());
+    x->item_off[p.C] = n;
+
+    std::vector<std::vector<int32_t>> by_slot(static_cast<size_t>(p.S));
+    for (int32_t c = 0; c < p.C; ++c)
+        for (int32_t it = x->item_off[c]; it < x->item_off[c + 1]; ++it) by_slot[x->map[c]].push_back(it);
+
     if (x->upload_pending) {
         HIP_TRY(x, hipEventSynchronize(x->upload_done));
         x->upload_pending = false;
     }
-    int32_t* work = x->staging;
-    int32_t* seg = x->staging + p.ntiles;
-    int32_t n = 0;
+    int32_t* st_items = x->staging;
+    int32_t* st_off = st_items + 2 * static_cast<size_t>(p.nrows);
+    int32_t* st_work = st_off + p.C + 1;
+    int32_t* st_seg = st_work + p.nrows;
+    int32_t* st_n = st_seg + p.S + 1;
+    std::memcpy(st_items, x->items.data(), sizeof(int32_t) * x->items.size());
+    std::memcpy(st_off, x->item_off.data(), sizeof(int32_t) * x->item_off.size());
+    int32_t k = 0;
     for (int32_t s = 0; s < p.S; ++s) {
-        seg[s] = n;
+        st_seg[s] = k;
         auto& v = by_slot[s];
         std::stable_sort(v.begin(), v.end(),
-                         [&](int32_t a, int32_t b) { return per_tile[a] > per_tile[b]; });
-        for (int32_t c : v)
-            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) work[n++] = t;
+                         [&](int32_t a, int32_t b) { return item_cost[a] > item_cost[b]; });
+        for (int32_t it : v) st_work[k++] = it;
     }
-    seg[p.S] = n;
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_work, work, sizeof(int32_t) * p.ntiles,
+    st_seg[p.S] = k;
+    *st_n = n;
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_items, st_items, sizeof(int32_t) * 2 * n,
                               hipMemcpyHostToDevice, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_seg, seg, sizeof(int32_t) * (p.S + 1),
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_itemoff, st_off, sizeof(int32_t) * (p.C + 1),
+                              hipMemcpyHostToDevice, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_work, st_work, sizeof(int32_t) * n,
+                              hipMemcpyHostToDevice, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_seg, st_seg, sizeof(int32_t) * (p.S + 1),
+                              hipMemcpyHostToDevice, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_ctrl + offsetof(Ctrl, nitems), st_n, sizeof(int32_t),
                               hipMemcpyHostToDevice, x->stream));
     HIP_TRY(x, hipEventRecord(x->upload_done, x->stream));
     x->upload_pending = true;
+    ++x->plan_version;
     return LB_OK;
 }
 
@@ -287,7 +351,7 @@ int capture(lb_ctx* x, int mode, int nsteps, hipGraphExec_t* out) {
             rc = launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, x->cap);
         } else {
             for (int32_t c = 0; c < p.C && rc == 0; ++c)
-                rc = launch_plain_chunk(x->args, p.prec, p.vec, c, x->tile_off[c + 1] - x->tile_off[c],
+                rc = launch_plain_chunk(x->args, p.prec, p.vec, c, x->item_off[c + 1] - x->item_off[c],
                                         p.block, p.lds, x->cap);
             if (rc == 0) rc = launch_finish(x->args, x->cap);
         }
@@ -341,6 +405,7 @@ void lb_config_default(lb_config* c) {
     c->tile_y = 0;
     c->steal = 1;
     c->graph_steps = 10;
+    c->item_split = 2;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
@@ -405,7 +470,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     if ((e = hipEventCreateWithFlags(&x->upload_done, hipEventDisableTiming)) != hipSuccess)
         return hip_bail(e, "hipEventCreateWithFlags");
     if ((e = hipHostMalloc(reinterpret_cast<void**>(&x->staging),
-                           sizeof(int32_t) * (static_cast<size_t>(P.ntiles) + P.S + 1))) != hipSuccess)
+                           sizeof(int32_t) * (3 * static_cast<size_t>(P.nrows) + P.C + P.S + 3))) != hipSuccess)
         return hip_bail(e, "hipHostMalloc");
 
     build_tiles(x);
@@ -416,7 +481,9 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.field1 = x->field[1];
     a.ktab = reinterpret_cast<const int32_t*>(x->ws + P.off_ktab);
     a.tiles = reinterpret_cast<const int32_t*>(x->ws + P.off_tiles);
-    a.tile_off = reinterpret_cast<const int32_t*>(x->ws + P.off_tileoff);
+    a.row_base = reinterpret_cast<const int32_t*>(x->ws + P.off_rowbase);
+    a.items = reinterpret_cast<const int32_t*>(x->ws + P.off_items);
+    a.item_off = reinterpret_cast<const int32_t*>(x->ws + P.off_itemoff);
     a.worklist = reinterpret_cast<const int32_t*>(x->ws + P.off_work);
     a.seg = reinterpret_cast<const int32_t*>(x->ws + P.off_seg);
     a.heads = reinterpret_cast<int32_t*>(x->ws + P.off_heads);
@@ -451,8 +518,8 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
                             hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload cost table");
     if ((e = hipMemcpyAsync(x->ws + P.off_tiles, x->tiles.data(), sizeof(int32_t) * x->tiles.size(),
                             hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload tiles");
-    if ((e = hipMemcpyAsync(x->ws + P.off_tileoff, x->tile_off.data(), sizeof(int32_t) * x->tile_off.size(),
-                            hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload tile offsets");
+    if ((e = hipMemcpyAsync(x->ws + P.off_rowbase, x->row_base.data(), sizeof(int32_t) * x->row_base.size(),
+                            hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload row bases");
     if ((r = launch_reset_control(a, x->stream)) != 0) return hip_bail(static_cast<hipError_t>(r), "reset control");
     if (init_field) {
         if ((e = hipMemcpyAsync(x->field[0], init_field, P.field_bytes, hipMemcpyDefault, x->stream)) != hipSuccess)
@@ -463,7 +530,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     }
     x->map.assign(static_cast<size_t>(P.C), 0);
     block_map(P.C, P.S, x->map.data());
-    if ((r = upload_queues(x, nullptr)) != LB_OK) {
+    if ((r = upload_plan(x, nullptr)) != LB_OK) {
         g_err = x->err;
         return bail(r);
     }
@@ -495,14 +562,21 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
                 LAUNCH_TRY(x, launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, x->stream));
             break;
         case LB_PLAIN_GRAPH:
-            if (!x->g_plain && (rc = capture(x, LB_PLAIN, 1, &x->g_plain)) != LB_OK) return rc;
+            if (x->g_plain && x->plain_graph_version != x->plan_version) {  // grid sizes changed
+                HIP_TRY(x, hipGraphExecDestroy(x->g_plain));
+                x->g_plain = nullptr;
+            }
+            if (!x->g_plain) {
+                if ((rc = capture(x, LB_PLAIN, 1, &x->g_plain)) != LB_OK) return rc;
+                x->plain_graph_version = x->plan_version;
+            }
             for (int i = 0; i < nsteps; ++i) HIP_TRY(x, hipGraphLaunch(x->g_plain, x->stream));
             break;
         default:  // LB_PLAIN
             for (int i = 0; i < nsteps; ++i) {
                 for (int32_t c = 0; c < p.C; ++c)
                     LAUNCH_TRY(x, launch_plain_chunk(x->args, p.prec, p.vec, c,
-                                                     x->tile_off[c + 1] - x->tile_off[c], p.block, p.lds,
+                                                     x->item_off[c + 1] - x->item_off[c], p.block, p.lds,
                                                      x->stream));
                 LAUNCH_TRY(x, launch_finish(x->args, x->stream));
             }
@@ -579,7 +653,7 @@ int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* lo
     const double after = imbalance(w, nm.data(), p.C, p.S);
     x->map = nm;
     HIP_TRY(x, hipSetDevice(x->device));
-    if ((rc = upload_queues(x, w)) != LB_OK) return rc;
+    if ((rc = upload_plan(x, w)) != LB_OK) return rc;
     if (map_out) std::memcpy(map_out, nm.data(), sizeof(int32_t) * p.C);
     if (nmigrated) *nmigrated = mig;
     if (lam) {
@@ -600,7 +674,7 @@ int lb_set_map(lb_ctx* x, const int32_t* map, const double* cost) {
             if (!(cost[c] >= 0.0)) return fail(&x->err, LB_E_INVAL, "costs must be >= 0");
     x->map.assign(map, map + p.C);
     HIP_TRY(x, hipSetDevice(x->device));
-    return upload_queues(x, cost);
+    return upload_plan(x, cost);
 }
 
 int lb_fields(lb_ctx* x, int32_t field, void* dst, size_t dst_bytes, double* checksum_out) {
@@ -633,6 +707,8 @@ int lb_stats(lb_ctx* x, lb_stats_t* out) {
     out->steps = x->steps;
     out->nchunks = p.C;
     out->ntiles = p.ntiles;
+    out->nrows = p.nrows;
+    out->nitems = static_cast<int32_t>(x->items.size() / 2);
     out->nslots = p.S;
     out->nwg = p.nwg;
     out->block = p.block;
@@ -659,12 +735,12 @@ int lb_wg_busy(lb_ctx* x, double* out, int32_t n) {
 int lb_visits(lb_ctx* x, int32_t* out, int32_t n, int32_t reset) {
     if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
     const Plan& p = x->plan;
-    if (out && n < p.ntiles) return fail(&x->err, LB_E_NOMEM, "out too small for ntiles entries");
+    if (out && n < p.nrows) return fail(&x->err, LB_E_NOMEM, "out too small for nrows entries");
     int rc = sync(x);
     if (rc != LB_OK) return rc;
-    if (out) HIP_TRY(x, hipMemcpy(out, x->ws + p.off_visits, sizeof(int32_t) * p.ntiles, hipMemcpyDeviceToHost));
+    if (out) HIP_TRY(x, hipMemcpy(out, x->ws + p.off_visits, sizeof(int32_t) * p.nrows, hipMemcpyDeviceToHost));
     if (reset) {
-        LAUNCH_TRY(x, launch_zero(x->ws + p.off_visits, sizeof(int32_t) * p.ntiles, x->stream));
+        LAUNCH_TRY(x, launch_zero(x->ws + p.off_visits, sizeof(int32_t) * p.nrows, x->stream));
         return sync(x);
     }
     return LB_OK;

@@ -68,6 +68,7 @@ class Grid:
         st = self.stats()
         self.nchunks, self.ntiles, self.nslots, self.nwg = (st["nchunks"], st["ntiles"],
                                                             st["nslots"], st["nwg"])
+        self.nrows = st["nrows"]
 
     # ---- lifecycle -------------------------------------------------------
     def close(self):
@@ -147,8 +148,8 @@ class Grid:
         return out
 
     def visits(self, reset: bool = False) -> np.ndarray:
-        out = np.empty(self.ntiles, dtype=np.int32)
-        check(_abi.lib().lb_visits(self.handle, ptr(out, C.c_int32), self.ntiles, int(reset)),
+        out = np.empty(self.nrows, dtype=np.int32)
+        check(_abi.lib().lb_visits(self.handle, ptr(out, C.c_int32), self.nrows, int(reset)),
               self.handle)
         return out
 
