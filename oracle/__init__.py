@@ -58,6 +58,13 @@ def _load():
             lib.orc_greedy.restype = i32
             lib.orc_refine.argtypes = [P(dbl), P(i32), i32, i32, dbl, P(i32)]
             lib.orc_refine.restype = i32
+            lib.orc_refineswap.argtypes = [P(dbl), P(i32), i32, i32, dbl, P(i32)]
+            lib.orc_refineswap.restype = i32
+            lib.orc_run_window.argtypes = [i32, i32, i32, i32, i32, i32, i32, dbl, dbl, dbl, i32,
+                                           P(i64), P(i64), P(i64), P(i64), dbl, i32, i32, i64,
+                                           i32, P(dbl)]
+            lib.orc_run_window.restype = i32
+            lib.orc_init_window.argtypes = [i32, i32, i32, i32, i32, i32, i32, i32, u64, P(dbl)]
             _lib = lib
     return _lib
 
@@ -166,6 +173,40 @@ def refine(w, old_map, S, thr) -> np.ndarray:
                           _p(m, C.c_int32)) != 0:
         raise ValueError("bad balancer arguments")
     return m
+
+
+def refineswap(w, old_map, S, thr) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    om = np.ascontiguousarray(old_map, dtype=np.int32)
+    m = np.empty(len(w), dtype=np.int32)
+    if _load().orc_refineswap(_p(w, C.c_double), _p(om, C.c_int32), len(w), S, thr,
+                              _p(m, C.c_int32)) != 0:
+        raise ValueError("bad balancer arguments")
+    return m
+
+
+def init_window(wl, ox, oy, nxw, nyw, f=0) -> np.ndarray:
+    """Seeded initial values of a window of field f: local column (x, y) is global column
+    ((ox + x) mod nx, (oy + y) mod ny)."""
+    q = np.empty((nyw, nxw, wl.nz), dtype=np.float64)
+    _load().orc_init_window(nxw, nyw, wl.nz, ox, oy, wl.nx, wl.ny, f, wl.seed, _p(q, C.c_double))
+    return q
+
+
+def run_window(wl, q0, ox, oy, nsteps, t0=None) -> np.ndarray:
+    """Advance a window (see init_window) by nsteps steps starting at time t0 (default
+    wl.t0); only columns at least nsteps away from the window border are exact."""
+    t0 = wl.t0 if t0 is None else t0
+    q = np.array(q0, dtype=np.float64, copy=True, order="C")
+    nyw, nxw, nz = q.shape
+    hx, hy, vx, vy = _hot_arrays(wl.hot)
+    rc = _load().orc_run_window(nxw, nyw, nz, ox, oy, wl.nx, wl.ny, wl.c_center, wl.c_nbr, wl.eps,
+                                len(wl.hot), _p(hx, C.c_int64), _p(hy, C.c_int64),
+                                _p(vx, C.c_int64), _p(vy, C.c_int64), wl.sigma, wl.kmin,
+                                wl.kmax, t0, nsteps, _p(q, C.c_double))
+    if rc != 0:
+        raise MemoryError("oracle window run failed")
+    return q
 
 
 def block_map(C_, S) -> np.ndarray:

@@ -78,27 +78,34 @@ static int64_t min_image(int64_t a, int64_t b, int64_t n)
     return (n - d < d) ? n - d : d;
 }
 
-/* k[y*nx + x] for absolute time index t (hotspot h sits at
- * (hx0[h] + hvx[h]*t, hy0[h] + hvy[h]*t) modulo the grid). */
+/* Trip count of global column (x, y) of an NX x NY grid at absolute time t
+ * (hotspot h sits at (hx0[h] + hvx[h]*t, hy0[h] + hvy[h]*t) modulo the grid). */
+static int32_t k_at(int64_t x, int64_t y, int32_t NX, int32_t NY, int32_t nhot,
+                    const int64_t *hx0, const int64_t *hy0, const int64_t *hvx,
+                    const int64_t *hvy, int64_t t, double sigma, int32_t kmin, int32_t kmax)
+{
+    double g = 0.0;
+    for (int32_t h = 0; h < nhot; ++h) {
+        int64_t cx = wrap64(hx0[h] + hvx[h] * t, NX);
+        int64_t cy = wrap64(hy0[h] + hvy[h] * t, NY);
+        int64_t dx = min_image(x, cx, NX);
+        int64_t dy = min_image(y, cy, NY);
+        int64_t r2 = dx * dx + dy * dy;
+        double e = exp(-(double)r2 / (2.0 * sigma * sigma));
+        if (e > g) g = e;
+    }
+    return kmin + (int32_t)floor((double)(kmax - kmin) * g);
+}
+
+/* k[y*nx + x] over the whole grid at absolute time index t. */
 void orc_kfield(int32_t nx, int32_t ny, int32_t nhot, const int64_t *hx0, const int64_t *hy0,
                 const int64_t *hvx, const int64_t *hvy, int64_t t, double sigma,
                 int32_t kmin, int32_t kmax, int32_t *k)
 {
-    for (int32_t y = 0; y < ny; ++y) {
-        for (int32_t x = 0; x < nx; ++x) {
-            double g = 0.0;
-            for (int32_t h = 0; h < nhot; ++h) {
-                int64_t cx = wrap64(hx0[h] + hvx[h] * t, nx);
-                int64_t cy = wrap64(hy0[h] + hvy[h] * t, ny);
-                int64_t dx = min_image(x, cx, nx);
-                int64_t dy = min_image(y, cy, ny);
-                int64_t r2 = dx * dx + dy * dy;
-                double e = exp(-(double)r2 / (2.0 * sigma * sigma));
-                if (e > g) g = e;
-            }
-            k[(int64_t)y * nx + x] = kmin + (int32_t)floor((double)(kmax - kmin) * g);
-        }
-    }
+    for (int32_t y = 0; y < ny; ++y)
+        for (int32_t x = 0; x < nx; ++x)
+            k[(int64_t)y * nx + x] = k_at(x, y, nx, ny, nhot, hx0, hy0, hvx, hvy, t, sigma,
+                                          kmin, kmax);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -215,6 +222,57 @@ int orc_run(int32_t nx, int32_t ny, int32_t nz, int32_t nfields, int32_t px, int
     return 0;
 }
 
+/* Same update restricted to a window of nxw x nyw columns whose local column
+ * (x, y) is global column ((ox + x) mod NX, (oy + y) mod NY) of an NX x NY grid.
+ * The window is advanced as if it were periodic, so after nsteps steps only
+ * the columns at least nsteps away from its border hold the true values (the
+ * 7-point update reaches one column further per step).  q (nyw*nxw*nz values,
+ * one field) holds the window on entry and on exit. */
+int orc_run_window(int32_t nxw, int32_t nyw, int32_t nz, int32_t ox, int32_t oy, int32_t NX,
+                   int32_t NY, double cc, double cn, double eps, int32_t nhot,
+                   const int64_t *hx0, const int64_t *hy0, const int64_t *hvx,
+                   const int64_t *hvy, double sigma, int32_t kmin, int32_t kmax, int64_t t0,
+                   int32_t nsteps, double *q)
+{
+    int64_t ncol = (int64_t)nxw * nyw;
+    double *s = (double *)malloc(sizeof(double) * (size_t)(ncol * nz));
+    int32_t *k = (int32_t *)malloc(sizeof(int32_t) * (size_t)ncol);
+    if (!s || !k) {
+        free(s);
+        free(k);
+        return -1;
+    }
+    for (int32_t step = 0; step < nsteps; ++step) {
+        for (int32_t y = 0; y < nyw; ++y)
+            for (int32_t x = 0; x < nxw; ++x)
+                k[(int64_t)y * nxw + x] = k_at(wrap64((int64_t)ox + x, NX), wrap64((int64_t)oy + y, NY),
+                                               NX, NY, nhot, hx0, hy0, hvx, hvy, t0 + step, sigma,
+                                               kmin, kmax);
+        orc_stencil(nxw, nyw, nz, cc, cn, q, s);
+        orc_physics(nxw, nyw, nz, eps, k, s);
+        memcpy(q, s, sizeof(double) * (size_t)(ncol * nz));
+    }
+    free(s);
+    free(k);
+    return 0;
+}
+
+/* Initial values of a window of field f (see orc_init_field): global cell
+ * ((f*NY + gy)*NX + gx)*nz + z with gx = (ox + x) mod NX, gy = (oy + y) mod NY. */
+void orc_init_window(int32_t nxw, int32_t nyw, int32_t nz, int32_t ox, int32_t oy, int32_t NX,
+                     int32_t NY, int32_t f, uint64_t seed, double *q)
+{
+    for (int32_t y = 0; y < nyw; ++y)
+        for (int32_t x = 0; x < nxw; ++x) {
+            int64_t gx = wrap64((int64_t)ox + x, NX), gy = wrap64((int64_t)oy + y, NY);
+            int64_t base = (((int64_t)f * NY + gy) * NX + gx) * nz;
+            for (int32_t z = 0; z < nz; ++z) {
+                uint64_t m = orc_splitmix64(seed, (uint64_t)(base + z)) >> 40;
+                q[((int64_t)y * nxw + x) * nz + z] = ((double)(int64_t)m - 8388608.0) * (1.0 / 8388608.0);
+            }
+        }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Balancers.  Loads w[C] >= 0; slots (the paper's processors) 0..S-1.       */
 
@@ -321,5 +379,120 @@ int orc_refine(const double *w, const int32_t *old_map, int32_t C, int32_t S, do
     free(L);
     free(done);
     free(ord);
+    return 0;
+}
+
+/* Chunk order light first: load ascending, then id ascending. */
+static int lighter_first(const void *a, const void *b)
+{
+    int32_t ia = *(const int32_t *)a, ib = *(const int32_t *)b;
+    if (g_sort_w[ia] < g_sort_w[ib]) return -1;
+    if (g_sort_w[ia] > g_sort_w[ib]) return 1;
+    return (ia < ib) ? -1 : (ia > ib);
+}
+
+/* RefineSwapLB with threshold thr (Section VI, Experiment B: move objects away
+ * from the most overloaded processors towards the average, and swap objects
+ * when no single move from an overloaded processor fits).  As orc_refine,
+ * except that when no chunk of p fits on the least loaded slot, the first
+ * swap that fits is made before p is given up: slots r != p in increasing
+ * (load, index) order, chunks c of p heavy first, chunks d of r light first
+ * (ties by id), with w[d] < w[c] and L[r] + (w[c] - w[d]) <= limit.  A swap
+ * lowers L[p] and keeps r at or under the limit.  At most 4*C moves and
+ * swaps are made in total. */
+int orc_refineswap(const double *w, const int32_t *old_map, int32_t C, int32_t S, double thr,
+                   int32_t *map)
+{
+    if (C < 0 || S < 1) return -1;
+    size_t nc = (size_t)(C > 0 ? C : 1);
+    double *L = (double *)calloc((size_t)S, sizeof(double));
+    char *done = (char *)calloc((size_t)S, 1);
+    int32_t *heavy = (int32_t *)malloc(sizeof(int32_t) * nc);
+    int32_t *light = (int32_t *)malloc(sizeof(int32_t) * nc);
+    int32_t *sl = (int32_t *)malloc(sizeof(int32_t) * (size_t)S);
+    if (!L || !done || !heavy || !light || !sl) {
+        free(L);
+        free(done);
+        free(heavy);
+        free(light);
+        free(sl);
+        return -1;
+    }
+    double W = 0.0;
+    for (int32_t c = 0; c < C; ++c) W += w[c];
+    double limit = (W / (double)S) * thr;
+    for (int32_t c = 0; c < C; ++c) {
+        map[c] = old_map[c];
+        L[map[c]] += w[c];
+    }
+    order_heavy_first(w, C, heavy);
+    for (int32_t c = 0; c < C; ++c) light[c] = c;
+    g_sort_w = w;
+    qsort(light, (size_t)C, sizeof(int32_t), lighter_first);
+
+    int64_t ops = 0;
+    while (ops < 4 * (int64_t)C) {
+        int32_t p = -1;
+        for (int32_t s = 0; s < S; ++s)
+            if (!done[s] && (p < 0 || L[s] > L[p])) p = s;
+        if (p < 0 || !(L[p] > limit)) break;
+        int32_t q = least_loaded(L, S);
+        int32_t moved = -1;
+        for (int32_t i = 0; i < C; ++i) {
+            int32_t c = heavy[i];
+            if (map[c] == p && L[q] + w[c] <= limit) {
+                moved = c;
+                break;
+            }
+        }
+        if (moved >= 0) {
+            map[moved] = q;
+            L[p] -= w[moved];
+            L[q] += w[moved];
+            ++ops;
+            continue;
+        }
+        /* slots in increasing (load, index) order (insertion sort) */
+        for (int32_t s = 0; s < S; ++s) {
+            int32_t i = s;
+            while (i > 0 && (L[sl[i - 1]] > L[s] || (L[sl[i - 1]] == L[s] && sl[i - 1] > s))) {
+                sl[i] = sl[i - 1];
+                --i;
+            }
+            sl[i] = s;
+        }
+        int32_t sc = -1, sd = -1, sr = -1;
+        for (int32_t ri = 0; ri < S && sc < 0; ++ri) {
+            int32_t r = sl[ri];
+            if (r == p) continue;
+            for (int32_t i = 0; i < C && sc < 0; ++i) {
+                int32_t c = heavy[i];
+                if (map[c] != p) continue;
+                for (int32_t j = 0; j < C; ++j) {
+                    int32_t d = light[j];
+                    if (map[d] == r && w[d] < w[c] && L[r] + (w[c] - w[d]) <= limit) {
+                        sc = c;
+                        sd = d;
+                        sr = r;
+                        break;
+                    }
+                }
+            }
+        }
+        if (sc < 0) {
+            done[p] = 1;
+            continue;
+        }
+        map[sc] = sr;
+        map[sd] = p;
+        L[p] = (L[p] - w[sc]) + w[sd];
+        L[sr] = (L[sr] - w[sd]) + w[sc];
+        ++ops;
+    }
+    free(L);
+    free(done);
+    free(heavy);
+    free(light);
+    free(sl);
     return 0;
 }

@@ -1,4 +1,4 @@
-// Host load balancers of the library: GreedyLB and RefineLB over chunk loads
+// Host load balancers of the library: GreedyLB, RefineLB and RefineSwapLB over chunk loads
 // (Section VI of the paper: GreedyLB in Experiment A, RefineSwapLB in
 // Experiments B and C; Refine is its move-only part).
 //
@@ -93,6 +93,95 @@ void refine(const double* w, const int32_t* old_map, int32_t C, int32_t S, doubl
     }
 }
 
+// RefineSwapLB: as refine(), but when no chunk of p fits on the least loaded
+// slot, make the first swap that fits (slots r != p by increasing load then
+// index, p's chunks heavy first, r's chunks light first, ties by id):
+// w[d] < w[c] and L[r] + (w[c] - w[d]) <= limit; give p up only when neither a
+// move nor a swap fits.  At most 4*C moves and swaps in total.
+void refine_swap(const double* w, const int32_t* old_map, int32_t C, int32_t S, double thr,
+                 int32_t* map) {
+    double W = 0.0;
+    for (int32_t c = 0; c < C; ++c) W += w[c];
+    const double limit = (W / static_cast<double>(S)) * thr;
+    std::vector<double> L(static_cast<size_t>(S), 0.0);
+    for (int32_t c = 0; c < C; ++c) {
+        map[c] = old_map[c];
+        L[map[c]] += w[c];
+    }
+    auto heavier = [w](int32_t a, int32_t b) { return w[a] > w[b] || (w[a] == w[b] && a < b); };
+    auto lighter = [w](int32_t a, int32_t b) { return w[a] < w[b] || (w[a] == w[b] && a < b); };
+    std::vector<std::vector<int32_t>> on(static_cast<size_t>(S));  // heavy-first per slot
+    for (int32_t c : heavy_first(w, C)) on[map[c]].push_back(c);
+    auto insert = [&](int32_t s, int32_t c) {
+        auto& v = on[s];
+        v.insert(std::lower_bound(v.begin(), v.end(), c, heavier), c);
+    };
+    auto remove = [&](int32_t s, int32_t c) {
+        auto& v = on[s];
+        v.erase(std::lower_bound(v.begin(), v.end(), c, heavier));
+    };
+
+    std::vector<char> given_up(static_cast<size_t>(S), 0);
+    std::vector<int32_t> by_load(static_cast<size_t>(S));
+    for (int64_t ops = 0; ops < 4 * static_cast<int64_t>(C);) {
+        int32_t p = -1;
+        for (int32_t s = 0; s < S; ++s)
+            if (!given_up[s] && (p < 0 || L[s] > L[p])) p = s;
+        if (p < 0 || !(L[p] > limit)) break;
+        const int32_t q = static_cast<int32_t>(std::min_element(L.begin(), L.end()) - L.begin());
+        const double Lq = L[q];
+        auto it = std::partition_point(on[p].begin(), on[p].end(),
+                                       [&](int32_t c) { return !(Lq + w[c] <= limit); });
+        if (it != on[p].end() && p != q) {
+            const int32_t c = *it;
+            on[p].erase(it);
+            map[c] = q;
+            L[p] -= w[c];
+            L[q] += w[c];
+            insert(q, c);
+            ++ops;
+            continue;
+        }
+        for (int32_t s = 0; s < S; ++s) by_load[s] = s;
+        std::sort(by_load.begin(), by_load.end(),
+                  [&](int32_t a, int32_t b) { return L[a] < L[b] || (L[a] == L[b] && a < b); });
+        int32_t sc = -1, sd = -1, sr = -1;
+        for (int32_t r : by_load) {
+            if (r == p) continue;
+            std::vector<int32_t> lr(on[r].begin(), on[r].end());
+            std::sort(lr.begin(), lr.end(), lighter);
+            for (int32_t c : on[p]) {
+                for (int32_t d : lr) {
+                    if (!(w[d] < w[c])) break;  // light first: no lighter chunk follows
+                    if (L[r] + (w[c] - w[d]) <= limit) {
+                        sc = c;
+                        sd = d;
+                        break;
+                    }
+                }
+                if (sc >= 0) break;
+            }
+            if (sc >= 0) {
+                sr = r;
+                break;
+            }
+        }
+        if (sc < 0) {
+            given_up[p] = 1;
+            continue;
+        }
+        remove(p, sc);
+        remove(sr, sd);
+        map[sc] = sr;
+        map[sd] = p;
+        L[p] = (L[p] - w[sc]) + w[sd];
+        L[sr] = (L[sr] - w[sd]) + w[sc];
+        insert(sr, sc);
+        insert(p, sd);
+        ++ops;
+    }
+}
+
 }  // namespace
 
 void block_map(int32_t C, int32_t S, int32_t* map) {
@@ -120,11 +209,14 @@ int balance(const double* w, const int32_t* old_map, int32_t C, int32_t S, int s
         greedy(w, C, S, map_out);
         return 0;
     }
-    if (strategy == kRefine) {
+    if (strategy == kRefine || strategy == kRefineSwap) {
         if (!old_map || !(threshold > 0.0)) return -1;
         for (int32_t c = 0; c < C; ++c)
             if (old_map[c] < 0 || old_map[c] >= S) return -1;
-        refine(w, old_map, C, S, threshold, map_out);
+        if (strategy == kRefine)
+            refine(w, old_map, C, S, threshold, map_out);
+        else
+            refine_swap(w, old_map, C, S, threshold, map_out);
         return 0;
     }
     return -2;

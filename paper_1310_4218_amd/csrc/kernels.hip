@@ -158,10 +158,16 @@ struct ItemOut {
     int chunk;
 };
 
-template <typename T, int V, int KAHAN>
-__device__ ItemOut process_item(const DevArgs& a, int item, const T* __restrict__ src,
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+// One item; `hook` runs in every thread right after the first prologue barrier
+// (the persistent kernel uses it to prefetch the next item's descriptor).
+template <typename T, int V, int KAHAN, typename Hook>
+__device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __restrict__ src,
                                 T* __restrict__ dst, const int* hcx, const int* hcy, T* lds,
-                                double* red) {
+                                double* red, Hook hook) {
     const int nz = a.nz, nx = a.nx, ny = a.ny;
     const int NQ = nz / V;
     const int TX = a.tile_x;
@@ -169,13 +175,10 @@ __device__ ItemOut process_item(const DevArgs& a, int item, const T* __restrict_
     const int tzq = threadIdx.x - tcol * NQ;
     const int zoff = tzq * V;
 
-    const int tile = a.items[2 * item];
-    const int rows = a.items[2 * item + 1];
-    const int x0 = a.tiles[4 * tile + 0];
-    const int y0 = a.tiles[4 * tile + 1] + (rows & 0xffff);  // first row of the item
-    const int w = a.tiles[4 * tile + 2] & 0xffff;
-    const int chunk = a.tiles[4 * tile + 3];
-    const int h = (rows >> 16) - (rows & 0xffff);              // rows in the item
+    const int x0 = d.x0;
+    const int y0 = d.y0;
+    const int w = d.wh & 0xffff;
+    const int h = d.wh >> 16;
 
     const int RL = (TX + 2) * nz;             // LDS row stride (elements)
     const bool has0 = tcol < w + 2;           // this thread fetches halo column tcol
@@ -186,6 +189,8 @@ __device__ ItemOut process_item(const DevArgs& a, int item, const T* __restrict_
     int gx1 = x0 - 1 + tcol + TX;
     gx1 = gx1 >= nx ? gx1 - nx : gx1;
     const T cc = static_cast<T>(a.cc), cn = static_cast<T>(a.cn), eps = static_cast<T>(a.eps);
+
+    int* kbuf = reinterpret_cast<int*>(lds + kRingRows * RL);
 
     double chk = 0.0, work = 0.0;
     for (int f = 0; f < a.nfields; ++f) {
@@ -204,62 +209,83 @@ __device__ ItemOut process_item(const DevArgs& a, int item, const T* __restrict_
             if (has0) st<T, V>(row + tcol * nz + zoff, r0);
             if (has1) st<T, V>(row + (tcol + TX) * nz + zoff, r1);
         };
-
-        Vec<T, V> p0, p1;
-        for (int i = -1; i <= 1; ++i) {  // prologue: rows y0-1, y0, y0+1
-            fetch(i, p0, p1);
-            put(i, p0, p1);
-        }
-        __syncthreads();
-
-        for (int r = 0; r < h; ++r) {
-            const bool pre = r + 2 <= h;
-            if (pre) fetch(r + 2, p0, p1);  // in flight during the compute below
-            if (active) {
-                const int gy = y0 + r;
-                const int k = column_k(a, hcx, hcy, x0 + tcol, gy);
-                const T* Lm = lds + ((r - 1) & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
-                const T* Lc = lds + (r & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
-                const T* Lp = lds + ((r + 1) & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
-                const Vec<T, V> c = ld<T, V>(Lc);
-                const Vec<T, V> xm = ld<T, V>(Lc - nz);
-                const Vec<T, V> xp = ld<T, V>(Lc + nz);
-                const Vec<T, V> ym = ld<T, V>(Lm);
-                const Vec<T, V> yp = ld<T, V>(Lp);
-                const T below = Lc[-1];  // neighbouring column's data when tzq == 0
-                const T above = Lc[V];   // ... when tzq == NQ - 1 (ignored then)
-                const T zlo = (tzq == 0) ? c.v[0] : below;
-                const T zhi = (tzq == NQ - 1) ? c.v[V - 1] : above;
-                T q[V];
+        auto compute = [&](int r) {
+            if (!active) return;
+            const int gy = y0 + r;
+            const int k = kbuf[r * TX + tcol];
+            const T* Lm = lds + ((r - 1) & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
+            const T* Lc = lds + (r & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
+            const T* Lp = lds + ((r + 1) & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
+            const Vec<T, V> c = ld<T, V>(Lc);
+            const Vec<T, V> xm = ld<T, V>(Lc - nz);
+            const Vec<T, V> xp = ld<T, V>(Lc + nz);
+            const Vec<T, V> ym = ld<T, V>(Lm);
+            const Vec<T, V> yp = ld<T, V>(Lp);
+            const T below = Lc[-1];  // neighbouring column's data when tzq == 0
+            const T above = Lc[V];   // ... when tzq == NQ - 1 (ignored then)
+            const T zlo = (tzq == 0) ? c.v[0] : below;
+            const T zhi = (tzq == NQ - 1) ? c.v[V - 1] : above;
+            T q[V];
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const T zm = (v == 0) ? zlo : c.v[v - 1];
-                    const T zp = (v == V - 1) ? zhi : c.v[v + 1];
-                    T sum = xm.v[v] + xp.v[v];
-                    sum = sum + ym.v[v];
-                    sum = sum + yp.v[v];
-                    sum = sum + zm;
-                    sum = sum + zp;
-                    q[v] = combine(cc, cn, c.v[v], sum);
-                }
-                physics_vec<KAHAN, T, V>(eps, k, q);
-                Vec<T, V> out;
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    out.v[v] = q[v];
-                    chk += static_cast<double>(q[v]);
-                }
-                st<T, V>(fdst + (static_cast<int64_t>(gy) * nx + x0 + tcol) * nz + zoff, out);
-                if (tzq == 0) work += static_cast<double>(nz) * static_cast<double>(a.alpha + k);
+            for (int v = 0; v < V; ++v) {
+                const T zm = (v == 0) ? zlo : c.v[v - 1];
+                const T zp = (v == V - 1) ? zhi : c.v[v + 1];
+                T sum = xm.v[v] + xp.v[v];
+                sum = sum + ym.v[v];
+                sum = sum + yp.v[v];
+                sum = sum + zm;
+                sum = sum + zp;
+                q[v] = combine(cc, cn, c.v[v], sum);
             }
-            if (pre) put(r + 2, p0, p1);
+            physics_vec<KAHAN, T, V>(eps, k, q);
+            Vec<T, V> out;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                out.v[v] = q[v];
+                chk += static_cast<double>(q[v]);
+            }
+            st<T, V>(fdst + (static_cast<int64_t>(gy) * nx + x0 + tcol) * nz + zoff, out);
+            if (tzq == 0) work += static_cast<double>(nz) * static_cast<double>(a.alpha + k);
+        };
+
+        // Prologue: rows -1, 0, 1 go to the LDS ring, row 2 stays in registers.
+        Vec<T, V> m0, m1, c0, c1, n0, n1, A0, A1, B0, B1;
+        fetch(-1, m0, m1);
+        fetch(0, c0, c1);
+        fetch(1, n0, n1);
+        if (2 <= h) fetch(2, A0, A1);
+        if (f == 0) {
+            // Trip counts of the item's columns, looked up once per item; these
+            // table loads are in flight together with the row loads above.
+            for (int i = threadIdx.x; i < w * h; i += blockDim.x) {
+                const int r = i / w, c = i - r * w;
+                kbuf[r * TX + c] = column_k(a, hcx, hcy, x0 + c, y0 + r);
+            }
+        }
+        put(-1, m0, m1);
+        put(0, c0, c1);
+        put(1, n0, n1);
+        __syncthreads();
+        if (f == 0) hook();
+
+        // Row r: fetch row r+3 (registers), compute row r from the ring, move row
+        // r+2 (fetched one row earlier) into the ring.  Two rows stay in flight.
+        // Unrolled by two so that the register slots A and B keep fixed names.
+        auto row = [&](int r, Vec<T, V>& P0, Vec<T, V>& P1, Vec<T, V>& Q0, Vec<T, V>& Q1) {
+            if (r + 3 <= h) fetch(r + 3, Q0, Q1);
+            compute(r);
+            if (r + 2 <= h) put(r + 2, P0, P1);
             __syncthreads();
+        };
+        for (int r = 0; r < h; r += 2) {
+            row(r, A0, A1, B0, B1);
+            if (r + 1 < h) row(r + 1, B0, B1, A0, A1);
         }
     }
     ItemOut o;
     o.checksum = block_sum(chk, red);
     o.work = block_sum(work, red);
-    o.chunk = chunk;
+    o.chunk = d.chunk;
     return o;
 }
 
@@ -284,15 +310,12 @@ __device__ __forceinline__ StepInfo step_info(const DevArgs& a) {
 // Called by thread 0 after an item: its checksum partial, the chunk's loads, and
 // one visit for each tile row the item covered (plain increments: exactly one
 // workgroup owns a row in a step, so a second claim would show as a miscount).
-__device__ __forceinline__ void record_item(const DevArgs& a, int item, const ItemOut& o,
-                                            double ticks) {
-    a.partials[item] = o.checksum;
-    unsafeAtomicAdd(&a.loads_work[o.chunk], o.work);
-    unsafeAtomicAdd(&a.loads_time[o.chunk], ticks);
-    const int tile = a.items[2 * item];
-    const int rows = a.items[2 * item + 1];
-    int32_t* v = a.visits + a.row_base[tile];
-    for (int r = rows & 0xffff; r < (rows >> 16); ++r) v[r] += 1;
+__device__ __forceinline__ void record_item(const DevArgs& a, const ItemDesc& d,
+                                            const ItemOut& o, double ticks) {
+    a.partials[d.id] = o.checksum;
+    unsafeAtomicAdd(&a.loads_work[d.chunk], o.work);
+    unsafeAtomicAdd(&a.loads_time[d.chunk], ticks);
+    for (int r = 0; r < (d.wh >> 16); ++r) a.visits[d.vbase + r] += 1;
 }
 
 // Deterministic sum of the per-item partials (item order) into the checksum ring,
@@ -310,6 +333,10 @@ __device__ void finish_step(const DevArgs& a, uint64_t step, double* red) {
 }
 
 // ---- claiming work ----------------------------------------------------------------
+// Workgroups are dispatched to the eight XCDs round-robin (workgroup w runs on
+// XCD w % 8).  When S is a multiple of 8, slot s is served only by workgroups
+// on XCD s % 8, so the items of a chunk share that XCD's L2.  Every slot has
+// exactly G workgroups, with ranks 0..G-1.
 __device__ __forceinline__ int home_slot(const DevArgs& a, int wg) {
     if (a.xcd_slots) {
         const int per_xcd = a.nslots / 8;
@@ -317,13 +344,18 @@ __device__ __forceinline__ int home_slot(const DevArgs& a, int wg) {
     }
     return wg % a.nslots;
 }
+__device__ __forceinline__ int slot_rank(const DevArgs& a, int wg) {
+    if (a.xcd_slots) return (wg >> 3) / (a.nslots / 8);
+    return wg / a.nslots;
+}
 
+// Queue index of a claimed item of slot s, or -1 if its queue is empty.
 __device__ __forceinline__ int try_claim(const DevArgs& a, int s) {
     const int beg = a.seg[s];
     const int n = a.seg[s + 1] - beg;
     if (__hip_atomic_load(&a.heads[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) return -1;
     const int i = atomicAdd(&a.heads[s], 1);
-    return i < n ? a.worklist[beg + i] : -1;
+    return i < n ? beg + i : -1;
 }
 
 // Called by all lanes of wave 0.  Home queue first; then, if stealing is on,
@@ -332,10 +364,10 @@ __device__ __forceinline__ int try_claim(const DevArgs& a, int s) {
 // for good (heads only grow), so the scan ends after at most S failures.
 __device__ int claim(const DevArgs& a, int home) {
     const int lane = threadIdx.x & (kWave - 1);
-    int item = -1;
-    if (lane == 0) item = try_claim(a, home);
-    item = __shfl(item, 0, kWave);
-    if (item >= 0 || !a.steal) return item;
+    int qi = -1;
+    if (lane == 0) qi = try_claim(a, home);
+    qi = __shfl(qi, 0, kWave);
+    if (qi >= 0 || !a.steal) return qi;
     const int S = a.nslots;
     const int per_xcd = a.xcd_slots ? S / 8 : S;
     int base = 0;
@@ -361,36 +393,66 @@ __device__ int claim(const DevArgs& a, int home) {
     return -1;
 }
 
+__device__ __forceinline__ ItemDesc no_item() {
+    ItemDesc d{};
+    d.id = -1;
+    return d;
+}
+
 // ---- kernels ----------------------------------------------------------------------
+// One launch per step.  Workgroup (slot s, rank j) starts with item j of its
+// slot's queue (no atomic), then claims the next item of its slot at the start
+// of each item (the claim and the next descriptor load overlap the item's own
+// work); once its slot is drained it claims through `claim` (stealing).  The
+// last workgroup to finish resets the heads, sums the checksum partials and
+// advances the step counter.
 template <typename T, int V, int KAHAN>
 __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
     __shared__ double red[kMaxBlock / kWave];
-    __shared__ int s_item;
+    __shared__ ItemDesc s_desc;
     __shared__ int s_last;
 
     const StepInfo si = step_info(a);
     const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);
     T* dst = static_cast<T*>((si.step & 1) ? a.field0 : a.field1);
     const int home = home_slot(a, blockIdx.x);
+    const int rank = slot_rank(a, blockIdx.x);
+    const int hbeg = a.seg[home];
+    const int hn = a.seg[home + 1] - hbeg;
     double busy = 0.0;
 
+    if (threadIdx.x == 0) s_desc = rank < hn ? a.queue[hbeg + rank] : no_item();
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x < kWave) {
-            const int item = claim(a, home);
-            if (threadIdx.x == 0) s_item = item;
+        ItemDesc d = s_desc;
+        if (d.id < 0) {                      // home queue drained: claim with stealing
+            __syncthreads();
+            if (threadIdx.x < kWave) {
+                const int qi = claim(a, home);
+                if (threadIdx.x == 0) s_desc = qi >= 0 ? a.queue[qi] : no_item();
+            }
+            __syncthreads();
+            d = s_desc;
+            if (d.id < 0) break;
         }
-        __syncthreads();
-        const int item = s_item;
-        if (item < 0) break;
+        __syncthreads();                     // every thread holds d before s_desc changes
+        int nidx = hn;
+        if (threadIdx.x == 0) nidx = atomicAdd(&a.heads[home], 1);
+        ItemDesc nd = no_item();
+        auto ahead = [&]() {
+            if (threadIdx.x == 0 && nidx < hn) nd = a.queue[hbeg + nidx];
+        };
         const uint64_t t_start = wall_clock64();
-        const ItemOut o = process_item<T, V, KAHAN>(a, item, src, dst, si.hcx, si.hcy, lds, red);
+        const ItemOut o = process_item<T, V, KAHAN>(a, d, src, dst, si.hcx, si.hcy, lds, red, ahead);
         if (threadIdx.x == 0) {
             const double ticks = static_cast<double>(wall_clock64() - t_start);
             busy += ticks;
-            record_item(a, item, o, ticks);
+            record_item(a, d, o, ticks);
+            s_desc = nd;
         }
+        __syncthreads();
     }
     if (threadIdx.x == 0) {
         a.wg_busy[blockIdx.x] += busy;
@@ -401,7 +463,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     __syncthreads();
     if (s_last) {
         __threadfence();
-        for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) a.heads[s] = 0;
+        for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) a.heads[s] = a.head0;
         finish_step(a, si.step, red);
     }
 }
@@ -416,10 +478,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
     const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);
     T* dst = static_cast<T*>((si.step & 1) ? a.field0 : a.field1);
     const int item = a.item_off[chunk] + blockIdx.x;
-    if (item >= a.item_off[chunk + 1]) return;  // grid sized for the largest plan
+    if (item >= a.item_off[chunk + 1]) return;  // grid sized for a larger plan
+    const ItemDesc d = a.items[item];
     const uint64_t t_start = wall_clock64();
-    const ItemOut o = process_item<T, V, KAHAN>(a, item, src, dst, si.hcx, si.hcy, lds, red);
-    if (threadIdx.x == 0) record_item(a, item, o, static_cast<double>(wall_clock64() - t_start));
+    const ItemOut o = process_item<T, V, KAHAN>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
+    if (threadIdx.x == 0) record_item(a, d, o, static_cast<double>(wall_clock64() - t_start));
 }
 
 __global__ __launch_bounds__(256) void k_finish(DevArgs a) {
@@ -450,7 +513,7 @@ __global__ void k_zero(uint32_t* p, size_t nwords) {
 }
 
 __global__ void k_reset_control(DevArgs a) {
-    for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) a.heads[s] = 0;
+    for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) a.heads[s] = a.head0;
     if (threadIdx.x == 0) {
         a.ctrl->done = 0;
         a.ctrl->step = 0;

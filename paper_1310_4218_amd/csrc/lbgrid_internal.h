@@ -23,18 +23,27 @@ struct Ctrl {
     uint64_t pad1[6];
 };
 
+// One work item: a range of rows of one tile, self-contained so that a claim
+// needs a single dependent load.
+struct alignas(16) ItemDesc {
+    int32_t x0, y0;         // first column and first row of the item
+    int32_t wh;             // columns | rows << 16
+    int32_t chunk;
+    int32_t id;             // index in chunk order (its checksum partial); -1 = none
+    int32_t vbase;          // visit counter of the item's first row
+    int32_t pad0, pad1;
+};
+
 // Kernel arguments: every pointer is device memory inside the caller's buffers.
 struct DevArgs {
     void* field0;
     void* field1;
     const int32_t* ktab;
-    const int32_t* tiles;      // 4 ints per tile: x0, y0, w | h << 16, chunk
-    const int32_t* row_base;   // per tile: index of its first row in visits
-    const int32_t* items;      // 2 ints per item: tile, first row | end row << 16
+    const ItemDesc* items;     // items in chunk order
     const int32_t* item_off;   // C + 1: items of chunk c are [item_off[c], item_off[c+1])
-    const int32_t* worklist;   // item ids, grouped by slot
-    const int32_t* seg;        // S + 1 offsets into worklist
-    int32_t* heads;            // S claim counters
+    const ItemDesc* queue;     // the same items grouped by slot, each slot's in cost order
+    const int32_t* seg;        // S + 1 offsets into queue
+    int32_t* heads;            // S claim counters; each launch starts them at head0
     Ctrl* ctrl;
     double* loads_work;        // C
     double* loads_time;        // C
@@ -44,7 +53,8 @@ struct DevArgs {
     int32_t* visits;           // per tile row: times it was computed
     int64_t ncells;            // cells per field
     int32_t nx, ny, nz, nfields;
-    int32_t ntiles, nslots, nwg, steal;
+    int32_t nslots, nwg, steal;
+    int32_t head0;             // G: the first G items of a slot go one to each of its workgroups
     int32_t tile_x;            // TX; block = TX * nz / V threads
     int32_t r2cut;
     int32_t kmin;

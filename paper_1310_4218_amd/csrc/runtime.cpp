@@ -47,9 +47,9 @@ struct Plan {
     int64_t ncells = 0;
     std::vector<int32_t> xs, ys;
     // workspace layout (byte offsets)
-    size_t off_ctrl = 0, off_ktab = 0, off_tiles = 0, off_rowbase = 0, off_items = 0,
-           off_itemoff = 0, off_work = 0, off_seg = 0, off_heads = 0, off_lw = 0, off_lt = 0,
-           off_part = 0, off_hist = 0, off_busy = 0, off_visits = 0, off_sum = 0, ws_bytes = 0;
+    size_t off_ctrl = 0, off_ktab = 0, off_items = 0, off_itemoff = 0, off_queue = 0, off_seg = 0,
+           off_heads = 0, off_lw = 0, off_lt = 0, off_part = 0, off_hist = 0, off_busy = 0,
+           off_visits = 0, off_sum = 0, ws_bytes = 0;
     size_t field_bytes = 0;
 };
 
@@ -110,14 +110,16 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         p.TX = c->tile_x;
     } else {
         p.TX = 16;
-        while (p.TX > 1 && (p.TX * NQ > kMaxBlock || (p.TX + 2) * row_elems_per_col > kMaxLds)) --p.TX;
+        while (p.TX > 1 && (p.TX * NQ > kMaxBlock ||
+                            (p.TX + 2) * row_elems_per_col + 4 * 16 * p.TX > kMaxLds)) --p.TX;
     }
     p.TY = c->tile_y > 0 ? c->tile_y : 16;
-    if (p.TX > 32767 || p.TY > 32767) return bad("tile sizes must be < 32768");
+    if (p.TX > 1024 || p.TY > 256) return bad("tile sizes must be at most 1024 x 256");
     p.block = p.TX * NQ;
     if (p.block > kMaxBlock) return bad("tile_x * nz / vector width exceeds 1024 threads");
-    p.lds = (p.TX + 2) * row_elems_per_col;
-    if (p.lds > kMaxLds) return bad("tile_x too large: the LDS row ring exceeds 64 KiB");
+    // LDS: the four-row ring, then one trip count per column of the tile
+    p.lds = (p.TX + 2) * row_elems_per_col + sizeof(int32_t) * static_cast<size_t>(p.TX) * p.TY;
+    if (p.lds > kMaxLds) return bad("tile too large: the LDS row ring and trip counts exceed 64 KiB");
 
     // tiles of every chunk, chunks in id order, tiles in raster order; every tile
     // row can become an item of its own
@@ -146,11 +148,9 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
     p.off_ctrl = take(sizeof(Ctrl));
     p.off_ktab = take(sizeof(int32_t) * (static_cast<size_t>(p.r2cut) + 1));
-    p.off_tiles = take(sizeof(int32_t) * 4 * static_cast<size_t>(p.ntiles));
-    p.off_rowbase = take(sizeof(int32_t) * static_cast<size_t>(p.ntiles));
-    p.off_items = take(sizeof(int32_t) * 2 * static_cast<size_t>(p.nrows));
+    p.off_items = take(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
     p.off_itemoff = take(sizeof(int32_t) * (static_cast<size_t>(p.C) + 1));
-    p.off_work = take(sizeof(int32_t) * static_cast<size_t>(p.nrows));
+    p.off_queue = take(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
     p.off_seg = take(sizeof(int32_t) * (static_cast<size_t>(p.S) + 1));
     p.off_heads = take(sizeof(int32_t) * static_cast<size_t>(p.S));
     p.off_lw = take(sizeof(double) * static_cast<size_t>(p.C));
@@ -179,7 +179,7 @@ struct lb_ctx {
     std::vector<int32_t> tiles;       // 4 per tile
     std::vector<int32_t> tile_off;    // C + 1: tiles of chunk c
     std::vector<int32_t> row_base;    // per tile: its first row in the visit counters
-    std::vector<int32_t> items;       // 2 per item of the installed plan
+    std::vector<ItemDesc> items;      // the installed plan, chunk order
     std::vector<int32_t> item_off;    // C + 1
     int64_t plan_version = 0;
     int64_t plain_graph_version = -1;
@@ -189,7 +189,7 @@ struct lb_ctx {
     int64_t steps = 0;
     int64_t window_steps = 0;
     double clock_hz = 100e6;
-    int32_t* staging = nullptr;       // pinned: items, item_off, worklist, seg, nitems
+    void* staging = nullptr;          // pinned: items, queue, item_off, seg, nitems
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
@@ -280,7 +280,7 @@ int upload_plan(lb_ctx* x, const double* cost) {
     x->item_off.assign(static_cast<size_t>(p.C) + 1, 0);
     std::vector<double> item_cost;
     for (int32_t c = 0; c < p.C; ++c) {
-        x->item_off[c] = static_cast<int32_t>(item_cost.size());
+        x->item_off[c] = static_cast<int32_t>(x->items.size());
         const int i = c % p.px, j = c / p.px;
         const double area_c = static_cast<double>(p.xs[i + 1] - p.xs[i]) * (p.ys[j + 1] - p.ys[j]);
         for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) {
@@ -291,13 +291,19 @@ int upload_plan(lb_ctx* x, const double* cost) {
                 pieces = static_cast<int>(std::min<double>(h, std::ceil(tc / target)));
             for (int k = 0; k < pieces; ++k) {
                 const int r0 = (k * h) / pieces, r1 = ((k + 1) * h) / pieces;
-                x->items.push_back(t);
-                x->items.push_back(r0 | (r1 << 16));
+                ItemDesc d{};
+                d.x0 = x->tiles[4 * t + 0];
+                d.y0 = x->tiles[4 * t + 1] + r0;
+                d.wh = w | ((r1 - r0) << 16);
+                d.chunk = c;
+                d.id = static_cast<int32_t>(x->items.size());
+                d.vbase = x->row_base[t] + r0;
+                x->items.push_back(d);
                 item_cost.push_back(tc * (r1 - r0) / h);
             }
         }
     }
-    const int32_t n = static_cast<int32_t>(item_cost.size());
+    const int32_t n = static_cast<int32_t>(x->items.size());
     x->item_off[p.C] = n;
 
     std::vector<std::vector<int32_t>> by_slot(static_cast<size_t>(p.S));
@@ -308,12 +314,12 @@ int upload_plan(lb_ctx* x, const double* cost) {
         HIP_TRY(x, hipEventSynchronize(x->upload_done));
         x->upload_pending = false;
     }
-    int32_t* st_items = x->staging;
-    int32_t* st_off = st_items + 2 * static_cast<size_t>(p.nrows);
-    int32_t* st_work = st_off + p.C + 1;
-    int32_t* st_seg = st_work + p.nrows;
+    ItemDesc* st_items = static_cast<ItemDesc*>(x->staging);
+    ItemDesc* st_queue = st_items + p.nrows;
+    int32_t* st_off = reinterpret_cast<int32_t*>(st_queue + p.nrows);
+    int32_t* st_seg = st_off + p.C + 1;
     int32_t* st_n = st_seg + p.S + 1;
-    std::memcpy(st_items, x->items.data(), sizeof(int32_t) * x->items.size());
+    std::memcpy(st_items, x->items.data(), sizeof(ItemDesc) * n);
     std::memcpy(st_off, x->item_off.data(), sizeof(int32_t) * x->item_off.size());
     int32_t k = 0;
     for (int32_t s = 0; s < p.S; ++s) {
@@ -321,15 +327,15 @@ int upload_plan(lb_ctx* x, const double* cost) {
         auto& v = by_slot[s];
         std::stable_sort(v.begin(), v.end(),
                          [&](int32_t a, int32_t b) { return item_cost[a] > item_cost[b]; });
-        for (int32_t it : v) st_work[k++] = it;
+        for (int32_t it : v) st_queue[k++] = x->items[it];
     }
     st_seg[p.S] = k;
     *st_n = n;
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_items, st_items, sizeof(int32_t) * 2 * n,
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_items, st_items, sizeof(ItemDesc) * n,
+                              hipMemcpyHostToDevice, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_queue, st_queue, sizeof(ItemDesc) * n,
                               hipMemcpyHostToDevice, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_itemoff, st_off, sizeof(int32_t) * (p.C + 1),
-                              hipMemcpyHostToDevice, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_work, st_work, sizeof(int32_t) * n,
                               hipMemcpyHostToDevice, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_seg, st_seg, sizeof(int32_t) * (p.S + 1),
                               hipMemcpyHostToDevice, x->stream));
@@ -469,8 +475,8 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
         return hip_bail(e, "hipStreamCreateWithFlags");
     if ((e = hipEventCreateWithFlags(&x->upload_done, hipEventDisableTiming)) != hipSuccess)
         return hip_bail(e, "hipEventCreateWithFlags");
-    if ((e = hipHostMalloc(reinterpret_cast<void**>(&x->staging),
-                           sizeof(int32_t) * (3 * static_cast<size_t>(P.nrows) + P.C + P.S + 3))) != hipSuccess)
+    if ((e = hipHostMalloc(&x->staging, sizeof(ItemDesc) * 2 * static_cast<size_t>(P.nrows) +
+                                            sizeof(int32_t) * (static_cast<size_t>(P.C) + P.S + 3))) != hipSuccess)
         return hip_bail(e, "hipHostMalloc");
 
     build_tiles(x);
@@ -480,11 +486,9 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.field0 = x->field[0];
     a.field1 = x->field[1];
     a.ktab = reinterpret_cast<const int32_t*>(x->ws + P.off_ktab);
-    a.tiles = reinterpret_cast<const int32_t*>(x->ws + P.off_tiles);
-    a.row_base = reinterpret_cast<const int32_t*>(x->ws + P.off_rowbase);
-    a.items = reinterpret_cast<const int32_t*>(x->ws + P.off_items);
+    a.items = reinterpret_cast<const ItemDesc*>(x->ws + P.off_items);
     a.item_off = reinterpret_cast<const int32_t*>(x->ws + P.off_itemoff);
-    a.worklist = reinterpret_cast<const int32_t*>(x->ws + P.off_work);
+    a.queue = reinterpret_cast<const ItemDesc*>(x->ws + P.off_queue);
     a.seg = reinterpret_cast<const int32_t*>(x->ws + P.off_seg);
     a.heads = reinterpret_cast<int32_t*>(x->ws + P.off_heads);
     a.ctrl = reinterpret_cast<Ctrl*>(x->ws + P.off_ctrl);
@@ -496,7 +500,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.visits = reinterpret_cast<int32_t*>(x->ws + P.off_visits);
     a.ncells = P.ncells;
     a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.nfields = P.nfields;
-    a.ntiles = P.ntiles; a.nslots = P.S; a.nwg = P.nwg; a.steal = cfg->steal;
+    a.nslots = P.S; a.nwg = P.nwg; a.steal = cfg->steal; a.head0 = P.G;
     a.tile_x = P.TX;
     a.r2cut = P.r2cut;
     a.kmin = cfg->kmin;
@@ -516,10 +520,6 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     if ((r = launch_zero(x->ws, P.ws_bytes, x->stream)) != 0) return hip_bail(static_cast<hipError_t>(r), "zero workspace");
     if ((e = hipMemcpyAsync(x->ws + P.off_ktab, ktab.data(), sizeof(int32_t) * ktab.size(),
                             hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload cost table");
-    if ((e = hipMemcpyAsync(x->ws + P.off_tiles, x->tiles.data(), sizeof(int32_t) * x->tiles.size(),
-                            hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload tiles");
-    if ((e = hipMemcpyAsync(x->ws + P.off_rowbase, x->row_base.data(), sizeof(int32_t) * x->row_base.size(),
-                            hipMemcpyHostToDevice, x->stream)) != hipSuccess) return hip_bail(e, "upload row bases");
     if ((r = launch_reset_control(a, x->stream)) != 0) return hip_bail(static_cast<hipError_t>(r), "reset control");
     if (init_field) {
         if ((e = hipMemcpyAsync(x->field[0], init_field, P.field_bytes, hipMemcpyDefault, x->stream)) != hipSuccess)
@@ -708,7 +708,7 @@ int lb_stats(lb_ctx* x, lb_stats_t* out) {
     out->nchunks = p.C;
     out->ntiles = p.ntiles;
     out->nrows = p.nrows;
-    out->nitems = static_cast<int32_t>(x->items.size() / 2);
+    out->nitems = static_cast<int32_t>(x->items.size());
     out->nslots = p.S;
     out->nwg = p.nwg;
     out->block = p.block;

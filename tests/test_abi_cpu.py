@@ -147,6 +147,20 @@ def test_host_refine_bit_exact_vs_oracle(lib):
             assert nm == int((ref != old).sum())
 
 
+def test_host_refineswap_bit_exact_vs_oracle(lib):
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        C_ = int(rng.integers(1, 200))
+        S = int(rng.integers(1, 30))
+        w = random_loads(rng, C_)
+        old = rng.integers(0, S, size=C_).astype(np.int32)
+        for thr in (1.0, 1.05, 1.2):
+            m, nm = _abi.balance_host(w, S, "refineswap", old_map=old, threshold=thr)
+            ref = oracle.refineswap(w, old, S, thr)
+            np.testing.assert_array_equal(m, ref)
+            assert nm == int((ref != old).sum())
+
+
 def test_host_balancer_large_instance(lib):
     wl = W.large()
     k = oracle.kfield(wl.nx, wl.ny, wl.hot, 0, wl.sigma, wl.kmin, wl.kmax)

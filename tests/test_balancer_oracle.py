@@ -112,3 +112,47 @@ def test_refine_moves_fewer_than_greedy_on_table5_shift():
 def test_block_map():
     assert list(oracle.block_map(16, 4)) == [0] * 4 + [1] * 4 + [2] * 4 + [3] * 4
     assert list(oracle.block_map(3, 8)) == [0, 1, 2]
+
+
+def test_refineswap_swaps_when_no_move_fits():
+    """Two processors holding {3, 3} and {2, 2}: no single move brings the first under the
+    average, a swap of a 3 with a 2 balances both (the swap case of RefineSwapLB)."""
+    w = np.array([3.0, 3.0, 2.0, 2.0])
+    old = np.array([0, 0, 1, 1], np.int32)
+    assert list(oracle.refine(w, old, 2, 1.0)) == [0, 0, 1, 1]
+    m = oracle.refineswap(w, old, 2, 1.0)
+    assert list(oracle.slot_loads(w, m, 2)) == [5.0, 5.0]
+    assert int((m != old).sum()) == 2
+
+
+def test_refineswap_postconditions_random():
+    """Max load never grows; every slot that was at or under the limit stays there; a slot
+    still above the limit has no chunk that could move onto the least loaded slot; the
+    number of chunks on each slot changes only through moves (swaps keep counts)."""
+    rng = np.random.default_rng(9)
+    for w, S in random_instances(300, 21, Cmax=10, Smax=4):
+        C_ = len(w)
+        old = rng.integers(0, S, size=C_).astype(np.int32)
+        for thr in (1.0, 1.05):
+            m = oracle.refineswap(w, old, S, thr)
+            L0 = oracle.slot_loads(w, old, S)
+            L = oracle.slot_loads(w, m, S)
+            limit = (w.sum() / S) * thr
+            assert L.max() <= L0.max() + 1e-9
+            for s in range(S):
+                if L0[s] <= limit:
+                    assert L[s] <= limit * (1 + 1e-12)
+                else:
+                    assert L[s] <= L0[s] + 1e-9
+            q = int(np.argmin(L))
+            for p in range(S):
+                if L[p] > limit:
+                    for c in range(C_):
+                        if m[c] == p and p != q:
+                            assert not (L[q] + w[c] <= limit)
+
+
+def test_refineswap_equals_refine_when_moves_suffice():
+    w = np.array([2.0] * 8 + [1.0] * 8)
+    old = np.array([0, 0, 0, 1, 2, 2, 2, 3, 0, 1, 1, 1, 2, 3, 3, 3], np.int32)
+    np.testing.assert_array_equal(oracle.refineswap(w, old, 4, 1.0), oracle.refine(w, old, 4, 1.0))
