@@ -7,11 +7,13 @@ cost field, the 7-point update, the column physics, the per-chunk load
 measurement and the FP64 checksum, all in the library's HIP kernels; every
 R steps (R = 10 for the default workload) the loads of the window are read
 back and GreedyLB remaps the chunks onto the slots (the paper's migration
-point, Section VI).  Two paths are timed on the same inputs:
+point, Section VI), which also rebuilds the cost-ordered item queues.  Two
+paths are timed on the same inputs:
   balanced: one persistent launch per step (replayed from a HIP graph of R
-            steps), cost-ordered per-slot queues, measurement + rebalance every
-            R steps, all inside the timed region;
-  plain:    one launch per chunk in chunk-id order, no balancing.
+            steps), per-slot cost-ordered queues, measurement + rebalance
+            every R steps, all inside the timed region;
+  plain:    one launch per chunk over its tiles, in chunk-id order, no
+            balancing (the static decomposition).
 ``value`` is the balanced path's point-updates/s (cells x steps / wall time).
 The default workload is the 256x256x64 grid with 64 equal chunks and a hotspot
 moving one cell per step (k in 1..200, sigma 24), balanced onto 256 slots.
@@ -30,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "grid point-updates/s and max/avg chunk-load ratio, balanced vs plain, 1 MI355X"
 
 
 def kernel_source_hash() -> str:
@@ -41,8 +44,8 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per launch of the persistent kernel from committed rocprofv3 counter
-    summaries, if they were taken on the current kernel source; else None."""
+    """HBM bytes per launch of the persistent kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -57,58 +60,52 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_balanced(Grid, wl, steps, warmup, R, strategy, threshold, torch):
-    import numpy as np
-
-    g = Grid(wl, graph_steps=R)
+def run_balanced(Grid, wl, steps, warmup, R, params, torch):
+    g = Grid(wl, graph_steps=R, **params)
     stream = g.stream
 
-    def window(n, events=None):
-        if events is not None:
-            events[0].record(stream)
+    def window(n, evs=None):
+        if evs is not None:
+            evs[0].record(stream)
         g.step(n, "persistent")
-        if events is not None:
-            events[1].record(stream)
+        if evs is not None:
+            evs[1].record(stream)
         loads = g.measure("work")            # synchronizes: the paper's measurement point
-        lam = g.rebalance(strategy, threshold, None)
-        return loads, lam
+        m, nmig, lam = g.rebalance(wl.strategy, wl.threshold)
+        return loads, nmig, lam
 
     done = 0
     while done < warmup:                     # warm-up windows (graph capture happens here)
         n = min(R, warmup - done)
         window(n)
         done += n
-    g.measure("work")                        # fresh window, fresh busy counters
+    g.measure("work")                        # fresh window and busy counters
     torch.cuda.synchronize()
-    evs = []
-    lam_win, loads_win = [], []
+    evs, wins = [], []
     t0 = time.perf_counter()
     done = 0
     while done < steps:
         n = min(R, steps - done)
         ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-        busy_before = None
-        loads, (m, nmig, (lam_before, lam_after)) = window(n, ev)
-        evs.append((ev, n))
-        lam_win.append((lam_before, lam_after, nmig))
-        loads_win.append(loads)
+        loads, nmig, lam = window(n, ev)
+        evs.append(ev)
+        wins.append((loads, nmig, lam))
         done += n
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_s = sum(e[0].elapsed_time(e[1]) for e, _ in evs) / 1e3
-    # workgroup balance of the persistent kernel over one extra measured window
-    g.measure("work")
+    kernel_s = sum(e[0].elapsed_time(e[1]) for e in evs) / 1e3
+    # workgroup busy time of the persistent kernel over one more window
     g.step(R, "persistent")
     busy = g.wg_busy()
-    w_last = g.measure("work")
+    g.measure("work")
     st = g.stats()
     g.close()
-    return dict(wall=wall, kernel_s=kernel_s, lam=lam_win, loads=loads_win, busy=busy,
-                w_last=w_last, stats=st)
+    return dict(wall=wall, kernel_s=kernel_s, wins=wins, busy=busy, stats=st)
 
 
-def run_plain(Grid, wl, steps, warmup, torch):
-    g = Grid(wl)
+def run_plain(Grid, wl, steps, warmup, params, torch):
+    p = {k: v for k, v in params.items() if k in ("tile_x", "tile_y")}
+    g = Grid(wl, **p)
     g.step(warmup, "plain")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -116,7 +113,7 @@ def run_plain(Grid, wl, steps, warmup, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     g.close()
-    return dict(wall=wall)
+    return dict(wall=wall, steps=steps)
 
 
 def cpu_baseline(wl, budget_s):
@@ -129,9 +126,10 @@ def cpu_baseline(wl, budget_s):
     t = time.perf_counter()
     oracle.run(wl, nsteps=n)
     dt = time.perf_counter() - t
-    return dict(value=wl.ncells * n / dt, unit="point-updates/s", cores=1, kind="oracle",
-                sample=f"{n} steps of the {wl.name} workload from the seeded field "
-                       f"(single-threaded FP64 C oracle)")
+    return dict(value=wl.ncells * wl.nfields * n / dt, unit="point-updates/s", cores=1,
+                kind="oracle",
+                sample=f"{n} steps of the {wl.name} workload from its seeded field "
+                       "(single-threaded FP64 C oracle, one core)")
 
 
 def main(argv=None) -> int:
@@ -140,21 +138,25 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="moving")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_kahan", "fp64"])
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tuned", action="store_true", help="library default launch shape")
+    ap.add_argument("--set", action="append", default=[], help="launch override key=value")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has "
+              "no multi-GPU path", file=sys.stderr)
         return 2
 
     import numpy as np
     import torch
 
     from paper_1310_4218_amd import workloads as W
+    from paper_1310_4218_amd.autotune import tuned_params
     from paper_1310_4218_amd.grid import Grid
 
     if not torch.cuda.is_available():
@@ -163,42 +165,46 @@ def main(argv=None) -> int:
     wl = W.get(args.workload)
     R = wl.rebalance_every or 10
     S = wl.nslots
-    log(f"bench: {wl.name} steps={args.steps} warmup={args.warmup} R={R} S={S}")
+    params = {} if args.no_tuned else tuned_params(args.workload, args.precision)
+    for kv in args.set:
+        k, v = kv.split("=")
+        params[k] = int(v)
+    params["precision"] = args.precision
+    log(f"bench: {wl.name} steps={args.steps} warmup={args.warmup} R={R} S={S} params={params}")
 
-    bal = run_balanced(Grid, wl, args.steps, args.warmup, R, wl.strategy, wl.threshold, torch)
-    log(f"balanced: {bal['wall'] * 1e3 / args.steps:.4f} ms/step, kernel {bal['kernel_s'] * 1e3 / args.steps:.4f} ms/step")
+    bal = run_balanced(Grid, wl, args.steps, args.warmup, R, params, torch)
+    log(f"balanced: {bal['wall'] * 1e3 / args.steps:.4f} ms/step, "
+        f"kernel {bal['kernel_s'] * 1e6 / args.steps:.2f} us/step")
     plain = None
     if not args.no_plain:
-        ps = args.plain_steps or args.steps
-        plain = run_plain(Grid, wl, ps, max(1, args.warmup // 2), torch)
-        plain["steps"] = ps
+        ps = args.plain_steps or min(args.steps, 100)
+        plain = run_plain(Grid, wl, ps, max(1, args.warmup // 4), params, torch)
         log(f"plain: {plain['wall'] * 1e3 / ps:.4f} ms/step")
 
-    value = wl.ncells * args.steps / bal["wall"]
-    # imbalance over the timed windows (the first window ran on the map of the warm-up)
-    import oracle  # noqa: F401  (only for the CPU baseline below)
-    from paper_1310_4218_amd._abi import balance_host  # host balancer = the library's own
-
-    lam_bal = float(np.mean([l[0] for l in bal["lam"]]))
-    block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)])
+    cells = wl.ncells * wl.nfields
+    value = cells * args.steps / bal["wall"]
+    plain_value = cells * plain["steps"] / plain["wall"] if plain else None
 
     def lam_of(w, m):
         L = np.bincount(m, weights=w, minlength=S)
         return float(L.max() / (w.sum() / S))
 
-    lam_plain = float(np.mean([lam_of(w, block) for w in bal["loads"]]))
-    lam_star = float(np.mean([max(1.0, S * w.max() / w.sum()) for w in bal["loads"]]))
+    block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)])
+    loads = [w for w, _, _ in bal["wins"]]
+    lam_bal = float(np.mean([lam[0] for _, _, lam in bal["wins"]]))   # map in force vs its window
+    lam_plain = float(np.mean([lam_of(w, block) for w in loads]))
+    lam_star = float(np.mean([max(1.0, S * w.max() / w.sum()) for w in loads]))
     busy = bal["busy"]
     lam_wg = float(busy.max() / busy.mean()) if busy.mean() > 0 else None
 
-    elem = 8 if False else 4
-    bytes_per_step = 2 * elem * wl.ncells * wl.nfields
+    elem = 8 if args.precision == "fp64" else 4
+    bytes_per_step = 2 * elem * cells
     kernel_step_s = bal["kernel_s"] / args.steps
     achieved = bytes_per_step / kernel_step_s / 1e9
-    traffic = measured_traffic(args.workload)
+    st = bal["stats"]
 
     out = {
-        "metric": "grid point-updates/s and max/avg chunk-load ratio, balanced vs plain, 1 MI355X",
+        "metric": METRIC,
         "value": value,
         "unit": "point-updates/s",
         "n_gpus": 1,
@@ -208,20 +214,21 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "fp32_kahan": "f32", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "chunks": wl.nchunks,
                    "slots": S, "rebalance_every": R, "strategy": wl.strategy,
-                   "parallelism": "single-gpu"},
+                   "launch": {k: v for k, v in params.items() if k != "precision"},
+                   "workgroups": st["nwg"], "tiles": st["ntiles"], "items": st["nitems"]},
         "balanced_vs_plain": {
             "balanced_point_updates_per_s": value,
-            "plain_point_updates_per_s": (wl.ncells * plain["steps"] / plain["wall"]) if plain else None,
-            "speedup": (value / (wl.ncells * plain["steps"] / plain["wall"])) if plain else None,
+            "plain_point_updates_per_s": plain_value,
+            "speedup": value / plain_value if plain_value else None,
             "lambda_balanced": lam_bal,
             "lambda_plain": lam_plain,
             "lambda_star": lam_star,
             "lambda_wg": lam_wg,
-            "migrations_per_rebalance": float(np.mean([l[2] for l in bal["lam"]])),
+            "migrations_per_rebalance": float(np.mean([n for _, n, _ in bal["wins"]])),
         },
         "roofline": {
             "bound": "hbm",
@@ -229,9 +236,10 @@ def main(argv=None) -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "k_persistent<float,4,0>",
-            "kernel_us_per_step_events": kernel_step_s * 1e6,
+            "traffic": measured_traffic(args.workload),
+            "kernel": "k_persistent",
+            "bytes_per_launch": bytes_per_step,
+            "us_per_launch_events": kernel_step_s * 1e6,
         },
     }
     if not args.no_cpu:

@@ -1,0 +1,148 @@
+"""Autotuner for the launch shape of the persistent step.
+
+    python -m paper_1310_4218_amd.autotune --workload moving [--precision fp32]
+
+Searches the launch parameters that do not change the method (tile_x,
+tile_y, wg_per_slot, item_split), keeping everything that defines the
+problem fixed (grid, chunks, hotspots, number of slots S).  Each candidate:
+a fresh context, a warm-up window, one load measurement and one rebalance
+with the workload's balancer (so that item splitting sees measured costs),
+then `steps` persistent steps timed with HIP events on the context's stream.
+Search is coordinate descent from the library defaults (two sweeps over the
+parameters).  The chosen configuration must give fields bit-identical to the
+library defaults after the same steps, otherwise it is rejected.
+
+Results are cached in ``tuned.json`` next to this file, keyed by GPU
+architecture, workload name and precision; ``tuned_params`` reads them.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned.json")
+
+SPACE = {
+    "tile_x": [8, 16, 32],
+    "tile_y": [4, 8, 16, 32],
+    "wg_per_slot": [1, 2, 4, 8],
+    "item_split": [0, 1, 2, 4, 8],
+}
+
+
+def _key(arch: str, workload: str, precision: str) -> str:
+    return f"{arch}/{workload}/{precision}"
+
+
+def tuned_params(workload_name: str, precision: str = "fp32", arch: str = None) -> dict:
+    """Cached launch parameters for a workload, or {} when none were tuned."""
+    if not os.path.exists(CACHE):
+        return {}
+    with open(CACHE) as f:
+        cache = json.load(f)
+    if arch is None:
+        arch = "gfx950"
+    return dict(cache.get(_key(arch, workload_name, precision), {}).get("params", {}))
+
+
+def _feasible(wl, p: dict) -> bool:
+    from . import _abi
+
+    try:
+        cfg, keep = _abi.config_from_workload(wl, **p)
+        _abi.query(cfg)
+        return True
+    except Exception:
+        return False
+
+
+def measure(wl, params: dict, precision: str, steps: int, warm: int, torch):
+    """Microseconds per persistent step for one candidate, plus its final field."""
+    from .grid import Grid
+
+    R = wl.rebalance_every or 10
+    g = Grid(wl, precision=precision, graph_steps=R, **params)
+    g.step(warm, "persistent")
+    g.measure("work")
+    g.rebalance(wl.strategy, wl.threshold)
+    g.step(R, "persistent")                 # graph capture, queue warm-up
+    s = g.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    g.step(steps, "persistent")
+    e1.record(s)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    field = g.field()
+    g.close()
+    return us, field
+
+
+def tune(wl, precision: str = "fp32", steps: int = 30, warm: int = 10, log=print) -> dict:
+    import torch
+
+    base = {}
+    t_base, f_base = measure(wl, base, precision, steps, warm, torch)
+    log(f"defaults: {t_base:.2f} us/step")
+    best, best_t = dict(base), t_base
+    tried = {json.dumps(best, sort_keys=True): t_base}
+    for sweep in range(2):
+        for name, values in SPACE.items():
+            for v in values:
+                cand = dict(best)
+                cand[name] = v
+                key = json.dumps(cand, sort_keys=True)
+                if key in tried or not _feasible(wl, cand):
+                    continue
+                try:
+                    t, f = measure(wl, cand, precision, steps, warm, torch)
+                except Exception as e:  # a shape the library rejects at init
+                    log(f"  {cand}: rejected ({e})")
+                    tried[key] = float("inf")
+                    continue
+                tried[key] = t
+                same = bool(torch.equal(f, f_base))
+                log(f"  {cand}: {t:.2f} us/step{'' if same else '  FIELDS DIFFER -> rejected'}")
+                if same and t < best_t:
+                    best, best_t = cand, t
+    return dict(params=best, us_per_step=best_t, default_us_per_step=t_base,
+                candidates=len(tried), when=time.strftime("%Y-%m-%d %H:%M:%S"))
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--workload", action="append", required=True)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warm", type=int, default=10)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from . import workloads as W
+
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = {}
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            cache = json.load(f)
+    for name in args.workload:
+        wl = W.get(name)
+        print(f"tuning {wl.name} ({args.precision}) on {arch}", flush=True)
+        res = tune(wl, args.precision, args.steps, args.warm,
+                   log=lambda *a: print(*a, flush=True))
+        print(json.dumps(res), flush=True)
+        cache[_key(arch, name, args.precision)] = res
+        with open(CACHE + ".tmp", "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(CACHE + ".tmp", CACHE)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
