@@ -145,6 +145,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tuned", action="store_true", help="library default launch shape")
     ap.add_argument("--set", action="append", default=[], help="launch override key=value")
+    ap.add_argument("--calibration-copy", type=float, default=0.0, metavar="MIB",
+                    help="after the run, copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -242,6 +244,13 @@ def main(argv=None) -> int:
             "us_per_launch_events": kernel_step_s * 1e6,
         },
     }
+    if args.calibration_copy > 0:
+        n = int(args.calibration_copy * 2 ** 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = n
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)

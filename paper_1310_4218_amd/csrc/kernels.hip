@@ -151,6 +151,30 @@ __device__ double block_sum(double v, double* red) {
     return s;
 }
 
+// Two sums at once (same fixed order); results valid in thread 0.  Uses red[0..2*nwaves).
+__device__ void block_sum2(double& a, double& b, double* red) {
+    const int wave = threadIdx.x / kWave;
+    const int nwaves = (blockDim.x + kWave - 1) / kWave;
+    const int active = min(kWave, static_cast<int>(blockDim.x) - wave * kWave);
+    a = wave_sum(a, active);
+    b = wave_sum(b, active);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[wave] = a;
+        red[kMaxBlock / kWave + wave] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int w = 0; w < nwaves; ++w) {
+            sa += red[w];
+            sb += red[kMaxBlock / kWave + w];
+        }
+        a = sa;
+        b = sb;
+    }
+    __syncthreads();
+}
+
 // ---- one work item ----------------------------------------------------------------
 struct ItemOut {
     double checksum;  // sum of the item's outputs over all fields (valid in thread 0)
@@ -282,9 +306,10 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
             if (r + 1 < h) row(r + 1, B0, B1, A0, A1);
         }
     }
+    block_sum2(chk, work, red);
     ItemOut o;
-    o.checksum = block_sum(chk, red);
-    o.work = block_sum(work, red);
+    o.checksum = chk;
+    o.work = work;
     o.chunk = d.chunk;
     return o;
 }
@@ -410,7 +435,7 @@ template <typename T, int V, int KAHAN>
 __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
-    __shared__ double red[kMaxBlock / kWave];
+    __shared__ double red[2 * kMaxBlock / kWave];
     __shared__ ItemDesc s_desc;
     __shared__ int s_last;
 
@@ -472,7 +497,7 @@ template <typename T, int V, int KAHAN>
 __global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
-    __shared__ double red[kMaxBlock / kWave];
+    __shared__ double red[2 * kMaxBlock / kWave];
 
     const StepInfo si = step_info(a);
     const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);

@@ -1,0 +1,102 @@
+"""HBM traffic of the persistent step kernel from two rocprofv3 counter runs.
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- python3 bench.py --workload W \
+        --no-cpu --no-plain --steps S --warmup 10 --calibration-copy 512
+    rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- python3 bench.py ...same...
+    python -m paper_1310_4218_amd.traffic --fetch OUT/fetch --write OUT/write --workload W \
+        --copy-mib 512
+
+Both counters are reported in KiB per dispatch.  Each is scaled by what the
+same counter reads for the plain device copy of known size that bench.py runs
+in the same process (--calibration-copy), so the result is in bytes as the
+counter sees them for a kernel whose true traffic is known.  Writes
+profiles/traffic_<workload>.json (per-launch bytes, the scale factors, and a
+hash of the kernel source so that stale numbers are not reported).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "lbgrid_internal.h"):
+        with open(os.path.join(ROOT, "paper_1310_4218_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_counter(outdir: str, counter: str):
+    """{kernel name: [value per dispatch]} from rocprofv3 counter CSVs under outdir."""
+    per = {}
+    files = glob.glob(os.path.join(outdir, "**", "*counter_collection*.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection CSV under {outdir}")
+    for path in files:
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = row.get("Kernel_Name", "")
+                per.setdefault(name, []).append(float(row["Counter_Value"]))
+    return per
+
+
+def pick(per: dict, needle) -> list:
+    vals = []
+    for name, v in per.items():
+        if any(n in name.lower() for n in needle):
+            vals.extend(v)
+    return vals
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--copy-mib", type=float, required=True)
+    ap.add_argument("--command", default="", help="command lines that produced the runs")
+    args = ap.parse_args(argv)
+
+    fetch = read_counter(args.fetch, "FETCH_SIZE")
+    write = read_counter(args.write, "WRITE_SIZE")
+    kf, kw = pick(fetch, ["k_persistent"]), pick(write, ["k_persistent"])
+    cf, cw = pick(fetch, ["copy"]), pick(write, ["copy"])
+    if not kf or not kw or not cf or not cw:
+        print("missing dispatches: persistent", len(kf), len(kw), "copy", len(cf), len(cw),
+              file=sys.stderr)
+        print("kernels seen:", sorted(set(fetch) | set(write)), file=sys.stderr)
+        return 1
+    copy_bytes = args.copy_mib * 2 ** 20
+    # the copy reads and writes copy_bytes; the counters report KiB per dispatch
+    f_scale = copy_bytes / (max(cf) * 1024.0)
+    w_scale = copy_bytes / (max(cw) * 1024.0)
+    mean = lambda v: sum(v) / len(v)
+    fetch_b = mean(kf) * 1024.0 * f_scale
+    write_b = mean(kw) * 1024.0 * w_scale
+    out = dict(workload=args.workload, kernel="k_persistent",
+               dispatches=dict(fetch=len(kf), write=len(kw)),
+               fetch_bytes_per_launch=fetch_b, write_bytes_per_launch=write_b,
+               hbm_bytes_per_launch=fetch_b + write_b,
+               raw_kib_per_launch=dict(fetch=mean(kf), write=mean(kw)),
+               calibration=dict(copy_bytes=copy_bytes, fetch_kib=max(cf), write_kib=max(cw),
+                                fetch_scale=f_scale, write_scale=w_scale),
+               kernel_source_hash=kernel_source_hash(), command=args.command)
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

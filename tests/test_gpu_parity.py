@@ -343,3 +343,97 @@ def test_moving_full_size_fp32_step_error():
     err = rel_err(q, ref)
     bad = int((np.abs(q - ref) > TOL * np.abs(ref).max()).sum())
     say(f"{T} steps: rel err {err:.3e}, {bad} of {q.size} cells beyond 1e-5")
+
+
+# ------------------------------------------------------------------ full sizes, sampled outputs
+def _launch(name, precision):
+    """The benchmark's launch parameters for a workload (tile shapes dropped where the
+    wider FP64 rows would not fit the LDS ring)."""
+    from paper_1310_4218_amd import _abi
+    from paper_1310_4218_amd.autotune import tuned_params
+    p = tuned_params(name, "fp32")
+    p.pop("precision", None)
+    p["precision"] = precision
+    try:
+        cfg, keep = _abi.config_from_workload(W.get(name), **p)
+        _abi.query(cfg)
+    except _abi.LbError:
+        p.pop("tile_x", None)
+        p.pop("tile_y", None)
+    return p
+
+
+def _windows(wl, T, w=16):
+    """Sample windows (origin x, origin y) of w x w columns: on a hotspot, near the
+    periodic corner, and two arbitrary places."""
+    hx, hy = wl.hot[0][0], wl.hot[0][1]
+    return [(hx - w // 2, hy - w // 2), (wl.nx - w // 2, wl.ny - w // 2),
+            (wl.nx // 3, 5), (7, wl.ny // 2 + 3)]
+
+
+def _oracle_loads(wl, t_from, t_to):
+    acc = np.zeros(wl.nchunks)
+    for t in range(t_from, t_to):
+        k = oracle.kfield(wl.nx, wl.ny, wl.hot, wl.t0 + t, wl.sigma, wl.kmin, wl.kmax)
+        acc += oracle.chunk_work(k, wl.nz, wl.xsplit, wl.ysplit, wl.alpha_work)
+    return acc * wl.nfields
+
+
+def _gpu_window(field_dev, ox, oy, w):
+    ny, nx, _ = field_dev.shape
+    ys = torch.arange(oy, oy + w, device=field_dev.device) % ny
+    xs = torch.arange(ox, ox + w, device=field_dev.device) % nx
+    return field_dev[ys][:, xs].double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["sweep1024", "precision", "large"])
+def test_full_size_fp64_sampled_windows(name):
+    """Full-size grids in the benchmark's launch configuration, FP64: measured loads and the
+    installed map equal the oracle's; after 12 steps (one rebalance included) sampled
+    16x16-column windows equal the windowed oracle bit for bit."""
+    wl = W.get(name)
+    T, R = 12, 10
+    say(name, "fp64 full size")
+    g = Grid(wl, **_launch(name, "fp64"))
+    g.step(R)
+    w = g.measure("work")
+    wref = _oracle_loads(wl, 0, R)
+    np.testing.assert_array_equal(w, wref)
+    m, _, _ = g.rebalance(wl.strategy, wl.threshold)
+    old = oracle.block_map(wl.nchunks, wl.nslots)
+    mref = {"greedy": lambda: oracle.greedy(wref, wl.nslots),
+            "refine": lambda: oracle.refine(wref, old, wl.nslots, wl.threshold)}[wl.strategy]()
+    np.testing.assert_array_equal(m, mref)
+    g.step(T - R)
+    np.testing.assert_array_equal(g.measure("work"), _oracle_loads(wl, R, T))
+    q = g.field(device="cuda")
+    for ox, oy in _windows(wl, T):
+        q0 = oracle.init_window(wl, ox - T, oy - T, 16 + 2 * T, 16 + 2 * T)
+        ref = oracle.run_window(wl, q0, ox - T, oy - T, T)[T:T + 16, T:T + 16]
+        np.testing.assert_array_equal(_gpu_window(q, ox, oy, 16), ref)
+    assert np.all(g.visits() == T)
+
+
+@pytest.mark.parametrize("name", ["precision", "large"])
+def test_full_size_fp32_step_error_windows(name):
+    """FP32 at full size: one step from the GPU's own state agrees with the oracle's FP64
+    step from that state within 1e-5 on sampled windows (relative to the field's max)."""
+    wl = W.get(name)
+    g = Grid(wl, **_launch(name, "fp32"))
+    g.step(10)
+    g.measure("work")
+    g.rebalance(wl.strategy, wl.threshold)
+    g.step(3)
+    before = g.field(device="cuda")
+    g.step(1)
+    after = g.field(device="cuda")
+    scale = float(after.abs().max())
+    t = g.stats()["steps"] - 1
+    worst = 0.0
+    for ox, oy in _windows(wl, 1):
+        q0 = _gpu_window(before, ox - 1, oy - 1, 18)
+        ref = oracle.run_window(wl, q0, ox - 1, oy - 1, 1, t0=wl.t0 + t)[1:17, 1:17]
+        got = _gpu_window(after, ox, oy, 16)
+        worst = max(worst, float(np.max(np.abs(got - ref))) / scale)
+    say(name, "one-step error", worst)
+    assert worst <= TOL
