@@ -99,7 +99,11 @@ typedef struct {
     int32_t kmin, kmax;      /* 0 <= kmin <= kmax: column-loop trip range      */
     int32_t alpha_work;      /* work units per cell for the stencil (32)       */
     int32_t nslots;          /* S, the balancer's processors (256)            */
-    int32_t wg_per_slot;     /* G workgroups per slot; 0 = max(1, 2048/S)     */
+    int32_t nqueues;         /* Q work queues of the persistent kernel; slot s
+                                feeds queue s mod Q; 0 = 8 when S is a
+                                multiple of 8 (one queue per XCD), else S     */
+    int32_t wg_per_queue;    /* G workgroups per queue; 0 = as many as can be
+                                resident on the device, divided by Q          */
     int32_t tile_x, tile_y;  /* columns per work item along x, y; 0 = 16, 16   */
     int32_t steal;           /* 1: a workgroup whose slot queue is empty takes
                                 items from other slots (default 1)            */
@@ -126,7 +130,8 @@ typedef struct {
     int32_t nrows;           /* tile rows (the finest possible items)         */
     int32_t nitems;          /* work items of the installed plan              */
     int32_t nslots;          /* S                                             */
-    int32_t nwg;             /* workgroups of the persistent launch (S*G)     */
+    int32_t nqueues;         /* Q                                             */
+    int32_t nwg;             /* workgroups of the persistent launch (Q*G)     */
     int32_t block;           /* threads per workgroup                         */
     int32_t tile_x, tile_y;
     double clock_hz;         /* rate of the in-kernel wall clock              */

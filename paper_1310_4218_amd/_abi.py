@@ -44,7 +44,7 @@ class LbConfig(C.Structure):
         ("hvx", C.c_int32 * LB_MAX_HOT), ("hvy", C.c_int32 * LB_MAX_HOT),
         ("sigma", C.c_double),
         ("kmin", C.c_int32), ("kmax", C.c_int32), ("alpha_work", C.c_int32),
-        ("nslots", C.c_int32), ("wg_per_slot", C.c_int32),
+        ("nslots", C.c_int32), ("nqueues", C.c_int32), ("wg_per_queue", C.c_int32),
         ("tile_x", C.c_int32), ("tile_y", C.c_int32),
         ("steal", C.c_int32), ("graph_steps", C.c_int32), ("item_split", C.c_int32),
         ("t0", C.c_int64), ("seed", C.c_uint64),
@@ -58,7 +58,8 @@ class LbBuffers(C.Structure):
 class LbStats(C.Structure):
     _fields_ = [
         ("steps", C.c_int64), ("nchunks", C.c_int32), ("ntiles", C.c_int32),
-        ("nrows", C.c_int32), ("nitems", C.c_int32), ("nslots", C.c_int32), ("nwg", C.c_int32), ("block", C.c_int32),
+        ("nrows", C.c_int32), ("nitems", C.c_int32), ("nslots", C.c_int32),
+        ("nqueues", C.c_int32), ("nwg", C.c_int32), ("block", C.c_int32),
         ("tile_x", C.c_int32), ("tile_y", C.c_int32),
         ("clock_hz", C.c_double), ("last_checksum", C.c_double),
         ("measured_steps", C.c_int64),
@@ -130,7 +131,7 @@ def ptr(a: np.ndarray, ct):
 
 def make_config(nx, ny, nz, px, py, xsplit=None, ysplit=None, *, nfields=1, precision="fp32",
                 c_center=0.4, c_nbr=0.1, eps=0.01, hot=(), sigma=8.0, kmin=1, kmax=1,
-                alpha_work=32, nslots=256, wg_per_slot=0, tile_x=0, tile_y=0, steal=1,
+                alpha_work=32, nslots=256, nqueues=0, wg_per_queue=0, tile_x=0, tile_y=0, steal=1,
                 graph_steps=10, item_split=2, t0=0, seed=0):
     """Build an LbConfig; returns (config, keepalive) -- keep both until the call returns."""
     cfg = LbConfig()
@@ -155,7 +156,7 @@ def make_config(nx, ny, nz, px, py, xsplit=None, ysplit=None, *, nfields=1, prec
         cfg.hx0[i], cfg.hy0[i], cfg.hvx[i], cfg.hvy[i] = x0, y0, vx, vy
     cfg.sigma, cfg.kmin, cfg.kmax = float(sigma), kmin, kmax
     cfg.alpha_work = alpha_work
-    cfg.nslots, cfg.wg_per_slot = nslots, wg_per_slot
+    cfg.nslots, cfg.nqueues, cfg.wg_per_queue = nslots, nqueues, wg_per_queue
     cfg.tile_x, cfg.tile_y = tile_x, tile_y
     cfg.steal, cfg.graph_steps, cfg.item_split = steal, graph_steps, item_split
     cfg.t0, cfg.seed = t0, seed

@@ -3,8 +3,8 @@
     python -m paper_1310_4218_amd.autotune --workload moving [--precision fp32]
 
 Searches the launch parameters that do not change the method (tile_x,
-tile_y, wg_per_slot, item_split), keeping everything that defines the
-problem fixed (grid, chunks, hotspots, number of slots S).  Each candidate:
+tile_y, nqueues, wg_per_queue, item_split), keeping everything that defines
+the problem fixed (grid, chunks, hotspots, number of balancer slots S).  Each candidate:
 a fresh context, a warm-up window, one load measurement and one rebalance
 with the workload's balancer (so that item splitting sees measured costs),
 then `steps` persistent steps timed with HIP events on the context's stream.
@@ -29,7 +29,8 @@ CACHE = os.path.join(HERE, "tuned.json")
 SPACE = {
     "tile_x": [8, 16, 32],
     "tile_y": [4, 8, 16, 32],
-    "wg_per_slot": [1, 2, 4, 8],
+    "nqueues": [1, 8, 32, 256],
+    "wg_per_queue": [0],          # 0: fill the device (resident workgroups / queues)
     "item_split": [0, 1, 2, 4, 8],
 }
 

@@ -3,9 +3,10 @@
 // Section VI Fig. 4 of the paper) with in-kernel per-chunk load measurement
 // (Section V), in two launch forms:
 //   - plain: one launch per chunk over that chunk's items, chunks in id order;
-//   - persistent: one launch per step whose workgroups claim items from
-//     per-slot queues (slots play the paper's processors) with atomic heads,
-//     optionally taking work from other slots once their own queue is empty.
+//   - persistent: one launch per step whose workgroups claim items from work
+//     queues with atomic heads (the chunks of balancer slot s, the paper's
+//     processors, feed queue s mod Q), optionally taking work from other
+//     queues once their own is empty.
 //
 // Data layout: field[((f*ny + y)*nx + x)*nz + z] (z fastest).  Chunks are cut
 // into tiles of up to TX x TY columns; a work item is a range of rows of one
@@ -359,57 +360,68 @@ __device__ void finish_step(const DevArgs& a, uint64_t step, double* red) {
 
 // ---- claiming work ----------------------------------------------------------------
 // Workgroups are dispatched to the eight XCDs round-robin (workgroup w runs on
-// XCD w % 8).  When S is a multiple of 8, slot s is served only by workgroups
-// on XCD s % 8, so the items of a chunk share that XCD's L2.  Every slot has
+// XCD w % 8).  When Q is a multiple of 8, queue q is served only by workgroups
+// on XCD q % 8, so the items of a chunk share that XCD's L2.  Every queue has
 // exactly G workgroups, with ranks 0..G-1.
-__device__ __forceinline__ int home_slot(const DevArgs& a, int wg) {
-    if (a.xcd_slots) {
-        const int per_xcd = a.nslots / 8;
+__device__ __forceinline__ int home_queue(const DevArgs& a, int wg) {
+    if (a.xcd_queues) {
+        const int per_xcd = a.nqueues / 8;
         return (wg & 7) + 8 * ((wg >> 3) % per_xcd);
     }
-    return wg % a.nslots;
+    return wg % a.nqueues;
 }
-__device__ __forceinline__ int slot_rank(const DevArgs& a, int wg) {
-    if (a.xcd_slots) return (wg >> 3) / (a.nslots / 8);
-    return wg / a.nslots;
+__device__ __forceinline__ int queue_rank(const DevArgs& a, int wg) {
+    if (a.xcd_queues) return (wg >> 3) / (a.nqueues / 8);
+    return wg / a.nqueues;
 }
 
-// Queue index of a claimed item of slot s, or -1 if its queue is empty.
-__device__ __forceinline__ int try_claim(const DevArgs& a, int s) {
-    const int beg = a.seg[s];
-    const int n = a.seg[s + 1] - beg;
-    if (__hip_atomic_load(&a.heads[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) return -1;
-    const int i = atomicAdd(&a.heads[s], 1);
+// Index (into the queue array) of a claimed item of queue q, or -1 if it is empty.
+__device__ __forceinline__ int try_claim(const DevArgs& a, int q) {
+    const int beg = a.seg[q];
+    const int n = a.seg[q + 1] - beg;
+    if (__hip_atomic_load(&a.heads[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) return -1;
+    const int i = atomicAdd(&a.heads[q], 1);
     return i < n ? beg + i : -1;
 }
 
 // Called by all lanes of wave 0.  Home queue first; then, if stealing is on,
-// scan the other queues 64 at a time (same-XCD slots first) and claim from
-// the first one with work left.  Every failed claim means that queue is empty
-// for good (heads only grow), so the scan ends after at most S failures.
+// scan the other queues 64 at a time (same-XCD queues first) and claim from
+// the one with the most work left among the first 64 with any.  Every failed
+// claim means that queue is empty for good (heads only grow), so the scan
+// ends after at most Q failures.
 __device__ int claim(const DevArgs& a, int home) {
     const int lane = threadIdx.x & (kWave - 1);
     int qi = -1;
     if (lane == 0) qi = try_claim(a, home);
     qi = __shfl(qi, 0, kWave);
     if (qi >= 0 || !a.steal) return qi;
-    const int S = a.nslots;
-    const int per_xcd = a.xcd_slots ? S / 8 : S;
+    const int Q = a.nqueues;
+    const int per_xcd = a.xcd_queues ? Q / 8 : Q;
     int base = 0;
-    while (base < S) {
+    while (base < Q) {
         const int j = base + lane;
-        int s = -1, rem = 0;
-        if (j < S && lane < static_cast<int>(blockDim.x)) {
-            s = a.xcd_slots ? (home + 8 * (j % per_xcd) + j / per_xcd) % S : (home + j) % S;
-            rem = (a.seg[s + 1] - a.seg[s]) -
-                  __hip_atomic_load(&a.heads[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int q = -1, rem = 0;
+        if (j < Q && lane < static_cast<int>(blockDim.x)) {
+            q = a.xcd_queues ? (home + 8 * (j % per_xcd) + j / per_xcd) % Q : (home + j) % Q;
+            rem = (a.seg[q + 1] - a.seg[q]) -
+                  __hip_atomic_load(&a.heads[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        const uint64_t mask = __ballot(rem > 0);
-        if (mask == 0) {
+        if (__ballot(rem > 0) == 0) {
             base += kWave;
             continue;
         }
-        const int victim = __shfl(s, __ffsll(static_cast<unsigned long long>(mask)) - 1, kWave);
+        // the lane with the most remaining work (lowest lane on ties) picks the victim
+        int best = rem, who = lane;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const int ob = __shfl_xor(best, o, kWave);
+            const int ow = __shfl_xor(who, o, kWave);
+            if (ob > best || (ob == best && ow < who)) {
+                best = ob;
+                who = ow;
+            }
+        }
+        const int victim = __shfl(q, who, kWave);
         int got = -1;
         if (lane == 0) got = try_claim(a, victim);
         got = __shfl(got, 0, kWave);
@@ -425,10 +437,10 @@ __device__ __forceinline__ ItemDesc no_item() {
 }
 
 // ---- kernels ----------------------------------------------------------------------
-// One launch per step.  Workgroup (slot s, rank j) starts with item j of its
-// slot's queue (no atomic), then claims the next item of its slot at the start
-// of each item (the claim and the next descriptor load overlap the item's own
-// work); once its slot is drained it claims through `claim` (stealing).  The
+// One launch per step.  Workgroup (queue q, rank j) starts with item j of its
+// queue (no atomic), then claims the next item of its queue at the start of
+// each item (the claim and the next descriptor load overlap the item's own
+// work); once its queue is drained it claims through `claim` (stealing).  The
 // last workgroup to finish resets the heads, sums the checksum partials and
 // advances the step counter.
 template <typename T, int V, int KAHAN>
@@ -442,8 +454,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     const StepInfo si = step_info(a);
     const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);
     T* dst = static_cast<T*>((si.step & 1) ? a.field0 : a.field1);
-    const int home = home_slot(a, blockIdx.x);
-    const int rank = slot_rank(a, blockIdx.x);
+    const int home = home_queue(a, blockIdx.x);
+    const int rank = queue_rank(a, blockIdx.x);
     const int hbeg = a.seg[home];
     const int hn = a.seg[home + 1] - hbeg;
     double busy = 0.0;
@@ -488,7 +500,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     __syncthreads();
     if (s_last) {
         __threadfence();
-        for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) a.heads[s] = a.head0;
+        for (int q = threadIdx.x; q < a.nqueues; q += blockDim.x) a.heads[q] = a.head0;
         finish_step(a, si.step, red);
     }
 }
@@ -538,7 +550,7 @@ __global__ void k_zero(uint32_t* p, size_t nwords) {
 }
 
 __global__ void k_reset_control(DevArgs a) {
-    for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) a.heads[s] = a.head0;
+    for (int q = threadIdx.x; q < a.nqueues; q += blockDim.x) a.heads[q] = a.head0;
     if (threadIdx.x == 0) {
         a.ctrl->done = 0;
         a.ctrl->step = 0;
@@ -598,6 +610,14 @@ PlainFn pick_plain(int prec, int vec) {
 }
 
 }  // namespace
+
+int persistent_occupancy(int prec, int vec, int block, size_t lds) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(pick_persistent(prec, vec)), block, lds) != hipSuccess)
+        return -1;
+    return n;
+}
 
 int launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, size_t lds,
                       void* stream) {

@@ -41,9 +41,9 @@ struct DevArgs {
     const int32_t* ktab;
     const ItemDesc* items;     // items in chunk order
     const int32_t* item_off;   // C + 1: items of chunk c are [item_off[c], item_off[c+1])
-    const ItemDesc* queue;     // the same items grouped by slot, each slot's in cost order
-    const int32_t* seg;        // S + 1 offsets into queue
-    int32_t* heads;            // S claim counters; each launch starts them at head0
+    const ItemDesc* queue;     // the same items grouped by queue, each queue's in cost order
+    const int32_t* seg;        // Q + 1 offsets into queue
+    int32_t* heads;            // Q claim counters; each launch starts them at head0
     Ctrl* ctrl;
     double* loads_work;        // C
     double* loads_time;        // C
@@ -53,14 +53,14 @@ struct DevArgs {
     int32_t* visits;           // per tile row: times it was computed
     int64_t ncells;            // cells per field
     int32_t nx, ny, nz, nfields;
-    int32_t nslots, nwg, steal;
-    int32_t head0;             // G: the first G items of a slot go one to each of its workgroups
+    int32_t nqueues, nwg, steal;
+    int32_t head0;             // G: the first G items of a queue go one to each of its workgroups
     int32_t tile_x;            // TX; block = TX * nz / V threads
     int32_t r2cut;
     int32_t kmin;
     int32_t alpha;
     int32_t nhot;
-    int32_t xcd_slots;         // 1: slot s is served by workgroups on XCD s % 8
+    int32_t xcd_queues;        // 1: queue q is served by workgroups on XCD q % 8
     int32_t hx0[kMaxHot], hy0[kMaxHot], hvx[kMaxHot], hvy[kMaxHot];
     int64_t t0;
     double cc, cn, eps;
@@ -77,6 +77,7 @@ int  launch_zero(void* p, size_t bytes, void* stream);
 int  launch_field_sum(const void* q, int prec, int64_t n, double* partial, double* out,
                       void* stream);
 int  launch_reset_control(const DevArgs& a, void* stream);
+int  persistent_occupancy(int prec, int vec, int block, size_t lds);  // resident workgroups per CU
 
 // Host balancer (balance.cpp).  Return 0 on success, -1 on bad arguments.
 enum Strategy { kGreedy = 0, kRefine = 1, kRefineSwap = 2 };

@@ -39,7 +39,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Everything lb_query / lb_grid_init derive from a configuration.
 struct Plan {
-    int32_t nx = 0, ny = 0, nz = 0, nfields = 1, px = 0, py = 0, C = 0, S = 0, G = 0, nwg = 0;
+    int32_t nx = 0, ny = 0, nz = 0, nfields = 1, px = 0, py = 0, C = 0, S = 0, Q = 0, G = 0, nwg = 0;
+    int32_t nwg_cap = 0;    // workgroup counters sized for this many
     int32_t prec = 0, vec = 1, elem = 4, TX = 16, TY = 16, block = 0, ntiles = 0;
     int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
     int32_t r2cut = 0;
@@ -82,7 +83,8 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->nhot > 0 && c->kmax > c->kmin && !(c->sigma > 0.0 && c->sigma <= 1e5)) return bad("sigma must be in (0, 1e5]");
     if (c->alpha_work < 0) return bad("alpha_work must be >= 0");
     if (c->nslots < 1 || c->nslots > 65536) return bad("nslots must be in [1, 65536]");
-    if (c->wg_per_slot < 0) return bad("wg_per_slot must be >= 0");
+    if (c->nqueues < 0 || c->nqueues > c->nslots) return bad("nqueues must be in [0, nslots]");
+    if (c->wg_per_queue < 0) return bad("wg_per_queue must be >= 0");
     if (c->tile_x < 0 || c->tile_y < 0) return bad("tile sizes must be >= 0");
     if (c->graph_steps < 1 || c->graph_steps > 1000) return bad("graph_steps must be in [1, 1000]");
     if (c->steal != 0 && c->steal != 1) return bad("steal must be 0 or 1");
@@ -135,10 +137,13 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.ntiles = static_cast<int32_t>(nt);
     p.nrows = static_cast<int32_t>(nr);
 
-    p.G = c->wg_per_slot > 0 ? c->wg_per_slot : std::max(1, 2048 / p.S);
-    const int64_t nwg = static_cast<int64_t>(p.S) * p.G;
-    if (nwg > 65536) return bad("nslots * wg_per_slot must be <= 65536");
+    p.Q = c->nqueues > 0 ? c->nqueues : (p.S % 8 == 0 ? 8 : p.S);
+    // G = 0: chosen at init from the kernel's occupancy (resident workgroups per CU x CUs)
+    p.G = c->wg_per_queue;
+    const int64_t nwg = static_cast<int64_t>(p.Q) * std::max(p.G, 1);
+    if (nwg > 65536) return bad("nqueues * wg_per_queue must be <= 65536");
     p.nwg = static_cast<int32_t>(nwg);
+    p.nwg_cap = p.G > 0 ? p.nwg : 65536;
 
     const int64_t cut = (c->nhot > 0) ? cost_table_cut(c->sigma, c->kmin, c->kmax) : 0;
     if (cut > (int64_t{1} << 26)) return bad("cost table too large (sigma too wide for kmax - kmin)");
@@ -151,13 +156,13 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_items = take(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
     p.off_itemoff = take(sizeof(int32_t) * (static_cast<size_t>(p.C) + 1));
     p.off_queue = take(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
-    p.off_seg = take(sizeof(int32_t) * (static_cast<size_t>(p.S) + 1));
-    p.off_heads = take(sizeof(int32_t) * static_cast<size_t>(p.S));
+    p.off_seg = take(sizeof(int32_t) * (static_cast<size_t>(p.Q) + 1));
+    p.off_heads = take(sizeof(int32_t) * static_cast<size_t>(p.Q));
     p.off_lw = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_lt = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_part = take(sizeof(double) * static_cast<size_t>(p.nrows));
     p.off_hist = take(sizeof(double) * kHistLen);
-    p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg));
+    p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg_cap));
     p.off_visits = take(sizeof(int32_t) * static_cast<size_t>(p.nrows));
     p.off_sum = take(sizeof(double) * (kSumBlocks + 1));
     p.ws_bytes = o;
@@ -306,9 +311,10 @@ int upload_plan(lb_ctx* x, const double* cost) {
     const int32_t n = static_cast<int32_t>(x->items.size());
     x->item_off[p.C] = n;
 
-    std::vector<std::vector<int32_t>> by_slot(static_cast<size_t>(p.S));
+    std::vector<std::vector<int32_t>> by_queue(static_cast<size_t>(p.Q));
     for (int32_t c = 0; c < p.C; ++c)
-        for (int32_t it = x->item_off[c]; it < x->item_off[c + 1]; ++it) by_slot[x->map[c]].push_back(it);
+        for (int32_t it = x->item_off[c]; it < x->item_off[c + 1]; ++it)
+            by_queue[x->map[c] % p.Q].push_back(it);
 
     if (x->upload_pending) {
         HIP_TRY(x, hipEventSynchronize(x->upload_done));
@@ -318,18 +324,18 @@ int upload_plan(lb_ctx* x, const double* cost) {
     ItemDesc* st_queue = st_items + p.nrows;
     int32_t* st_off = reinterpret_cast<int32_t*>(st_queue + p.nrows);
     int32_t* st_seg = st_off + p.C + 1;
-    int32_t* st_n = st_seg + p.S + 1;
+    int32_t* st_n = st_seg + p.Q + 1;
     std::memcpy(st_items, x->items.data(), sizeof(ItemDesc) * n);
     std::memcpy(st_off, x->item_off.data(), sizeof(int32_t) * x->item_off.size());
     int32_t k = 0;
-    for (int32_t s = 0; s < p.S; ++s) {
-        st_seg[s] = k;
-        auto& v = by_slot[s];
+    for (int32_t q = 0; q < p.Q; ++q) {
+        st_seg[q] = k;
+        auto& v = by_queue[q];
         std::stable_sort(v.begin(), v.end(),
                          [&](int32_t a, int32_t b) { return item_cost[a] > item_cost[b]; });
         for (int32_t it : v) st_queue[k++] = x->items[it];
     }
-    st_seg[p.S] = k;
+    st_seg[p.Q] = k;
     *st_n = n;
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_items, st_items, sizeof(ItemDesc) * n,
                               hipMemcpyHostToDevice, x->stream));
@@ -337,7 +343,7 @@ int upload_plan(lb_ctx* x, const double* cost) {
                               hipMemcpyHostToDevice, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_itemoff, st_off, sizeof(int32_t) * (p.C + 1),
                               hipMemcpyHostToDevice, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_seg, st_seg, sizeof(int32_t) * (p.S + 1),
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_seg, st_seg, sizeof(int32_t) * (p.Q + 1),
                               hipMemcpyHostToDevice, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_ctrl + offsetof(Ctrl, nitems), st_n, sizeof(int32_t),
                               hipMemcpyHostToDevice, x->stream));
@@ -406,7 +412,8 @@ void lb_config_default(lb_config* c) {
     c->kmax = 1;
     c->alpha_work = 32;
     c->nslots = 256;
-    c->wg_per_slot = 0;
+    c->nqueues = 0;
+    c->wg_per_queue = 0;
     c->tile_x = 0;
     c->tile_y = 0;
     c->steal = 1;
@@ -476,9 +483,26 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     if ((e = hipEventCreateWithFlags(&x->upload_done, hipEventDisableTiming)) != hipSuccess)
         return hip_bail(e, "hipEventCreateWithFlags");
     if ((e = hipHostMalloc(&x->staging, sizeof(ItemDesc) * 2 * static_cast<size_t>(P.nrows) +
-                                            sizeof(int32_t) * (static_cast<size_t>(P.C) + P.S + 3))) != hipSuccess)
+                                            sizeof(int32_t) * (static_cast<size_t>(P.C) + P.Q + 3))) != hipSuccess)
         return hip_bail(e, "hipHostMalloc");
 
+    if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
+        int ncu = 0;
+        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device)) != hipSuccess)
+            return hip_bail(e, "hipDeviceGetAttribute(MultiprocessorCount)");
+        const int occ = persistent_occupancy(P.prec, P.vec, P.block, P.lds);
+        if (occ < 1) {
+            fail(nullptr, LB_E_HIP, "persistent kernel occupancy query failed");
+            return bail(LB_E_HIP);
+        }
+        Plan& W = x->plan;
+        W.G = std::max(1, (occ * ncu) / W.Q);
+        W.nwg = W.Q * W.G;
+        if (W.nwg > W.nwg_cap) {
+            W.G = std::max(1, W.nwg_cap / W.Q);
+            W.nwg = W.Q * W.G;
+        }
+    }
     build_tiles(x);
     const std::vector<int32_t> ktab = build_cost_table(*cfg, P.r2cut);
 
@@ -500,13 +524,13 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.visits = reinterpret_cast<int32_t*>(x->ws + P.off_visits);
     a.ncells = P.ncells;
     a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.nfields = P.nfields;
-    a.nslots = P.S; a.nwg = P.nwg; a.steal = cfg->steal; a.head0 = P.G;
+    a.nqueues = P.Q; a.nwg = P.nwg; a.steal = cfg->steal; a.head0 = P.G;
     a.tile_x = P.TX;
     a.r2cut = P.r2cut;
     a.kmin = cfg->kmin;
     a.alpha = cfg->alpha_work;
     a.nhot = cfg->nhot;
-    a.xcd_slots = (P.S % 8 == 0 && P.nwg % 8 == 0) ? 1 : 0;
+    a.xcd_queues = (P.Q % 8 == 0 && P.nwg % 8 == 0) ? 1 : 0;
     for (int h = 0; h < kMaxHot; ++h) {
         a.hx0[h] = cfg->hx0[h]; a.hy0[h] = cfg->hy0[h];
         a.hvx[h] = cfg->hvx[h]; a.hvy[h] = cfg->hvy[h];
@@ -710,6 +734,7 @@ int lb_stats(lb_ctx* x, lb_stats_t* out) {
     out->nrows = p.nrows;
     out->nitems = static_cast<int32_t>(x->items.size());
     out->nslots = p.S;
+    out->nqueues = p.Q;
     out->nwg = p.nwg;
     out->block = p.block;
     out->tile_x = p.TX;

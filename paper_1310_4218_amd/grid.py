@@ -19,7 +19,7 @@ class Grid:
     """One over-decomposed grid on a GPU.
 
     ``wl`` is a :class:`paper_1310_4218_amd.workloads.Workload`; keyword
-    overrides go to the library configuration (precision, nslots, wg_per_slot,
+    overrides go to the library configuration (precision, nslots, nqueues, wg_per_queue,
     tile_x, tile_y, steal, graph_steps, ...).  ``init_field`` (optional) is a
     host or device array of nfields*ny*nx*nz values in the field precision.
     """
@@ -68,6 +68,7 @@ class Grid:
         st = self.stats()
         self.nchunks, self.ntiles, self.nslots, self.nwg = (st["nchunks"], st["ntiles"],
                                                             st["nslots"], st["nwg"])
+        self.nqueues = st["nqueues"]
         self.nrows = st["nrows"]
 
     # ---- lifecycle -------------------------------------------------------

@@ -58,7 +58,7 @@ def test_query_sizes(lib):
     ("nx", 0, "nx"), ("nz", 0, "nz"), ("px", 65, "px"), ("precision", 7, "precision"),
     ("nslots", 0, "nslots"), ("kmax", 0, "kmin"), ("nhot", 5, "nhot"), ("graph_steps", 0, "graph"),
     ("steal", 2, "steal"), ("nfields", 0, "nfields"), ("sigma", -1.0, "sigma"),
-    ("tile_x", 2000, "1024"), ("alpha_work", -1, "alpha"), ("wg_per_slot", 100000, "65536"),
+    ("tile_x", 2000, "1024"), ("alpha_work", -1, "alpha"), ("wg_per_queue", 100000, "65536"),
 ])
 def test_query_rejects_bad_config(lib, field, value, msg):
     cfg, keep = _abi.config_from_workload(W.small())

@@ -127,8 +127,9 @@ def test_launch_forms_bit_identical():
 
 
 @pytest.mark.parametrize("over", [
-    dict(nslots=1, wg_per_slot=8), dict(nslots=3, wg_per_slot=2, steal=0),
-    dict(nslots=16, wg_per_slot=1, steal=1), dict(nslots=8, wg_per_slot=4, steal=0),
+    dict(nslots=1, wg_per_queue=8), dict(nslots=3, nqueues=3, wg_per_queue=2, steal=0),
+    dict(nslots=16, nqueues=16, wg_per_queue=1, steal=1), dict(nslots=8, nqueues=8, wg_per_queue=4, steal=0),
+    dict(nslots=16, nqueues=4, wg_per_queue=3), dict(nslots=16, nqueues=8),
     dict(tile_x=4, tile_y=3), dict(tile_x=7, tile_y=5, nslots=2), dict(tile_x=16, tile_y=1),
 ])
 def test_schedule_invariance(over):
@@ -160,7 +161,7 @@ def test_split_items_bit_identical():
     wl = mk(64, 48, 16, 4, 3, kmax=150, sigma=6.0, split="dirichlet", steps=6, nslots=4)
     _, base, wb = run_gpu(wl, 6, "plain")
     for split in (1, 4, 64):
-        g = Grid(wl, item_split=split, wg_per_slot=4)
+        g = Grid(wl, item_split=split, wg_per_queue=4)
         g.step(2)
         g.measure("work")
         g.rebalance("greedy")
@@ -272,7 +273,7 @@ def test_measure_rebalance_map_parity():
 
 def test_time_loads_and_busy_counters():
     wl = W.small()
-    g = Grid(wl, nslots=4, wg_per_slot=8)
+    g = Grid(wl, nslots=4, wg_per_queue=8)
     g.step(5)
     t = g.measure("time", reset=False)
     w = g.measure("work", reset=False)
