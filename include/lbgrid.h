@@ -109,8 +109,11 @@ typedef struct {
                                 items from other slots (default 1)            */
     int32_t graph_steps;     /* persistent steps per captured graph (10)      */
     int32_t item_split;      /* after a rebalance, tiles whose measured cost
-                                exceeds W/(S*G*item_split) are cut into row
+                                exceeds W/(Q*G*item_split) are cut into row
                                 ranges; 0 = never (2)                          */
+    int32_t stage_rows;      /* rows per direct global->LDS batch (nz % 4 == 0
+                                only); 0 = 4 when nz % 4 == 0, else the
+                                register pipeline; -1 = register pipeline      */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;

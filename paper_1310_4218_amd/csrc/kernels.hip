@@ -138,10 +138,10 @@ __device__ __forceinline__ double wave_sum(double v, int active) {
 }
 
 // Sum over the block; the result is valid in thread 0.  Uses red[0..nwaves).
-__device__ double block_sum(double v, double* red) {
+__device__ double block_sum(double v, double* red, int bs) {
     const int wave = threadIdx.x / kWave;
-    const int nwaves = (blockDim.x + kWave - 1) / kWave;
-    const int active = min(kWave, static_cast<int>(blockDim.x) - wave * kWave);
+    const int nwaves = (bs + kWave - 1) / kWave;
+    const int active = min(kWave, bs - wave * kWave);
     v = wave_sum(v, active);
     if ((threadIdx.x & (kWave - 1)) == 0) red[wave] = v;
     __syncthreads();
@@ -153,10 +153,10 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // Two sums at once (same fixed order); results valid in thread 0.  Uses red[0..2*nwaves).
-__device__ void block_sum2(double& a, double& b, double* red) {
+__device__ void block_sum2(double& a, double& b, double* red, int bs) {
     const int wave = threadIdx.x / kWave;
-    const int nwaves = (blockDim.x + kWave - 1) / kWave;
-    const int active = min(kWave, static_cast<int>(blockDim.x) - wave * kWave);
+    const int nwaves = (bs + kWave - 1) / kWave;
+    const int active = min(kWave, bs - wave * kWave);
     a = wave_sum(a, active);
     b = wave_sum(b, active);
     if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -187,15 +187,36 @@ struct NoHook {
     __device__ void operator()() const {}
 };
 
+using lds_ptr = __attribute__((address_space(3))) unsigned char*;
+using glb_ptr = const __attribute__((address_space(1))) unsigned char*;
+
+// One 16-byte direct global->LDS load per active lane (gfx950 global_load_lds
+// dwordx4): lane i of the wave writes LDS bytes [wave_base + 16 i, +16).
+// wave_base must be the same in every lane of the wave.  The load counts in
+// vmcnt like any vector load (see wait_vmem).
+__device__ __forceinline__ void dma16(const void* g, lds_ptr wave_base) {
+    __builtin_amdgcn_global_load_lds((glb_ptr)g, wave_base, 16, 0, 0);
+}
+
+// s_waitcnt vmcnt(0) (gfx9 encoding: expcnt and lgkmcnt fields at their maxima,
+// i.e. not waited on).  The compiler does not track direct global->LDS loads,
+// and a workgroup barrier's fence does not wait for vector memory on this
+// target, so every barrier that publishes such loads is preceded by this.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // One item; `hook` runs in every thread right after the first prologue barrier
 // (the persistent kernel uses it to prefetch the next item's descriptor).
-template <typename T, int V, int KAHAN, typename Hook>
+// PIPE 0: rows move HBM -> registers -> LDS, two rows in flight per workgroup.
+// PIPE 1 (V = 4 only): rows move HBM -> LDS directly, a.stage_rows rows in
+// flight per workgroup, through a ring of 2*stage_rows + 2 LDS rows.
+template <typename T, int V, int KAHAN, int PIPE, typename Hook>
 __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __restrict__ src,
                                 T* __restrict__ dst, const int* hcx, const int* hcy, T* lds,
                                 double* red, Hook hook) {
     const int nz = a.nz, nx = a.nx, ny = a.ny;
     const int NQ = nz / V;
     const int TX = a.tile_x;
+    const int BS = a.block;                   // == blockDim.x, kept in a register
     const int tcol = threadIdx.x / NQ;
     const int tzq = threadIdx.x - tcol * NQ;
     const int zoff = tzq * V;
@@ -215,7 +236,19 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
     gx1 = gx1 >= nx ? gx1 - nx : gx1;
     const T cc = static_cast<T>(a.cc), cn = static_cast<T>(a.cn), eps = static_cast<T>(a.eps);
 
-    int* kbuf = reinterpret_cast<int*>(lds + kRingRows * RL);
+    const int RING = PIPE ? 2 * a.stage_rows + 2 : kRingRows;
+    int* kbuf = reinterpret_cast<int*>(lds + RING * RL);
+    auto slot = [&](int i) -> T* {              // LDS row of tile-relative row i >= -1
+        return PIPE ? lds + ((i + 1) % RING) * RL : lds + (i & (kRingRows - 1)) * RL;
+    };
+    auto fill_k = [&]() {
+        // Trip counts of the item's columns, looked up once per item; these table
+        // loads are in flight together with the first row loads.
+        for (int i = threadIdx.x; i < w * h; i += BS) {
+            const int r = i / w, c = i - r * w;
+            kbuf[r * TX + c] = column_k(a, hcx, hcy, x0 + c, y0 + r);
+        }
+    };
 
     double chk = 0.0, work = 0.0;
     for (int f = 0; f < a.nfields; ++f) {
@@ -230,7 +263,7 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
             if (has1) r1 = ld<T, V>(row + static_cast<int64_t>(gx1) * nz + zoff);
         };
         auto put = [&](int i, const Vec<T, V>& r0, const Vec<T, V>& r1) {
-            T* row = lds + (i & (kRingRows - 1)) * RL;
+            T* row = slot(i);
             if (has0) st<T, V>(row + tcol * nz + zoff, r0);
             if (has1) st<T, V>(row + (tcol + TX) * nz + zoff, r1);
         };
@@ -238,9 +271,9 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
             if (!active) return;
             const int gy = y0 + r;
             const int k = kbuf[r * TX + tcol];
-            const T* Lm = lds + ((r - 1) & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
-            const T* Lc = lds + (r & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
-            const T* Lp = lds + ((r + 1) & (kRingRows - 1)) * RL + (tcol + 1) * nz + zoff;
+            const T* Lm = slot(r - 1) + (tcol + 1) * nz + zoff;
+            const T* Lc = slot(r) + (tcol + 1) * nz + zoff;
+            const T* Lp = slot(r + 1) + (tcol + 1) * nz + zoff;
             const Vec<T, V> c = ld<T, V>(Lc);
             const Vec<T, V> xm = ld<T, V>(Lc - nz);
             const Vec<T, V> xp = ld<T, V>(Lc + nz);
@@ -273,41 +306,77 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
             if (tzq == 0) work += static_cast<double>(nz) * static_cast<double>(a.alpha + k);
         };
 
-        // Prologue: rows -1, 0, 1 go to the LDS ring, row 2 stays in registers.
-        Vec<T, V> m0, m1, c0, c1, n0, n1, A0, A1, B0, B1;
-        fetch(-1, m0, m1);
-        fetch(0, c0, c1);
-        fetch(1, n0, n1);
-        if (2 <= h) fetch(2, A0, A1);
-        if (f == 0) {
-            // Trip counts of the item's columns, looked up once per item; these
-            // table loads are in flight together with the row loads above.
-            for (int i = threadIdx.x; i < w * h; i += blockDim.x) {
-                const int r = i / w, c = i - r * w;
-                kbuf[r * TX + c] = column_k(a, hcx, hcy, x0 + c, y0 + r);
-            }
-        }
-        put(-1, m0, m1);
-        put(0, c0, c1);
-        put(1, n0, n1);
-        __syncthreads();
-        if (f == 0) hook();
-
-        // Row r: fetch row r+3 (registers), compute row r from the ring, move row
-        // r+2 (fetched one row earlier) into the ring.  Two rows stay in flight.
-        // Unrolled by two so that the register slots A and B keep fixed names.
-        auto row = [&](int r, Vec<T, V>& P0, Vec<T, V>& P1, Vec<T, V>& Q0, Vec<T, V>& Q1) {
-            if (r + 3 <= h) fetch(r + 3, Q0, Q1);
-            compute(r);
-            if (r + 2 <= h) put(r + 2, P0, P1);
+        if constexpr (PIPE == 0) {
+            // Prologue: rows -1, 0, 1 go to the LDS ring, row 2 stays in registers.
+            Vec<T, V> m0, m1, c0, c1, n0, n1, A0, A1, B0, B1;
+            fetch(-1, m0, m1);
+            fetch(0, c0, c1);
+            fetch(1, n0, n1);
+            if (2 <= h) fetch(2, A0, A1);
+            if (f == 0) fill_k();
+            put(-1, m0, m1);
+            put(0, c0, c1);
+            put(1, n0, n1);
             __syncthreads();
-        };
-        for (int r = 0; r < h; r += 2) {
-            row(r, A0, A1, B0, B1);
-            if (r + 1 < h) row(r + 1, B0, B1, A0, A1);
+            if (f == 0) hook();
+
+            // Row r: fetch row r+3 (registers), compute row r from the ring, move
+            // row r+2 (fetched one row earlier) into the ring.  Two rows stay in
+            // flight.  Unrolled by two so the register slots keep fixed names.
+            auto row = [&](int r, Vec<T, V>& P0, Vec<T, V>& P1, Vec<T, V>& Q0, Vec<T, V>& Q1) {
+                if (r + 3 <= h) fetch(r + 3, Q0, Q1);
+                compute(r);
+                if (r + 2 <= h) put(r + 2, P0, P1);
+                __syncthreads();
+            };
+            for (int r = 0; r < h; r += 2) {
+                row(r, A0, A1, B0, B1);
+                if (r + 1 < h) row(r + 1, B0, B1, A0, A1);
+            }
+        } else {
+            // Direct loads: a row of the item is (w+2) columns of nz*sizeof(T)
+            // bytes, contiguous in LDS, moved as 16-byte chunks.  Chunk c of the
+            // row is loaded by thread c mod blockDim; the lanes of one wave fill
+            // 64 consecutive chunks, so the wave's LDS base is uniform.
+            const int CPC = nz * static_cast<int>(sizeof(T)) / 16;   // chunks per column
+            const int nchunk = (w + 2) * CPC;
+            const int lane = threadIdx.x & (kWave - 1);
+            const int wave_first0 = threadIdx.x - lane;
+            const lds_ptr lds3 = (lds_ptr)lds;  // address-space cast: lds is LDS
+            auto issue = [&](int i) {
+                int gy = y0 + i;
+                gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+                const unsigned char* row = reinterpret_cast<const unsigned char*>(
+                    fsrc + static_cast<int64_t>(gy) * nx * nz);
+                const int slot_byte = static_cast<int>(
+                    reinterpret_cast<unsigned char*>(slot(i)) - reinterpret_cast<unsigned char*>(lds));
+                for (int c0 = 0; c0 < nchunk; c0 += BS) {
+                    const int first = c0 + wave_first0;     // wave-uniform
+                    if (first >= nchunk) break;
+                    const int c = c0 + threadIdx.x;
+                    const int base = __builtin_amdgcn_readfirstlane(slot_byte + first * 16);
+                    if (c < nchunk) {
+                        const int col = c / CPC, off = c - col * CPC;
+                        int gx = x0 - 1 + col;
+                        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+                        dma16(row + (static_cast<int64_t>(gx) * nz * sizeof(T) + off * 16), lds3 + base);
+                    }
+                }
+            };
+            const int B = a.stage_rows;
+            for (int i = -1; i <= min(B, h); ++i) issue(i);        // rows -1 .. B
+            if (f == 0) fill_k();
+            for (int r0 = 0; r0 < h; r0 += B) {
+                wait_vmem();            // this thread's loads of rows <= r0 + B have landed
+                __syncthreads();        // ... everyone's; and block r0 - B is done
+                if (f == 0 && r0 == 0) hook();
+                for (int i = r0 + B + 1; i <= min(r0 + 2 * B, h); ++i) issue(i);
+                for (int r = r0; r < min(r0 + B, h); ++r) compute(r);
+            }
+            __syncthreads();            // the ring is free again
         }
     }
-    block_sum2(chk, work, red);
+    block_sum2(chk, work, red, BS);
     ItemOut o;
     o.checksum = chk;
     o.work = work;
@@ -346,11 +415,11 @@ __device__ __forceinline__ void record_item(const DevArgs& a, const ItemDesc& d,
 
 // Deterministic sum of the per-item partials (item order) into the checksum ring,
 // then the step counter moves on.  Run by one whole workgroup.
-__device__ void finish_step(const DevArgs& a, uint64_t step, double* red) {
+__device__ void finish_step(const DevArgs& a, uint64_t step, double* red, int bs) {
     const int n = static_cast<int>(a.ctrl->nitems);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += a.partials[i];
-    const double total = block_sum(acc, red);
+    for (int i = threadIdx.x; i < n; i += bs) acc += a.partials[i];
+    const double total = block_sum(acc, red, bs);
     if (threadIdx.x == 0) {
         a.hist[step % kHistLen] = total;
         a.ctrl->done = 0;
@@ -401,7 +470,7 @@ __device__ int claim(const DevArgs& a, int home) {
     while (base < Q) {
         const int j = base + lane;
         int q = -1, rem = 0;
-        if (j < Q && lane < static_cast<int>(blockDim.x)) {
+        if (j < Q && lane < a.block) {
             q = a.xcd_queues ? (home + 8 * (j % per_xcd) + j / per_xcd) % Q : (home + j) % Q;
             rem = (a.seg[q + 1] - a.seg[q]) -
                   __hip_atomic_load(&a.heads[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -443,7 +512,7 @@ __device__ __forceinline__ ItemDesc no_item() {
 // work); once its queue is drained it claims through `claim` (stealing).  The
 // last workgroup to finish resets the heads, sums the checksum partials and
 // advances the step counter.
-template <typename T, int V, int KAHAN>
+template <typename T, int V, int KAHAN, int PIPE>
 __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
@@ -482,7 +551,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
             if (threadIdx.x == 0 && nidx < hn) nd = a.queue[hbeg + nidx];
         };
         const uint64_t t_start = wall_clock64();
-        const ItemOut o = process_item<T, V, KAHAN>(a, d, src, dst, si.hcx, si.hcy, lds, red, ahead);
+        const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, src, dst, si.hcx, si.hcy, lds, red, ahead);
         if (threadIdx.x == 0) {
             const double ticks = static_cast<double>(wall_clock64() - t_start);
             busy += ticks;
@@ -500,12 +569,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     __syncthreads();
     if (s_last) {
         __threadfence();
-        for (int q = threadIdx.x; q < a.nqueues; q += blockDim.x) a.heads[q] = a.head0;
-        finish_step(a, si.step, red);
+        for (int q = threadIdx.x; q < a.nqueues; q += a.block) a.heads[q] = a.head0;
+        finish_step(a, si.step, red, a.block);
     }
 }
 
-template <typename T, int V, int KAHAN>
+template <typename T, int V, int KAHAN, int PIPE>
 __global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
@@ -518,13 +587,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
     if (item >= a.item_off[chunk + 1]) return;  // grid sized for a larger plan
     const ItemDesc d = a.items[item];
     const uint64_t t_start = wall_clock64();
-    const ItemOut o = process_item<T, V, KAHAN>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
+    const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
     if (threadIdx.x == 0) record_item(a, d, o, static_cast<double>(wall_clock64() - t_start));
 }
 
 __global__ __launch_bounds__(256) void k_finish(DevArgs a) {
     __shared__ double red[256 / kWave];
-    finish_step(a, a.ctrl->step, red);
+    finish_step(a, a.ctrl->step, red, 256);
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
@@ -564,16 +633,16 @@ __global__ __launch_bounds__(256) void k_sum1(const T* q, int64_t n, double* par
     const int64_t b = blockIdx.x, B = gridDim.x;
     const int64_t lo = b * n / B, hi = (b + 1) * n / B;
     double acc = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += static_cast<double>(q[i]);
-    const double s = block_sum(acc, red);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += static_cast<double>(q[i]);
+    const double s = block_sum(acc, red, 256);
     if (threadIdx.x == 0) partial[b] = s;
 }
 
 __global__ __launch_bounds__(256) void k_sum2(const double* partial, int nb, double* out) {
     __shared__ double red[256 / kWave];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partial[i];
-    const double s = block_sum(acc, red);
+    for (int i = threadIdx.x; i < nb; i += 256) acc += partial[i];
+    const double s = block_sum(acc, red, 256);
     if (threadIdx.x == 0) *out = s;
 }
 
@@ -582,53 +651,56 @@ using PersistentFn = void (*)(DevArgs);
 using PlainFn = void (*)(DevArgs, int);
 
 template <typename T, int KAHAN>
-PersistentFn persistent_for(int vec) {
+PersistentFn persistent_for(int vec, int pipe) {
+    if (pipe) return k_persistent<T, 4, KAHAN, 1>;
     switch (vec) {
-        case 4: return k_persistent<T, 4, KAHAN>;
-        case 2: return k_persistent<T, 2, KAHAN>;
-        default: return k_persistent<T, 1, KAHAN>;
+        case 4: return k_persistent<T, 4, KAHAN, 0>;
+        case 2: return k_persistent<T, 2, KAHAN, 0>;
+        default: return k_persistent<T, 1, KAHAN, 0>;
     }
 }
 template <typename T, int KAHAN>
-PlainFn plain_for(int vec) {
+PlainFn plain_for(int vec, int pipe) {
+    if (pipe) return k_plain<T, 4, KAHAN, 1>;
     switch (vec) {
-        case 4: return k_plain<T, 4, KAHAN>;
-        case 2: return k_plain<T, 2, KAHAN>;
-        default: return k_plain<T, 1, KAHAN>;
+        case 4: return k_plain<T, 4, KAHAN, 0>;
+        case 2: return k_plain<T, 2, KAHAN, 0>;
+        default: return k_plain<T, 1, KAHAN, 0>;
     }
 }
 
-PersistentFn pick_persistent(int prec, int vec) {
-    if (prec == 2) return persistent_for<double, 0>(vec);
-    if (prec == 1) return persistent_for<float, 1>(vec);
-    return persistent_for<float, 0>(vec);
+PersistentFn pick_persistent(int prec, int vec, int pipe) {
+    if (prec == 2) return persistent_for<double, 0>(vec, pipe);
+    if (prec == 1) return persistent_for<float, 1>(vec, pipe);
+    return persistent_for<float, 0>(vec, pipe);
 }
-PlainFn pick_plain(int prec, int vec) {
-    if (prec == 2) return plain_for<double, 0>(vec);
-    if (prec == 1) return plain_for<float, 1>(vec);
-    return plain_for<float, 0>(vec);
+PlainFn pick_plain(int prec, int vec, int pipe) {
+    if (prec == 2) return plain_for<double, 0>(vec, pipe);
+    if (prec == 1) return plain_for<float, 1>(vec, pipe);
+    return plain_for<float, 0>(vec, pipe);
 }
 
 }  // namespace
 
-int persistent_occupancy(int prec, int vec, int block, size_t lds) {
+int persistent_occupancy(const DevArgs& a, int prec, int vec, int block, size_t lds) {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(pick_persistent(prec, vec)), block, lds) != hipSuccess)
+            &n, reinterpret_cast<const void*>(pick_persistent(prec, vec, a.stage_rows > 0)), block,
+            lds) != hipSuccess)
         return -1;
     return n;
 }
 
 int launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, size_t lds,
                       void* stream) {
-    hipLaunchKernelGGL(pick_persistent(prec, vec), dim3(nwg), dim3(block), lds,
+    hipLaunchKernelGGL(pick_persistent(prec, vec, a.stage_rows > 0), dim3(nwg), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a);
     return static_cast<int>(hipGetLastError());
 }
 
 int launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitems_chunk,
                        int block, size_t lds, void* stream) {
-    hipLaunchKernelGGL(pick_plain(prec, vec), dim3(nitems_chunk), dim3(block), lds,
+    hipLaunchKernelGGL(pick_plain(prec, vec, a.stage_rows > 0), dim3(nitems_chunk), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a, chunk);
     return static_cast<int>(hipGetLastError());
 }

@@ -13,7 +13,7 @@ constexpr int kHistLen = 1024;      // per-step checksum ring
 constexpr int kSumBlocks = 1024;    // first pass of the field sum
 constexpr int kRingRows = 4;        // LDS row ring of the tile kernel
 constexpr int kMaxBlock = 1024;
-constexpr size_t kMaxLds = 64 * 1024;
+constexpr size_t kMaxLds = 160 * 1024;  // gfx950: 160 KiB of LDS per CU
 
 // Device control block (first bytes of the workspace).
 struct Ctrl {
@@ -55,7 +55,9 @@ struct DevArgs {
     int32_t nx, ny, nz, nfields;
     int32_t nqueues, nwg, steal;
     int32_t head0;             // G: the first G items of a queue go one to each of its workgroups
-    int32_t tile_x;            // TX; block = TX * nz / V threads
+    int32_t tile_x;            // TX
+    int32_t block;             // threads per workgroup = TX * nz / V (== blockDim.x)
+    int32_t stage_rows;        // > 0: rows per direct global->LDS batch (V = 4 only); 0: registers
     int32_t r2cut;
     int32_t kmin;
     int32_t alpha;
@@ -77,7 +79,7 @@ int  launch_zero(void* p, size_t bytes, void* stream);
 int  launch_field_sum(const void* q, int prec, int64_t n, double* partial, double* out,
                       void* stream);
 int  launch_reset_control(const DevArgs& a, void* stream);
-int  persistent_occupancy(int prec, int vec, int block, size_t lds);  // resident workgroups per CU
+int  persistent_occupancy(const DevArgs& a, int prec, int vec, int block, size_t lds);  // per CU
 
 // Host balancer (balance.cpp).  Return 0 on success, -1 on bad arguments.
 enum Strategy { kGreedy = 0, kRefine = 1, kRefineSwap = 2 };

@@ -43,6 +43,8 @@ struct Plan {
     int32_t nwg_cap = 0;    // workgroup counters sized for this many
     int32_t prec = 0, vec = 1, elem = 4, TX = 16, TY = 16, block = 0, ntiles = 0;
     int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
+    int32_t B = 0;          // rows per direct global->LDS batch; 0 = register pipeline
+    int32_t ring = 4;       // LDS ring rows
     int32_t r2cut = 0;
     size_t lds = 0;
     int64_t ncells = 0;
@@ -89,6 +91,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->graph_steps < 1 || c->graph_steps > 1000) return bad("graph_steps must be in [1, 1000]");
     if (c->steal != 0 && c->steal != 1) return bad("steal must be 0 or 1");
     if (c->item_split < 0 || c->item_split > 64) return bad("item_split must be in [0, 64]");
+    if (c->stage_rows < -1 || c->stage_rows > 32) return bad("stage_rows must be in [-1, 32]");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
     p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
@@ -107,21 +110,26 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (!strictly_increasing(p.ys, p.ny)) return bad("ysplit must rise strictly from 0 to ny");
 
     const int NQ = p.nz / p.vec;
-    const size_t row_elems_per_col = static_cast<size_t>(p.nz) * p.elem * kRingRows;
+    // pipeline: direct global->LDS batches of B rows (V = 4 only) or the register path
+    if (c->stage_rows > 0 && p.vec != 4) return bad("stage_rows > 0 needs nz divisible by 4");
+    p.B = c->stage_rows > 0 ? c->stage_rows : (c->stage_rows == 0 && p.vec == 4 ? 4 : 0);
+    p.ring = p.B > 0 ? 2 * p.B + 2 : kRingRows;
+    p.TY = c->tile_y > 0 ? c->tile_y : 16;
+    const size_t col_bytes = static_cast<size_t>(p.nz) * p.elem;
+    auto lds_for = [&](int tx) {  // LDS: the row ring, then one trip count per tile column
+        return static_cast<size_t>(p.ring) * (tx + 2) * col_bytes + sizeof(int32_t) * static_cast<size_t>(tx) * p.TY;
+    };
     if (c->tile_x > 0) {
         p.TX = c->tile_x;
     } else {
         p.TX = 16;
-        while (p.TX > 1 && (p.TX * NQ > kMaxBlock ||
-                            (p.TX + 2) * row_elems_per_col + 4 * 16 * p.TX > kMaxLds)) --p.TX;
+        while (p.TX > 1 && (p.TX * NQ > kMaxBlock || lds_for(p.TX) > 64 * 1024)) --p.TX;
     }
-    p.TY = c->tile_y > 0 ? c->tile_y : 16;
     if (p.TX > 1024 || p.TY > 256) return bad("tile sizes must be at most 1024 x 256");
     p.block = p.TX * NQ;
     if (p.block > kMaxBlock) return bad("tile_x * nz / vector width exceeds 1024 threads");
-    // LDS: the four-row ring, then one trip count per column of the tile
-    p.lds = (p.TX + 2) * row_elems_per_col + sizeof(int32_t) * static_cast<size_t>(p.TX) * p.TY;
-    if (p.lds > kMaxLds) return bad("tile too large: the LDS row ring and trip counts exceed 64 KiB");
+    p.lds = lds_for(p.TX);
+    if (p.lds > kMaxLds) return bad("tile too large: the LDS row ring and trip counts exceed 160 KiB");
 
     // tiles of every chunk, chunks in id order, tiles in raster order; every tile
     // row can become an item of its own
@@ -419,6 +427,7 @@ void lb_config_default(lb_config* c) {
     c->steal = 1;
     c->graph_steps = 10;
     c->item_split = 2;
+    c->stage_rows = 0;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
@@ -486,22 +495,13 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
                                             sizeof(int32_t) * (static_cast<size_t>(P.C) + P.Q + 3))) != hipSuccess)
         return hip_bail(e, "hipHostMalloc");
 
-    if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
-        int ncu = 0;
-        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device)) != hipSuccess)
-            return hip_bail(e, "hipDeviceGetAttribute(MultiprocessorCount)");
-        const int occ = persistent_occupancy(P.prec, P.vec, P.block, P.lds);
-        if (occ < 1) {
-            fail(nullptr, LB_E_HIP, "persistent kernel occupancy query failed");
-            return bail(LB_E_HIP);
-        }
-        Plan& W = x->plan;
-        W.G = std::max(1, (occ * ncu) / W.Q);
-        W.nwg = W.Q * W.G;
-        if (W.nwg > W.nwg_cap) {
-            W.G = std::max(1, W.nwg_cap / W.Q);
-            W.nwg = W.Q * W.G;
-        }
+    int lds_limit = 0;
+    if ((e = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, x->device)) != hipSuccess)
+        return hip_bail(e, "hipDeviceGetAttribute(MaxSharedMemoryPerBlock)");
+    if (P.lds > static_cast<size_t>(lds_limit)) {
+        fail(nullptr, LB_E_INVAL, "tile needs " + std::to_string(P.lds) + " bytes of LDS, the device allows " +
+                                      std::to_string(lds_limit));
+        return bail(LB_E_INVAL);
     }
     build_tiles(x);
     const std::vector<int32_t> ktab = build_cost_table(*cfg, P.r2cut);
@@ -524,8 +524,27 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.visits = reinterpret_cast<int32_t*>(x->ws + P.off_visits);
     a.ncells = P.ncells;
     a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.nfields = P.nfields;
-    a.nqueues = P.Q; a.nwg = P.nwg; a.steal = cfg->steal; a.head0 = P.G;
     a.tile_x = P.TX;
+    a.block = P.block;
+    a.stage_rows = P.B;
+    if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
+        int ncu = 0;
+        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device)) != hipSuccess)
+            return hip_bail(e, "hipDeviceGetAttribute(MultiprocessorCount)");
+        const int occ = persistent_occupancy(a, P.prec, P.vec, P.block, P.lds);
+        if (occ < 1) {
+            fail(nullptr, LB_E_HIP, "persistent kernel occupancy query failed");
+            return bail(LB_E_HIP);
+        }
+        Plan& W = x->plan;
+        W.G = std::max(1, (occ * ncu) / W.Q);
+        W.nwg = W.Q * W.G;
+        if (W.nwg > W.nwg_cap) {
+            W.G = std::max(1, W.nwg_cap / W.Q);
+            W.nwg = W.Q * W.G;
+        }
+    }
+    a.nqueues = P.Q; a.nwg = P.nwg; a.steal = cfg->steal; a.head0 = P.G;
     a.r2cut = P.r2cut;
     a.kmin = cfg->kmin;
     a.alpha = cfg->alpha_work;

@@ -131,6 +131,8 @@ def test_launch_forms_bit_identical():
     dict(nslots=16, nqueues=16, wg_per_queue=1, steal=1), dict(nslots=8, nqueues=8, wg_per_queue=4, steal=0),
     dict(nslots=16, nqueues=4, wg_per_queue=3), dict(nslots=16, nqueues=8),
     dict(tile_x=4, tile_y=3), dict(tile_x=7, tile_y=5, nslots=2), dict(tile_x=16, tile_y=1),
+    dict(stage_rows=-1), dict(stage_rows=1), dict(stage_rows=3, tile_y=7), dict(stage_rows=8),
+    dict(stage_rows=-1, tile_x=5, tile_y=3), dict(stage_rows=2, tile_x=32, tile_y=4),
 ])
 def test_schedule_invariance(over):
     wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=3)
@@ -186,7 +188,8 @@ def test_ragged_fp64_bit_exact(shape):
     say("ragged", shape)
     wl = mk(nx, ny, nz, px, py, hot=((nx // 3, ny // 2, 1, -1), (0, 0, 0, 0)), sigma=3.0,
             kmax=25, split="dirichlet" if px > 1 else "equal", steps=3, nslots=3)
-    for tiles in (dict(), dict(tile_x=3, tile_y=2)):
+    for tiles in (dict(), dict(tile_x=3, tile_y=2), dict(stage_rows=-1), dict(tile_y=5, stage_rows=2)
+                  if nz % 4 == 0 else dict(tile_y=5)):
         g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **tiles)
         ref, work, _, _ = oracle.run(wl, nsteps=3)
         np.testing.assert_array_equal(q, ref)
