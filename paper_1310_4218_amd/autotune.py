@@ -3,7 +3,7 @@
     python -m paper_1310_4218_amd.autotune --workload moving [--precision fp32]
 
 Searches the launch parameters that do not change the method (tile_x,
-tile_y, nqueues, wg_per_queue, item_split), keeping everything that defines
+tile_y, nqueues, wg_per_queue, item_split, stage_rows), keeping everything that defines
 the problem fixed (grid, chunks, hotspots, number of balancer slots S).  Each candidate:
 a fresh context, a warm-up window, one load measurement and one rebalance
 with the workload's balancer (so that item splitting sees measured costs),
@@ -32,6 +32,7 @@ SPACE = {
     "nqueues": [1, 8, 32, 256],
     "wg_per_queue": [0],          # 0: fill the device (resident workgroups / queues)
     "item_split": [0, 1, 2, 4, 8],
+    "stage_rows": [-1, 2, 4, 6, 8],   # -1: register pipeline; n: direct-to-LDS batches of n rows
 }
 
 
