@@ -72,6 +72,13 @@ enum {
     LB_PLAIN_GRAPH = 2,    /* LB_PLAIN's launches replayed from a HIP graph    */
     LB_PERSISTENT_EAGER = 3 /* LB_PERSISTENT launched directly (no graph)      */
 };
+/* Column physics.  POINTWISE: every cell of column (x, y) gets k(x, y)
+ * applications of Phi (a pointwise reading of Fig. 1).  VERTICAL: k(x, y)
+ * upward sweeps, level z (1..nz-1, in order) becoming
+ * q[z] + eps*((q[z-1]^3) - (q[z]^3)) from the level below as already updated
+ * in the same sweep, level 0 fixed (Fig. 1 / Fig. 4 as written, with the
+ * level wrap of Fig. 4 kept inside 1..nz-1). */
+enum { LB_PHYS_POINTWISE = 0, LB_PHYS_VERTICAL = 1 };
 /* Load source for lb_measure / lb_rebalance. */
 enum { LB_LOAD_WORK = 0, LB_LOAD_TIME = 1 };
 /* Balancer. */
@@ -114,6 +121,8 @@ typedef struct {
     int32_t stage_rows;      /* rows per direct global->LDS batch (nz % 4 == 0
                                 only); 0 = 4 when nz % 4 == 0, else the
                                 register pipeline; -1 = register pipeline      */
+    int32_t physics;         /* LB_PHYS_POINTWISE | LB_PHYS_VERTICAL (the
+                                latter needs nz/V to divide 64)               */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;

@@ -52,8 +52,9 @@ def _load():
             lib.orc_sum.restype = dbl
             lib.orc_run.argtypes = [i32, i32, i32, i32, i32, i32, P(i32), P(i32), dbl, dbl, dbl,
                                     i32, P(i64), P(i64), P(i64), P(i64), dbl, i32, i32, i32, i64,
-                                    i32, P(dbl), P(dbl), P(dbl), P(i32)]
+                                    i32, P(dbl), P(dbl), P(dbl), P(i32), i32]
             lib.orc_run.restype = i32
+            lib.orc_physics_vertical.argtypes = [i32, i32, i32, dbl, P(i32), P(dbl)]
             lib.orc_greedy.argtypes = [P(dbl), i32, i32, P(i32)]
             lib.orc_greedy.restype = i32
             lib.orc_refine.argtypes = [P(dbl), P(i32), i32, i32, dbl, P(i32)]
@@ -62,7 +63,7 @@ def _load():
             lib.orc_refineswap.restype = i32
             lib.orc_run_window.argtypes = [i32, i32, i32, i32, i32, i32, i32, dbl, dbl, dbl, i32,
                                            P(i64), P(i64), P(i64), P(i64), dbl, i32, i32, i64,
-                                           i32, P(dbl)]
+                                           i32, P(dbl), i32]
             lib.orc_run_window.restype = i32
             lib.orc_init_window.argtypes = [i32, i32, i32, i32, i32, i32, i32, i32, u64, P(dbl)]
             _lib = lib
@@ -108,11 +109,12 @@ def stencil(q, cc=0.4, cn=0.1) -> np.ndarray:
     return s
 
 
-def physics(s, k, eps=0.01) -> np.ndarray:
+def physics(s, k, eps=0.01, vertical=False) -> np.ndarray:
     s = np.array(s, dtype=np.float64, copy=True, order="C")
     ny, nx, nz = s.shape
     k = np.ascontiguousarray(k, dtype=np.int32)
-    _load().orc_physics(nx, ny, nz, eps, _p(k, C.c_int32), _p(s, C.c_double))
+    fn = _load().orc_physics_vertical if vertical else _load().orc_physics
+    fn(nx, ny, nz, eps, _p(k, C.c_int32), _p(s, C.c_double))
     return s
 
 
@@ -151,7 +153,7 @@ def run(wl, q0=None, nsteps=None, t0=None):
                          _p(hx, C.c_int64), _p(hy, C.c_int64), _p(vx, C.c_int64),
                          _p(vy, C.c_int64), wl.sigma, wl.kmin, wl.kmax, wl.alpha_work, t0,
                          nsteps, _p(q, C.c_double), _p(work, C.c_double), _p(ck, C.c_double),
-                         _p(klast, C.c_int32))
+                         _p(klast, C.c_int32), int(getattr(wl, "vertical", 0)))
     if rc != 0:
         raise MemoryError("oracle run failed")
     return q, work[:nsteps], ck[:nsteps], klast
@@ -203,7 +205,8 @@ def run_window(wl, q0, ox, oy, nsteps, t0=None) -> np.ndarray:
     rc = _load().orc_run_window(nxw, nyw, nz, ox, oy, wl.nx, wl.ny, wl.c_center, wl.c_nbr, wl.eps,
                                 len(wl.hot), _p(hx, C.c_int64), _p(hy, C.c_int64),
                                 _p(vx, C.c_int64), _p(vy, C.c_int64), wl.sigma, wl.kmin,
-                                wl.kmax, t0, nsteps, _p(q, C.c_double))
+                                wl.kmax, t0, nsteps, _p(q, C.c_double),
+                                int(getattr(wl, "vertical", 0)))
     if rc != 0:
         raise MemoryError("oracle window run failed")
     return q

@@ -24,7 +24,9 @@
  *    array is k_t(x,y) = kmin + floor((kmax-kmin) * max_h exp(-r_h^2/(2 sigma^2))),
  *    r_h^2 the integer minimum-image squared distance to hotspot h at step t.
  *  - The physics map per iteration is Phi(q) = q + eps*(q - (q*q)*q), applied
- *    k times to every cell of the column (a pointwise reading of Fig. 1).
+ *    k times to every cell of the column (a pointwise reading of Fig. 1); the
+ *    vertical variant sweeps the column k times with a dependency on the
+ *    level below (Fig. 1 / Fig. 4 as written).
  *  - Section V / Section VI: load is measured per virtual processor (chunk);
  *    here in deterministic work units w_c = sum over columns of nz*(alpha+k).
  *  - Section VI, Experiment A: GreedyLB "always assigns the heaviest object to
@@ -157,6 +159,27 @@ void orc_physics(int32_t nx, int32_t ny, int32_t nz, double eps, const int32_t *
     }
 }
 
+/* Column physics with a vertical dependency (Fig. 1: a(k) = f(b(k), a(k-1));
+ * Fig. 4: the level loop repeated C(i,j) times).  For each column, k(x,y)
+ * upward sweeps; within a sweep level z (1..nz-1, in order) becomes
+ *   q[z] + eps*((q[z-1]*q[z-1])*q[z-1] - (q[z]*q[z])*q[z])
+ * using level z-1 as already updated in the same sweep.  Level 0 is the
+ * bottom boundary and is not updated. */
+void orc_physics_vertical(int32_t nx, int32_t ny, int32_t nz, double eps, const int32_t *k,
+                          double *s)
+{
+    for (int64_t col = 0; col < (int64_t)nx * ny; ++col) {
+        double *c = s + col * nz;
+        for (int32_t it = 0; it < k[col]; ++it) {
+            for (int32_t z = 1; z < nz; ++z) {
+                double below = (c[z - 1] * c[z - 1]) * c[z - 1];
+                double here = (c[z] * c[z]) * c[z];
+                c[z] = c[z] + eps * (below - here);
+            }
+        }
+    }
+}
+
 /* Per-chunk work of one step: w_c = sum over the chunk's columns of nz*(alpha + k).
  * Chunk c = j*px + i covers [xs[i], xs[i+1]) x [ys[j], ys[j+1]). */
 void orc_chunk_work(int32_t nx, int32_t nz, int32_t px, int32_t py, const int32_t *xs,
@@ -189,7 +212,8 @@ int orc_run(int32_t nx, int32_t ny, int32_t nz, int32_t nfields, int32_t px, int
             const int32_t *xs, const int32_t *ys, double cc, double cn, double eps,
             int32_t nhot, const int64_t *hx0, const int64_t *hy0, const int64_t *hvx,
             const int64_t *hvy, double sigma, int32_t kmin, int32_t kmax, int32_t alpha,
-            int64_t t0, int32_t nsteps, double *q, double *work, double *cksum, int32_t *kout)
+            int64_t t0, int32_t nsteps, double *q, double *work, double *cksum, int32_t *kout,
+            int32_t vertical)
 {
     int64_t ncol = (int64_t)nx * ny;
     int64_t nper = ncol * nz;
@@ -205,7 +229,10 @@ int orc_run(int32_t nx, int32_t ny, int32_t nz, int32_t nfields, int32_t px, int
         for (int32_t f = 0; f < nfields; ++f) {
             double *qf = q + (int64_t)f * nper;
             orc_stencil(nx, ny, nz, cc, cn, qf, s);
-            orc_physics(nx, ny, nz, eps, k, s);
+            if (vertical)
+                orc_physics_vertical(nx, ny, nz, eps, k, s);
+            else
+                orc_physics(nx, ny, nz, eps, k, s);
             memcpy(qf, s, sizeof(double) * (size_t)nper);
         }
         if (work) {
@@ -232,7 +259,7 @@ int orc_run_window(int32_t nxw, int32_t nyw, int32_t nz, int32_t ox, int32_t oy,
                    int32_t NY, double cc, double cn, double eps, int32_t nhot,
                    const int64_t *hx0, const int64_t *hy0, const int64_t *hvx,
                    const int64_t *hvy, double sigma, int32_t kmin, int32_t kmax, int64_t t0,
-                   int32_t nsteps, double *q)
+                   int32_t nsteps, double *q, int32_t vertical)
 {
     int64_t ncol = (int64_t)nxw * nyw;
     double *s = (double *)malloc(sizeof(double) * (size_t)(ncol * nz));
@@ -249,7 +276,10 @@ int orc_run_window(int32_t nxw, int32_t nyw, int32_t nz, int32_t ox, int32_t oy,
                                                NX, NY, nhot, hx0, hy0, hvx, hvy, t0 + step, sigma,
                                                kmin, kmax);
         orc_stencil(nxw, nyw, nz, cc, cn, q, s);
-        orc_physics(nxw, nyw, nz, eps, k, s);
+        if (vertical)
+            orc_physics_vertical(nxw, nyw, nz, eps, k, s);
+        else
+            orc_physics(nxw, nyw, nz, eps, k, s);
         memcpy(q, s, sizeof(double) * (size_t)(ncol * nz));
     }
     free(s);

@@ -103,6 +103,42 @@ __device__ __forceinline__ void physics_vec(T eps, int k, T (&q)[V]) {
     }
 }
 
+// ---- column physics with the vertical dependency ----------------------------------
+// One update of level z from the level below (already updated in this sweep):
+// q + eps*((b*b)*b - (q*q)*q).
+__device__ __forceinline__ float vstep(float eps, float q, float b) {
+    return q + eps * ((b * b) * b - (q * q) * q);
+}
+__device__ __forceinline__ double vstep(double eps, double q, double b) {
+#pragma clang fp contract(off)
+    const double below = (b * b) * b;
+    const double here = (q * q) * q;
+    return q + eps * (below - here);
+}
+
+// k upward sweeps over a column whose nz levels are spread over NQ consecutive
+// lanes (V levels per lane, NQ a power of two <= 64), as a systolic wavefront:
+// at time step tau lane j applies sweep tau - j to its levels, taking the
+// level below from lane j - 1's result of the previous time step.  Level 0 is
+// the fixed bottom boundary.  k + NQ - 1 time steps instead of k * nz.
+template <typename T, int V>
+__device__ __forceinline__ void physics_vertical(T eps, int k, int tzq, int NQ, T (&q)[V]) {
+    T top = q[V - 1];
+    const int steps = k > 0 ? k + NQ - 1 : 0;
+    for (int tau = 0; tau < steps; ++tau) {
+        const T below = __shfl_up(top, 1, NQ);
+        const int sweep = tau - tzq;
+        if (sweep >= 0 && sweep < k) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                if (v == 0 && tzq == 0) continue;
+                q[v] = vstep(eps, q[v], v == 0 ? below : q[v - 1]);
+            }
+        }
+        top = q[V - 1];
+    }
+}
+
 // ---- cost field --------------------------------------------------------------
 __device__ __forceinline__ int wrap_mod(int64_t a, int n) {
     int64_t r = a % n;
@@ -295,7 +331,10 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
                 sum = sum + zp;
                 q[v] = combine(cc, cn, c.v[v], sum);
             }
-            physics_vec<KAHAN, T, V>(eps, k, q);
+            if (a.vertical)
+                physics_vertical<T, V>(eps, k, tzq, NQ, q);
+            else
+                physics_vec<KAHAN, T, V>(eps, k, q);
             Vec<T, V> out;
 #pragma unroll
             for (int v = 0; v < V; ++v) {

@@ -58,6 +58,7 @@ struct DevArgs {
     int32_t tile_x;            // TX
     int32_t block;             // threads per workgroup = TX * nz / V (== blockDim.x)
     int32_t stage_rows;        // > 0: rows per direct global->LDS batch (V = 4 only); 0: registers
+    int32_t vertical;          // 1: column physics with the vertical dependency
     int32_t r2cut;
     int32_t kmin;
     int32_t alpha;

@@ -92,6 +92,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->steal != 0 && c->steal != 1) return bad("steal must be 0 or 1");
     if (c->item_split < 0 || c->item_split > 64) return bad("item_split must be in [0, 64]");
     if (c->stage_rows < -1 || c->stage_rows > 32) return bad("stage_rows must be in [-1, 32]");
+    if (c->physics != LB_PHYS_POINTWISE && c->physics != LB_PHYS_VERTICAL) return bad("physics");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
     p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
@@ -110,6 +111,9 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (!strictly_increasing(p.ys, p.ny)) return bad("ysplit must rise strictly from 0 to ny");
 
     const int NQ = p.nz / p.vec;
+    if (c->physics == LB_PHYS_VERTICAL && (NQ > 64 || 64 % NQ != 0))
+        return fail(err, LB_E_UNSUPPORTED,
+                    "vertical physics needs nz / V to divide 64 (V = 4, 2 or 1 by divisibility of nz)");
     // pipeline: direct global->LDS batches of B rows (V = 4 only) or the register path
     if (c->stage_rows > 0 && p.vec != 4) return bad("stage_rows > 0 needs nz divisible by 4");
     p.B = c->stage_rows > 0 ? c->stage_rows : (c->stage_rows == 0 && p.vec == 4 ? 4 : 0);
@@ -428,6 +432,7 @@ void lb_config_default(lb_config* c) {
     c->graph_steps = 10;
     c->item_split = 2;
     c->stage_rows = 0;
+    c->physics = LB_PHYS_POINTWISE;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
@@ -527,6 +532,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.tile_x = P.TX;
     a.block = P.block;
     a.stage_rows = P.B;
+    a.vertical = cfg->physics == LB_PHYS_VERTICAL ? 1 : 0;
     if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
         int ncu = 0;
         if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device)) != hipSuccess)

@@ -5,6 +5,7 @@
     rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- python3 bench.py ...same...
     python -m paper_1310_4218_amd.traffic --fetch OUT/fetch --write OUT/write --workload W \
         --copy-mib 512
+    python -m paper_1310_4218_amd.traffic stats OUT/stats --title T --command C --write F.md
 
 Both counters are reported in KiB per dispatch.  Each is scaled by what the
 same counter reads for the plain device copy of known size that bench.py runs
@@ -58,7 +59,46 @@ def pick(per: dict, needle) -> list:
     return vals
 
 
+def stats_summary(outdir: str, title: str, command: str, top: int = 12) -> str:
+    """Markdown table of the per-kernel statistics rocprofv3 --stats wrote under outdir."""
+    files = glob.glob(os.path.join(outdir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no kernel_stats CSV under {outdir}")
+    rows = []
+    for path in files:
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+    out = [f"# {title}", "", "Command:", "", "```", command, "```", "",
+           "| kernel | calls | total ms | average us | min us | max us | % |",
+           "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r.get("Name", "")
+        if len(name) > 70:
+            name = name[:67] + "..."
+        out.append("| `{}` | {} | {:.3f} | {:.2f} | {:.2f} | {:.2f} | {:.1f} |".format(
+            name, r.get("Calls"), float(r.get("TotalDurationNs", 0)) / 1e6,
+            float(r.get("AverageNs", 0)) / 1e3, float(r.get("MinNs", 0)) / 1e3,
+            float(r.get("MaxNs", 0)) / 1e3, float(r.get("Percentage", 0))))
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None) -> int:
+    if argv is None:
+        argv = sys.argv[1:]
+    if argv and argv[0] == "stats":
+        ap = argparse.ArgumentParser(prog="traffic stats")
+        ap.add_argument("outdir")
+        ap.add_argument("--title", required=True)
+        ap.add_argument("--command", required=True)
+        ap.add_argument("--write", help="markdown file to write")
+        a = ap.parse_args(argv[1:])
+        md = stats_summary(a.outdir, a.title, a.command)
+        if a.write:
+            with open(a.write, "w") as f:
+                f.write(md)
+        print(md)
+        return 0
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)

@@ -60,6 +60,7 @@ class Workload:
     seed: int = 0
     split_kind: str = "equal"
     alpha_d: float = 0.0
+    vertical: int = 0                 # 1: column physics with the vertical dependency
 
     @property
     def nchunks(self) -> int:

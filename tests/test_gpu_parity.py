@@ -441,3 +441,34 @@ def test_full_size_fp32_step_error_windows(name):
         worst = max(worst, float(np.max(np.abs(got - ref))) / scale)
     say(name, "one-step error", worst)
     assert worst <= TOL
+
+
+# ------------------------------------------------------------------ vertical column physics
+@pytest.mark.parametrize("nz", [64, 32, 16, 8, 2, 1])
+def test_vertical_physics_fp64_bit_exact(nz):
+    wl = mk(40, 36, nz, 4, 3, kmax=40, sigma=5.0, split="dirichlet", steps=3).replace(vertical=1)
+    ref, work, _, _ = oracle.run(wl, nsteps=3)
+    for over in (dict(), dict(stage_rows=-1), dict(tile_x=5, tile_y=3)):
+        g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
+        np.testing.assert_array_equal(q, ref)
+        np.testing.assert_array_equal(w, work.sum(axis=0))
+        g.close()
+
+
+def test_vertical_physics_fp32_and_launch_forms():
+    wl = W.small().replace(vertical=1)
+    ref, _, _, _ = oracle.run(wl)
+    _, q, _ = run_gpu(wl, wl.steps, "persistent")
+    _, qp, _ = run_gpu(wl, wl.steps, "plain")
+    np.testing.assert_array_equal(q, qp)
+    err = rel_err(q, ref)
+    say("vertical fp32 rel err", err)
+    assert err <= TOL
+
+
+def test_vertical_physics_rejects_unsupported_nz():
+    from paper_1310_4218_amd._abi import LbError, LB_E_UNSUPPORTED
+    wl = mk(16, 16, 80, 2, 2).replace(vertical=1)        # 80 / 4 = 20 lanes per column
+    with pytest.raises(LbError) as e:
+        Grid(wl)
+    assert e.value.code == LB_E_UNSUPPORTED

@@ -244,3 +244,57 @@ def test_dirichlet_splits_valid():
     # extreme concentration still yields a valid split
     xs, _ = W.make_splits(40, 40, 40, 2, "dirichlet", 0.05, 1)
     assert np.all(np.diff(xs) == 1)
+
+
+# ---------------------------------------------------------------- vertical column physics
+def test_vertical_constant_columns_fixed():
+    """Equal levels give b^3 - q^3 = 0 exactly, so constant columns never change."""
+    s = np.zeros((2, 3, 6))
+    s[0] = 0.3
+    s[1] = -0.7
+    out = oracle.physics(s, np.full((2, 3), 25, np.int32), vertical=True)
+    np.testing.assert_array_equal(out, s)
+
+
+def test_vertical_bottom_fixed_and_single_level():
+    rng = np.random.default_rng(1)
+    s = rng.uniform(-1, 1, size=(3, 4, 7))
+    out = oracle.physics(s, np.full((3, 4), 9, np.int32), vertical=True)
+    np.testing.assert_array_equal(out[:, :, 0], s[:, :, 0])
+    s1 = rng.uniform(-1, 1, size=(3, 4, 1))
+    np.testing.assert_array_equal(oracle.physics(s1, np.full((3, 4), 9, np.int32), vertical=True), s1)
+
+
+def test_vertical_sweep_is_sequential_upward():
+    """One sweep over three levels: level 2 sees level 1 already updated in the same sweep
+    (Fig. 1's a(k) = f(b(k), a(k-1))), which a simultaneous update would not."""
+    eps = 0.01
+    q0, q1, q2 = 0.9, -0.2, 0.4
+    s = np.array([[[q0, q1, q2]]])
+    out = oracle.physics(s, np.array([[1]], np.int32), eps, vertical=True)[0, 0]
+    n1 = q1 + eps * (q0 ** 3 - q1 ** 3)
+    seq2 = q2 + eps * (n1 ** 3 - q2 ** 3)
+    par2 = q2 + eps * (q1 ** 3 - q2 ** 3)
+    assert out[1] == pytest.approx(n1, abs=1e-16)
+    assert out[2] == pytest.approx(seq2, abs=1e-16)
+    assert abs(out[2] - par2) > 1e-6
+
+
+def test_vertical_two_level_relaxation_rate():
+    """Two levels, bottom fixed at a: the top relaxes towards a with slope 1 - 3 eps a^2
+    per sweep, so a small offset d decays like d (1 - 3 eps a^2)^k."""
+    a, d, k = 0.5, 1e-9, 60
+    s = np.array([[[a, a + d]]])
+    out = oracle.physics(s, np.array([[k]], np.int32), 0.01, vertical=True)[0, 0]
+    assert out[1] - a == pytest.approx(d * (1 - 3 * 0.01 * a * a) ** k, rel=1e-5)
+
+
+def test_vertical_odd_symmetric_and_bounded():
+    wl = tiny(kmin=1, kmax=40, steps=3).replace(vertical=1)
+    q0 = oracle.init_field(wl.nx, wl.ny, wl.nz, seed=12)
+    a, _, _, _ = oracle.run(wl, q0=q0)
+    b, _, _, _ = oracle.run(wl, q0=-q0)
+    np.testing.assert_array_equal(a, -b)
+    assert np.abs(a).max() <= 1.0
+    p, _, _, _ = oracle.run(wl.replace(vertical=0), q0=q0)
+    assert not np.array_equal(a, p)                   # the two physics differ
