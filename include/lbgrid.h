@@ -215,6 +215,11 @@ int lb_stats(lb_ctx *ctx, lb_stats_t *out);
  * imbalance of the persistent kernel. */
 int lb_wg_busy(lb_ctx *ctx, double *out, int32_t n);
 
+/* Synchronize and copy the timeline of the last persistent launch: 4 doubles
+ * per workgroup (n >= 4*nwg), in microseconds from the earliest workgroup
+ * start: start, first item start, last item end, exit. */
+int lb_wg_timeline(lb_ctx *ctx, double *out, int32_t n);
+
 /* Synchronize and copy per-tile-row visit counts since the last reset (n >= nrows
  * int32, tiles in chunk order, rows top to bottom); every row is computed
  * exactly once per step.  reset != 0 zeroes them. */

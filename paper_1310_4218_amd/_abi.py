@@ -80,6 +80,7 @@ SIGNATURES = {
     "lb_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, DBLP]),
     "lb_stats": (C.c_int, [C.c_void_p, C.POINTER(LbStats)]),
     "lb_wg_busy": (C.c_int, [C.c_void_p, DBLP, C.c_int32]),
+    "lb_wg_timeline": (C.c_int, [C.c_void_p, DBLP, C.c_int32]),
     "lb_visits": (C.c_int, [C.c_void_p, I32P, C.c_int32, C.c_int32]),
     "lb_checksums": (C.c_int, [C.c_void_p, DBLP, C.c_int32, I32P]),
     "lb_balance_host": (C.c_int, [DBLP, I32P, C.c_int32, C.c_int32, C.c_int32, C.c_double, I32P,

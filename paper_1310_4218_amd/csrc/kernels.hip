@@ -441,23 +441,41 @@ __device__ __forceinline__ StepInfo step_info(const DevArgs& a) {
     return s;
 }
 
-// Called by thread 0 after an item: its checksum partial, the chunk's loads, and
-// one visit for each tile row the item covered (plain increments: exactly one
-// workgroup owns a row in a step, so a second claim would show as a miscount).
+// Called by every thread after an item.  Thread 0 writes the item's checksum
+// partial and adds its work and ticks to the chunk's loads; the tile rows the
+// item covered each get one visit, one thread per row.  None of these waits
+// for a reply (stores and non-returning atomics), so an item's bookkeeping
+// costs no memory latency.  Exactly one workgroup owns a row in a step, so a
+// second claim or a missed row shows as a wrong visit count.
 __device__ __forceinline__ void record_item(const DevArgs& a, const ItemDesc& d,
                                             const ItemOut& o, double ticks) {
-    a.partials[d.id] = o.checksum;
-    unsafeAtomicAdd(&a.loads_work[d.chunk], o.work);
-    unsafeAtomicAdd(&a.loads_time[d.chunk], ticks);
-    for (int r = 0; r < (d.wh >> 16); ++r) a.visits[d.vbase + r] += 1;
+    if (threadIdx.x == 0) {
+        a.partials[d.id] = o.checksum;
+        unsafeAtomicAdd(&a.loads_work[d.chunk], o.work);
+        unsafeAtomicAdd(&a.loads_time[d.chunk], ticks);
+    }
+    for (int r = threadIdx.x; r < (d.wh >> 16); r += a.block)
+        __hip_atomic_fetch_add(&a.visits[d.vbase + r], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Deterministic sum of the per-item partials (item order) into the checksum ring,
 // then the step counter moves on.  Run by one whole workgroup.
 __device__ void finish_step(const DevArgs& a, uint64_t step, double* red, int bs) {
     const int n = static_cast<int>(a.ctrl->nitems);
+    // Thread t adds partials t, t + bs, t + 2 bs, ... in that order; the loads of
+    // a batch are issued together so that one memory latency covers 16 of them.
+    constexpr int kBatch = 16;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += bs) acc += a.partials[i];
+    for (int i0 = 0; i0 < n; i0 += kBatch * bs) {
+        double v[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int i = i0 + j * bs + static_cast<int>(threadIdx.x);
+            v[j] = i < n ? a.partials[i] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) acc += v[j];
+    }
     const double total = block_sum(acc, red, bs);
     if (threadIdx.x == 0) {
         a.hist[step % kHistLen] = total;
@@ -568,6 +586,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     const int hn = a.seg[home + 1] - hbeg;
     double busy = 0.0;
 
+    uint64_t t_first = 0, t_last = 0;
+    const uint64_t t_launch = wall_clock64();
     if (threadIdx.x == 0) s_desc = rank < hn ? a.queue[hbeg + rank] : no_item();
     __syncthreads();
     for (;;) {
@@ -590,17 +610,24 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
             if (threadIdx.x == 0 && nidx < hn) nd = a.queue[hbeg + nidx];
         };
         const uint64_t t_start = wall_clock64();
+        if (t_first == 0) t_first = t_start;
         const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, src, dst, si.hcx, si.hcy, lds, red, ahead);
+        t_last = wall_clock64();
+        const double ticks = static_cast<double>(t_last - t_start);  // used by thread 0
+        record_item(a, d, o, ticks);
         if (threadIdx.x == 0) {
-            const double ticks = static_cast<double>(wall_clock64() - t_start);
             busy += ticks;
-            record_item(a, d, o, ticks);
             s_desc = nd;
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         a.wg_busy[blockIdx.x] += busy;
+        uint64_t* tl = a.wg_timeline + 4 * static_cast<size_t>(blockIdx.x);
+        tl[0] = t_launch;
+        tl[1] = t_first ? t_first : t_launch;
+        tl[2] = t_last ? t_last : t_launch;
+        tl[3] = wall_clock64();
         __threadfence();
         const uint32_t prev = atomicAdd(&a.ctrl->done, 1u);
         s_last = (prev == static_cast<uint32_t>(a.nwg) - 1u);
@@ -627,7 +654,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
     const ItemDesc d = a.items[item];
     const uint64_t t_start = wall_clock64();
     const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
-    if (threadIdx.x == 0) record_item(a, d, o, static_cast<double>(wall_clock64() - t_start));
+    record_item(a, d, o, static_cast<double>(wall_clock64() - t_start));
 }
 
 __global__ __launch_bounds__(256) void k_finish(DevArgs a) {

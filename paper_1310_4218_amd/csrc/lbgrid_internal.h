@@ -50,6 +50,8 @@ struct DevArgs {
     double* partials;          // per item: sum of the item's outputs in the last step
     double* hist;              // kHistLen per-step sums
     double* wg_busy;           // nwg
+    uint64_t* wg_timeline;     // 4 per workgroup, last persistent launch: start, first item,
+                               // end of last item, exit (wall-clock ticks)
     int32_t* visits;           // per tile row: times it was computed
     int64_t ncells;            // cells per field
     int32_t nx, ny, nz, nfields;

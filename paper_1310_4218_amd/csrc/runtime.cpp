@@ -51,7 +51,7 @@ struct Plan {
     std::vector<int32_t> xs, ys;
     // workspace layout (byte offsets)
     size_t off_ctrl = 0, off_ktab = 0, off_items = 0, off_itemoff = 0, off_queue = 0, off_seg = 0,
-           off_heads = 0, off_lw = 0, off_lt = 0, off_part = 0, off_hist = 0, off_busy = 0,
+           off_heads = 0, off_lw = 0, off_lt = 0, off_part = 0, off_hist = 0, off_busy = 0, off_tl = 0,
            off_visits = 0, off_sum = 0, ws_bytes = 0;
     size_t field_bytes = 0;
 };
@@ -175,6 +175,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_part = take(sizeof(double) * static_cast<size_t>(p.nrows));
     p.off_hist = take(sizeof(double) * kHistLen);
     p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg_cap));
+    p.off_tl = take(sizeof(uint64_t) * 4 * static_cast<size_t>(p.nwg_cap));
     p.off_visits = take(sizeof(int32_t) * static_cast<size_t>(p.nrows));
     p.off_sum = take(sizeof(double) * (kSumBlocks + 1));
     p.ws_bytes = o;
@@ -526,6 +527,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.partials = reinterpret_cast<double*>(x->ws + P.off_part);
     a.hist = reinterpret_cast<double*>(x->ws + P.off_hist);
     a.wg_busy = reinterpret_cast<double*>(x->ws + P.off_busy);
+    a.wg_timeline = reinterpret_cast<uint64_t*>(x->ws + P.off_tl);
     a.visits = reinterpret_cast<int32_t*>(x->ws + P.off_visits);
     a.ncells = P.ncells;
     a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.nfields = P.nfields;
@@ -779,6 +781,21 @@ int lb_wg_busy(lb_ctx* x, double* out, int32_t n) {
     int rc = sync(x);
     if (rc != LB_OK) return rc;
     HIP_TRY(x, hipMemcpy(out, x->ws + x->plan.off_busy, sizeof(double) * x->plan.nwg, hipMemcpyDeviceToHost));
+    return LB_OK;
+}
+
+int lb_wg_timeline(lb_ctx* x, double* out, int32_t n) {
+    if (!x || !out) return fail(x ? &x->err : nullptr, LB_E_INVAL, "ctx and out are required");
+    const Plan& p = x->plan;
+    if (n < 4 * p.nwg) return fail(&x->err, LB_E_NOMEM, "out too small for 4 * nwg entries");
+    int rc = sync(x);
+    if (rc != LB_OK) return rc;
+    std::vector<uint64_t> t(4 * static_cast<size_t>(p.nwg));
+    HIP_TRY(x, hipMemcpy(t.data(), x->ws + p.off_tl, sizeof(uint64_t) * t.size(), hipMemcpyDeviceToHost));
+    uint64_t t0 = UINT64_MAX;
+    for (int32_t w = 0; w < p.nwg; ++w) t0 = std::min(t0, t[4 * w]);
+    for (size_t i = 0; i < t.size(); ++i)
+        out[i] = t[i] >= t0 ? static_cast<double>(t[i] - t0) / x->clock_hz * 1e6 : 0.0;
     return LB_OK;
 }
 

@@ -148,6 +148,14 @@ class Grid:
         check(_abi.lib().lb_wg_busy(self.handle, ptr(out, C.c_double), self.nwg), self.handle)
         return out
 
+    def wg_timeline(self) -> np.ndarray:
+        """(nwg, 4) microseconds of the last persistent launch: start, first item start,
+        last item end, exit, from the earliest workgroup start."""
+        out = np.empty(4 * self.nwg, dtype=np.float64)
+        check(_abi.lib().lb_wg_timeline(self.handle, ptr(out, C.c_double), 4 * self.nwg),
+              self.handle)
+        return out.reshape(self.nwg, 4)
+
     def visits(self, reset: bool = False) -> np.ndarray:
         out = np.empty(self.nrows, dtype=np.int32)
         check(_abi.lib().lb_visits(self.handle, ptr(out, C.c_int32), self.nrows, int(reset)),
