@@ -123,6 +123,10 @@ typedef struct {
                                 register pipeline; -1 = register pipeline      */
     int32_t physics;         /* LB_PHYS_POINTWISE | LB_PHYS_VERTICAL (the
                                 latter needs nz/V to divide 64)               */
+    int32_t tail_split;      /* in every queue, the cheapest tiles that make up
+                                the last 1/G of its cost are cut this many
+                                times finer, so a step ends on small items;
+                                0 or 1 = off (4)                              */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;

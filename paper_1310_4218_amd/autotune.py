@@ -33,6 +33,7 @@ SPACE = {
     "wg_per_queue": [0],          # 0: fill the device (resident workgroups / queues)
     "item_split": [0, 1, 2, 4, 8],
     "stage_rows": [-1, 2, 4, 6, 8],   # -1: register pipeline; n: direct-to-LDS batches of n rows
+    "tail_split": [0, 2, 4, 8],
 }
 
 

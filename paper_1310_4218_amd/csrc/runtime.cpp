@@ -91,6 +91,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->graph_steps < 1 || c->graph_steps > 1000) return bad("graph_steps must be in [1, 1000]");
     if (c->steal != 0 && c->steal != 1) return bad("steal must be 0 or 1");
     if (c->item_split < 0 || c->item_split > 64) return bad("item_split must be in [0, 64]");
+    if (c->tail_split < 0 || c->tail_split > 64) return bad("tail_split must be in [0, 64]");
     if (c->stage_rows < -1 || c->stage_rows > 32) return bad("stage_rows must be in [-1, 32]");
     if (c->physics != LB_PHYS_POINTWISE && c->physics != LB_PHYS_VERTICAL) return bad("physics");
 
@@ -294,21 +295,54 @@ int upload_plan(lb_ctx* x, const double* cost) {
     const int split = x->cfg.item_split;
     const double target = (cost && split > 0 && W > 0.0) ? W / (static_cast<double>(p.nwg) * split) : 0.0;
 
+    // Estimated cost of every tile: its chunk's measured cost times its share of
+    // the chunk's area; without measurements, the tile's area.
+    std::vector<double> tcost(static_cast<size_t>(p.ntiles));
+    std::vector<int> pieces(static_cast<size_t>(p.ntiles), 1);
+    for (int32_t c = 0; c < p.C; ++c) {
+        const int i = c % p.px, j = c / p.px;
+        const double area_c = static_cast<double>(p.xs[i + 1] - p.xs[i]) * (p.ys[j + 1] - p.ys[j]);
+        for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) {
+            const int w = x->tiles[4 * t + 2] & 0xffff, h = x->tiles[4 * t + 2] >> 16;
+            const double area_t = static_cast<double>(w) * h;
+            tcost[t] = cost ? cost[c] * (area_t / area_c) : area_t;
+            if (target > 0.0 && tcost[t] > target)
+                pieces[t] = static_cast<int>(std::min<double>(h, std::ceil(tcost[t] / target)));
+        }
+    }
+    // Tail: in every queue, the cheapest tiles whose pieces make up the last
+    // 1/G of the queue's cost (the final round of its G workgroups) are cut
+    // tail_split times finer, so the step ends on small items.
+    const int tail = x->cfg.tail_split;
+    if (tail > 1) {
+        std::vector<std::vector<int32_t>> qt(static_cast<size_t>(p.Q));
+        for (int32_t c = 0; c < p.C; ++c)
+            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) qt[x->map[c] % p.Q].push_back(t);
+        for (auto& v : qt) {
+            double Wq = 0.0;
+            for (int32_t t : v) Wq += tcost[t];
+            std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
+                return tcost[a] / pieces[a] > tcost[b] / pieces[b];
+            });
+            const double share = Wq / std::max(p.G, 1);
+            double acc = 0.0;
+            for (auto it = v.rbegin(); it != v.rend() && acc < share; ++it) {
+                acc += tcost[*it];
+                const int h = x->tiles[4 * *it + 2] >> 16;
+                pieces[*it] = std::min(h, pieces[*it] * tail);
+            }
+        }
+    }
+
     x->items.clear();
     x->item_off.assign(static_cast<size_t>(p.C) + 1, 0);
     std::vector<double> item_cost;
     for (int32_t c = 0; c < p.C; ++c) {
         x->item_off[c] = static_cast<int32_t>(x->items.size());
-        const int i = c % p.px, j = c / p.px;
-        const double area_c = static_cast<double>(p.xs[i + 1] - p.xs[i]) * (p.ys[j + 1] - p.ys[j]);
         for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) {
             const int w = x->tiles[4 * t + 2] & 0xffff, h = x->tiles[4 * t + 2] >> 16;
-            const double tc = cost ? cost[c] * (static_cast<double>(w) * h / area_c) : 0.0;
-            int pieces = 1;
-            if (target > 0.0 && tc > target)
-                pieces = static_cast<int>(std::min<double>(h, std::ceil(tc / target)));
-            for (int k = 0; k < pieces; ++k) {
-                const int r0 = (k * h) / pieces, r1 = ((k + 1) * h) / pieces;
+            for (int k = 0; k < pieces[t]; ++k) {
+                const int r0 = (k * h) / pieces[t], r1 = ((k + 1) * h) / pieces[t];
                 ItemDesc d{};
                 d.x0 = x->tiles[4 * t + 0];
                 d.y0 = x->tiles[4 * t + 1] + r0;
@@ -317,7 +351,7 @@ int upload_plan(lb_ctx* x, const double* cost) {
                 d.id = static_cast<int32_t>(x->items.size());
                 d.vbase = x->row_base[t] + r0;
                 x->items.push_back(d);
-                item_cost.push_back(tc * (r1 - r0) / h);
+                item_cost.push_back(tcost[t] * (r1 - r0) / h);
             }
         }
     }
@@ -434,6 +468,7 @@ void lb_config_default(lb_config* c) {
     c->item_split = 2;
     c->stage_rows = 0;
     c->physics = LB_PHYS_POINTWISE;
+    c->tail_split = 4;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
