@@ -69,16 +69,25 @@ def stats_summary(outdir: str, title: str, command: str, top: int = 12) -> str:
         with open(path, newline="") as f:
             rows.extend(csv.DictReader(f))
     rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+    # per-kernel median duration from the dispatch trace, when it was written too
+    durs = {}
+    for path in glob.glob(os.path.join(outdir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for t in csv.DictReader(f):
+                durs.setdefault(t["Kernel_Name"], []).append(
+                    int(t["End_Timestamp"]) - int(t["Start_Timestamp"]))
     out = [f"# {title}", "", "Command:", "", "```", command, "```", "",
-           "| kernel | calls | total ms | average us | min us | max us | % |",
-           "|---|---|---|---|---|---|---|"]
+           "| kernel | calls | total ms | average us | median us | min us | max us | % |",
+           "|---|---|---|---|---|---|---|---|"]
     for r in rows[:top]:
         name = r.get("Name", "")
+        d = sorted(durs.get(name, []))
+        med = "{:.2f}".format(d[len(d) // 2] / 1e3) if d else "-"
         if len(name) > 70:
             name = name[:67] + "..."
-        out.append("| `{}` | {} | {:.3f} | {:.2f} | {:.2f} | {:.2f} | {:.1f} |".format(
+        out.append("| `{}` | {} | {:.3f} | {:.2f} | {} | {:.2f} | {:.2f} | {:.1f} |".format(
             name, r.get("Calls"), float(r.get("TotalDurationNs", 0)) / 1e6,
-            float(r.get("AverageNs", 0)) / 1e3, float(r.get("MinNs", 0)) / 1e3,
+            float(r.get("AverageNs", 0)) / 1e3, med, float(r.get("MinNs", 0)) / 1e3,
             float(r.get("MaxNs", 0)) / 1e3, float(r.get("Percentage", 0))))
     return "\n".join(out) + "\n"
 
