@@ -429,10 +429,10 @@ struct StepInfo {
     int hcx[kMaxHot], hcy[kMaxHot];
 };
 
-__device__ __forceinline__ StepInfo step_info(const DevArgs& a) {
+__device__ __forceinline__ StepInfo step_info(const DevArgs& a, uint64_t step) {
     StepInfo s;
-    s.step = a.ctrl->step;
-    const int64_t t = a.t0 + static_cast<int64_t>(s.step);
+    s.step = step;
+    const int64_t t = a.t0 + static_cast<int64_t>(step);
 #pragma unroll
     for (int h = 0; h < kMaxHot; ++h) {
         s.hcx[h] = h < a.nhot ? wrap_mod(a.hx0[h] + static_cast<int64_t>(a.hvx[h]) * t, a.nx) : 0;
@@ -447,10 +447,10 @@ __device__ __forceinline__ StepInfo step_info(const DevArgs& a) {
 // for a reply (stores and non-returning atomics), so an item's bookkeeping
 // costs no memory latency.  Exactly one workgroup owns a row in a step, so a
 // second claim or a missed row shows as a wrong visit count.
-__device__ __forceinline__ void record_item(const DevArgs& a, const ItemDesc& d,
+__device__ __forceinline__ void record_item(const DevArgs& a, double* partials, const ItemDesc& d,
                                             const ItemOut& o, double ticks) {
     if (threadIdx.x == 0) {
-        a.partials[d.id] = o.checksum;
+        partials[d.id] = o.checksum;
         unsafeAtomicAdd(&a.loads_work[d.chunk], o.work);
         unsafeAtomicAdd(&a.loads_time[d.chunk], ticks);
     }
@@ -458,29 +458,52 @@ __device__ __forceinline__ void record_item(const DevArgs& a, const ItemDesc& d,
         __hip_atomic_fetch_add(&a.visits[d.vbase + r], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Deterministic sum of the per-item partials (item order) into the checksum ring,
-// then the step counter moves on.  Run by one whole workgroup.
-__device__ void finish_step(const DevArgs& a, uint64_t step, double* red, int bs) {
-    const int n = static_cast<int>(a.ctrl->nitems);
-    // Thread t adds partials t, t + bs, t + 2 bs, ... in that order; the loads of
-    // a batch are issued together so that one memory latency covers 16 of them.
+// Deterministic sum of n checksum partials, valid in every thread.  The shape is
+// fixed whatever the block size: accumulator v (0..255) adds partials v,
+// v + 256, v + 512, ... in that order, then the 256 accumulators are added as a
+// pairwise tree (v + 128, then v + 64, ...), so every kernel that sums a step's
+// partials gets the same bits.  acc must hold kSumThreads doubles of LDS.
+// Loads go out 16 at a time so that one memory latency covers a batch.
+constexpr int kSumThreads = 256;
+constexpr int kRedLen = kSumThreads;  // LDS doubles for block sums and partial sums
+static_assert(kRedLen >= 2 * kMaxBlock / 64, "block_sum2 needs two entries per wave");
+__device__ double sum_partials(const double* part, int n, double* acc, int bs) {
     constexpr int kBatch = 16;
-    double acc = 0.0;
-    for (int i0 = 0; i0 < n; i0 += kBatch * bs) {
-        double v[kBatch];
+    for (int v = threadIdx.x; v < kSumThreads; v += bs) {
+        double s = 0.0;
+        for (int i0 = 0; i0 < n; i0 += kBatch * kSumThreads) {
+            double x[kBatch];
 #pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-            const int i = i0 + j * bs + static_cast<int>(threadIdx.x);
-            v[j] = i < n ? a.partials[i] : 0.0;
+            for (int j = 0; j < kBatch; ++j) {
+                const int i = i0 + j * kSumThreads + v;
+                x[j] = i < n ? part[i] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) s += x[j];
         }
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) acc += v[j];
+        acc[v] = s;
     }
-    const double total = block_sum(acc, red, bs);
+    __syncthreads();
+    for (int h = kSumThreads / 2; h > 0; h >>= 1) {
+        for (int v = threadIdx.x; v < h; v += bs) acc[v] = acc[v] + acc[v + h];
+        __syncthreads();
+    }
+    const double total = acc[0];
+    __syncthreads();                  // acc may be reused at once
+    return total;
+}
+
+// If partials buffer p holds a step whose sum is still pending, sum it into the
+// checksum ring and mark it done.  Run by one whole workgroup, with no other
+// workgroup touching buffer p.
+__device__ void settle_partials(const DevArgs& a, int p, double* red, int bs) {
+    const uint64_t ps = a.ctrl->pend_step[p];     // the same value in every thread
+    if (ps == 0) return;
+    const int n = static_cast<int>(a.ctrl->pend_n[p]);
+    const double total = sum_partials(a.partials + static_cast<int64_t>(p) * a.part_stride, n, red, bs);
     if (threadIdx.x == 0) {
-        a.hist[step % kHistLen] = total;
-        a.ctrl->done = 0;
-        a.ctrl->step = step + 1;
+        a.hist[(ps - 1) % kHistLen] = total;
+        a.ctrl->pend_step[p] = 0;
     }
 }
 
@@ -488,7 +511,8 @@ __device__ void finish_step(const DevArgs& a, uint64_t step, double* red, int bs
 // Workgroups are dispatched to the eight XCDs round-robin (workgroup w runs on
 // XCD w % 8).  When Q is a multiple of 8, queue q is served only by workgroups
 // on XCD q % 8, so the items of a chunk share that XCD's L2.  Every queue has
-// exactly G workgroups, with ranks 0..G-1.
+// exactly G workgroups, with ranks 0..G-1 (rank (w >> 3) / (Q / 8), else w / Q);
+// the host uses the same assignment to precompute each workgroup's first item.
 __device__ __forceinline__ int home_queue(const DevArgs& a, int wg) {
     if (a.xcd_queues) {
         const int per_xcd = a.nqueues / 8;
@@ -496,17 +520,13 @@ __device__ __forceinline__ int home_queue(const DevArgs& a, int wg) {
     }
     return wg % a.nqueues;
 }
-__device__ __forceinline__ int queue_rank(const DevArgs& a, int wg) {
-    if (a.xcd_queues) return (wg >> 3) / (a.nqueues / 8);
-    return wg / a.nqueues;
-}
 
 // Index (into the queue array) of a claimed item of queue q, or -1 if it is empty.
-__device__ __forceinline__ int try_claim(const DevArgs& a, int q) {
+__device__ __forceinline__ int try_claim(const DevArgs& a, int* heads, int q) {
     const int beg = a.seg[q];
     const int n = a.seg[q + 1] - beg;
-    if (__hip_atomic_load(&a.heads[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) return -1;
-    const int i = atomicAdd(&a.heads[q], 1);
+    if (__hip_atomic_load(&heads[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) return -1;
+    const int i = atomicAdd(&heads[q], 1);
     return i < n ? beg + i : -1;
 }
 
@@ -515,10 +535,10 @@ __device__ __forceinline__ int try_claim(const DevArgs& a, int q) {
 // the one with the most work left among the first 64 with any.  Every failed
 // claim means that queue is empty for good (heads only grow), so the scan
 // ends after at most Q failures.
-__device__ int claim(const DevArgs& a, int home) {
+__device__ int claim(const DevArgs& a, int* heads, int home) {
     const int lane = threadIdx.x & (kWave - 1);
     int qi = -1;
-    if (lane == 0) qi = try_claim(a, home);
+    if (lane == 0) qi = try_claim(a, heads, home);
     qi = __shfl(qi, 0, kWave);
     if (qi >= 0 || !a.steal) return qi;
     const int Q = a.nqueues;
@@ -530,7 +550,7 @@ __device__ int claim(const DevArgs& a, int home) {
         if (j < Q && lane < a.block) {
             q = a.xcd_queues ? (home + 8 * (j % per_xcd) + j / per_xcd) % Q : (home + j) % Q;
             rem = (a.seg[q + 1] - a.seg[q]) -
-                  __hip_atomic_load(&a.heads[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  __hip_atomic_load(&heads[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (__ballot(rem > 0) == 0) {
             base += kWave;
@@ -549,7 +569,7 @@ __device__ int claim(const DevArgs& a, int home) {
         }
         const int victim = __shfl(q, who, kWave);
         int got = -1;
-        if (lane == 0) got = try_claim(a, victim);
+        if (lane == 0) got = try_claim(a, heads, victim);
         got = __shfl(got, 0, kWave);
         if (got >= 0) return got;
     }
@@ -564,38 +584,55 @@ __device__ __forceinline__ ItemDesc no_item() {
 
 // ---- kernels ----------------------------------------------------------------------
 // One launch per step.  Workgroup (queue q, rank j) starts with item j of its
-// queue (no atomic), then claims the next item of its queue at the start of
-// each item (the claim and the next descriptor load overlap the item's own
-// work); once its queue is drained it claims through `claim` (stealing).  The
-// last workgroup to finish resets the heads, sums the checksum partials and
-// advances the step counter.
+// queue (its descriptor is precomputed, so no atomic and no dependent load),
+// then claims the next item of its queue at the start of each item (the claim
+// and the next descriptor load overlap the item's own work); once its queue is
+// drained it claims through `claim` (stealing).  A step needs no end-of-launch
+// work: the step number is kept per workgroup, the claim counters alternate
+// between two sets by step parity (workgroup 0 resets the set of the next
+// step), and the checksum partials of the step are summed by the last
+// workgroup of the next step (or by k_flush), so workgroups simply exit and
+// the launch boundary orders one step before the next.
 template <typename T, int V, int KAHAN, int PIPE>
 __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
-    __shared__ double red[2 * kMaxBlock / kWave];
+    __shared__ double red[kRedLen];
     __shared__ ItemDesc s_desc;
-    __shared__ int s_last;
 
-    const StepInfo si = step_info(a);
-    const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);
-    T* dst = static_cast<T*>((si.step & 1) ? a.field0 : a.field1);
-    const int home = home_queue(a, blockIdx.x);
-    const int rank = queue_rank(a, blockIdx.x);
+    const uint64_t t_launch = wall_clock64();
+    const int wg = blockIdx.x;
+    const uint64_t step = a.wstep[wg];          // equal in every workgroup of the launch
+    const int par = static_cast<int>(step & 1);
+    const StepInfo si = step_info(a, step);
+    const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(par ? a.field0 : a.field1);
+    int* heads = a.heads + par * a.nqueues;
+    double* partials = a.partials + static_cast<int64_t>(par) * a.part_stride;
+    const int home = home_queue(a, wg);
     const int hbeg = a.seg[home];
     const int hn = a.seg[home + 1] - hbeg;
     double busy = 0.0;
 
     uint64_t t_first = 0, t_last = 0;
-    const uint64_t t_launch = wall_clock64();
-    if (threadIdx.x == 0) s_desc = rank < hn ? a.queue[hbeg + rank] : no_item();
+    if (threadIdx.x == 0) s_desc = a.firstd[wg];
+    if (wg == 0) {
+        // the previous step, which used the other set, has ended; the next one uses it
+        int* other = a.heads + (par ^ 1) * a.nqueues;
+        for (int q = threadIdx.x; q < a.nqueues; q += a.block) other[q] = a.head0;
+        if (threadIdx.x == 0) {
+            a.ctrl->pend_n[par] = a.ctrl->nitems;
+            a.ctrl->pend_step[par] = step + 1;
+        }
+    }
+    if (wg == a.nwg - 1) settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
     __syncthreads();
     for (;;) {
         ItemDesc d = s_desc;
         if (d.id < 0) {                      // home queue drained: claim with stealing
             __syncthreads();
             if (threadIdx.x < kWave) {
-                const int qi = claim(a, home);
+                const int qi = claim(a, heads, home);
                 if (threadIdx.x == 0) s_desc = qi >= 0 ? a.queue[qi] : no_item();
             }
             __syncthreads();
@@ -604,7 +641,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
         }
         __syncthreads();                     // every thread holds d before s_desc changes
         int nidx = hn;
-        if (threadIdx.x == 0) nidx = atomicAdd(&a.heads[home], 1);
+        if (threadIdx.x == 0) nidx = atomicAdd(&heads[home], 1);
         ItemDesc nd = no_item();
         auto ahead = [&]() {
             if (threadIdx.x == 0 && nidx < hn) nd = a.queue[hbeg + nidx];
@@ -614,7 +651,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
         const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, src, dst, si.hcx, si.hcy, lds, red, ahead);
         t_last = wall_clock64();
         const double ticks = static_cast<double>(t_last - t_start);  // used by thread 0
-        record_item(a, d, o, ticks);
+        record_item(a, partials, d, o, ticks);
         if (threadIdx.x == 0) {
             busy += ticks;
             s_desc = nd;
@@ -622,21 +659,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        a.wg_busy[blockIdx.x] += busy;
-        uint64_t* tl = a.wg_timeline + 4 * static_cast<size_t>(blockIdx.x);
+        unsafeAtomicAdd(&a.wg_busy[wg], busy);
+        uint64_t* tl = a.wg_timeline + 4 * static_cast<size_t>(wg);
         tl[0] = t_launch;
         tl[1] = t_first ? t_first : t_launch;
         tl[2] = t_last ? t_last : t_launch;
         tl[3] = wall_clock64();
-        __threadfence();
-        const uint32_t prev = atomicAdd(&a.ctrl->done, 1u);
-        s_last = (prev == static_cast<uint32_t>(a.nwg) - 1u);
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        for (int q = threadIdx.x; q < a.nqueues; q += a.block) a.heads[q] = a.head0;
-        finish_step(a, si.step, red, a.block);
+        a.wstep[wg] = step + 1;
     }
 }
 
@@ -646,20 +675,44 @@ __global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
     T* lds = reinterpret_cast<T*>(smem);
     __shared__ double red[2 * kMaxBlock / kWave];
 
-    const StepInfo si = step_info(a);
-    const T* src = static_cast<const T*>((si.step & 1) ? a.field1 : a.field0);
-    T* dst = static_cast<T*>((si.step & 1) ? a.field0 : a.field1);
+    const uint64_t step = a.wstep[0];
+    const int par = static_cast<int>(step & 1);
+    const StepInfo si = step_info(a, step);
+    const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(par ? a.field0 : a.field1);
     const int item = a.item_off[chunk] + blockIdx.x;
     if (item >= a.item_off[chunk + 1]) return;  // grid sized for a larger plan
     const ItemDesc d = a.items[item];
     const uint64_t t_start = wall_clock64();
     const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
-    record_item(a, d, o, static_cast<double>(wall_clock64() - t_start));
+    record_item(a, a.partials + static_cast<int64_t>(par) * a.part_stride, d, o,
+                static_cast<double>(wall_clock64() - t_start));
 }
 
-__global__ __launch_bounds__(256) void k_finish(DevArgs a) {
-    __shared__ double red[256 / kWave];
-    finish_step(a, a.ctrl->step, red, 256);
+// End of a plain step (one workgroup): settle a persistent step still pending
+// in the other buffer, sum this step's partials, reset both claim-counter
+// sets, and move every workgroup's step number on.
+__global__ __launch_bounds__(kSumThreads) void k_finish(DevArgs a) {
+    __shared__ double red[kRedLen];
+    const uint64_t step = a.wstep[0];
+    const int par = static_cast<int>(step & 1);
+    settle_partials(a, par ^ 1, red, kSumThreads);
+    const double total = sum_partials(a.partials + static_cast<int64_t>(par) * a.part_stride,
+                                      static_cast<int>(a.ctrl->nitems), red, kSumThreads);
+    if (threadIdx.x == 0) {
+        a.hist[step % kHistLen] = total;
+        a.ctrl->pend_step[par] = 0;
+    }
+    for (int q = threadIdx.x; q < 2 * a.nqueues; q += kSumThreads) a.heads[q] = a.head0;
+    __syncthreads();                  // every thread has read wstep[0]
+    for (int w = threadIdx.x; w < a.nwg; w += kSumThreads) a.wstep[w] = step + 1;
+}
+
+// Sums the checksum of any persistent step still pending (one workgroup).
+__global__ __launch_bounds__(kSumThreads) void k_flush(DevArgs a) {
+    __shared__ double red[kRedLen];
+    settle_partials(a, 0, red, kSumThreads);
+    settle_partials(a, 1, red, kSumThreads);
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
@@ -685,10 +738,11 @@ __global__ void k_zero(uint32_t* p, size_t nwords) {
 }
 
 __global__ void k_reset_control(DevArgs a) {
-    for (int q = threadIdx.x; q < a.nqueues; q += blockDim.x) a.heads[q] = a.head0;
+    for (int q = threadIdx.x; q < 2 * a.nqueues; q += blockDim.x) a.heads[q] = a.head0;
+    for (int w = threadIdx.x; w < a.nwg; w += blockDim.x) a.wstep[w] = 0;
     if (threadIdx.x == 0) {
-        a.ctrl->done = 0;
-        a.ctrl->step = 0;
+        a.ctrl->pend_step[0] = 0;
+        a.ctrl->pend_step[1] = 0;
     }
 }
 
@@ -772,7 +826,12 @@ int launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitem
 }
 
 int launch_finish(const DevArgs& a, void* stream) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), a);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kSumThreads), 0, static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_flush(const DevArgs& a, void* stream) {
+    hipLaunchKernelGGL(k_flush, dim3(1), dim3(kSumThreads), 0, static_cast<hipStream_t>(stream), a);
     return static_cast<int>(hipGetLastError());
 }
 

@@ -17,10 +17,14 @@ constexpr size_t kMaxLds = 160 * 1024;  // gfx950: 160 KiB of LDS per CU
 
 // Device control block (first bytes of the workspace).
 struct Ctrl {
-    uint32_t done;          // workgroups finished in the current persistent launch
     uint32_t nitems;        // work items of the installed plan
-    uint64_t step;          // steps completed since init
-    uint64_t pad1[6];
+    uint32_t pad0;
+    // The checksum partials of a persistent step are summed during the next
+    // step (or by k_flush): pend_step[p] = 1 + the step whose partials buffer p
+    // holds, 0 once they are summed; pend_n[p] = the items that wrote it.
+    uint64_t pend_step[2];
+    uint32_t pend_n[2];
+    uint64_t pad1[4];
 };
 
 // One work item: a range of rows of one tile, self-contained so that a claim
@@ -43,17 +47,23 @@ struct DevArgs {
     const int32_t* item_off;   // C + 1: items of chunk c are [item_off[c], item_off[c+1])
     const ItemDesc* queue;     // the same items grouped by queue, each queue's in cost order
     const int32_t* seg;        // Q + 1 offsets into queue
-    int32_t* heads;            // Q claim counters; each launch starts them at head0
+    const ItemDesc* firstd;    // nwg: the first item of each workgroup in a step (id -1: none)
+    int32_t* heads;            // 2 x Q claim counters, one set per step parity; a step finds
+                               // its set at head0 and resets the other set for the next step
+    uint64_t* wstep;           // nwg: steps completed, kept by each workgroup (all equal
+                               // between launches)
     Ctrl* ctrl;
     double* loads_work;        // C
     double* loads_time;        // C
-    double* partials;          // per item: sum of the item's outputs in the last step
+    double* partials;          // 2 x part_stride, by step parity: per item, the sum of its
+                               // outputs in that step
     double* hist;              // kHistLen per-step sums
     double* wg_busy;           // nwg
     uint64_t* wg_timeline;     // 4 per workgroup, last persistent launch: start, first item,
                                // end of last item, exit (wall-clock ticks)
     int32_t* visits;           // per tile row: times it was computed
     int64_t ncells;            // cells per field
+    int32_t part_stride;       // items a partials buffer can hold
     int32_t nx, ny, nz, nfields;
     int32_t nqueues, nwg, steal;
     int32_t head0;             // G: the first G items of a queue go one to each of its workgroups
@@ -77,6 +87,7 @@ int  launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, 
 int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitems_chunk,
                         int block, size_t lds, void* stream);
 int  launch_finish(const DevArgs& a, void* stream);
+int  launch_flush(const DevArgs& a, void* stream);
 int  launch_init_field(void* q, int prec, int64_t n, uint64_t seed, void* stream);
 int  launch_zero(void* p, size_t bytes, void* stream);
 int  launch_field_sum(const void* q, int prec, int64_t n, double* partial, double* out,

@@ -52,7 +52,7 @@ struct Plan {
     // workspace layout (byte offsets)
     size_t off_ctrl = 0, off_ktab = 0, off_items = 0, off_itemoff = 0, off_queue = 0, off_seg = 0,
            off_heads = 0, off_lw = 0, off_lt = 0, off_part = 0, off_hist = 0, off_busy = 0, off_tl = 0,
-           off_visits = 0, off_sum = 0, ws_bytes = 0;
+           off_visits = 0, off_sum = 0, off_first = 0, off_wstep = 0, ws_bytes = 0;
     size_t field_bytes = 0;
 };
 
@@ -170,15 +170,17 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_itemoff = take(sizeof(int32_t) * (static_cast<size_t>(p.C) + 1));
     p.off_queue = take(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
     p.off_seg = take(sizeof(int32_t) * (static_cast<size_t>(p.Q) + 1));
-    p.off_heads = take(sizeof(int32_t) * static_cast<size_t>(p.Q));
+    p.off_heads = take(sizeof(int32_t) * 2 * static_cast<size_t>(p.Q));
     p.off_lw = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_lt = take(sizeof(double) * static_cast<size_t>(p.C));
-    p.off_part = take(sizeof(double) * static_cast<size_t>(p.nrows));
+    p.off_part = take(sizeof(double) * 2 * static_cast<size_t>(p.nrows));
     p.off_hist = take(sizeof(double) * kHistLen);
     p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg_cap));
     p.off_tl = take(sizeof(uint64_t) * 4 * static_cast<size_t>(p.nwg_cap));
     p.off_visits = take(sizeof(int32_t) * static_cast<size_t>(p.nrows));
     p.off_sum = take(sizeof(double) * (kSumBlocks + 1));
+    p.off_first = take(sizeof(ItemDesc) * static_cast<size_t>(p.nwg_cap));
+    p.off_wstep = take(sizeof(uint64_t) * static_cast<size_t>(p.nwg_cap));
     p.ws_bytes = o;
     p.field_bytes = static_cast<size_t>(p.ncells) * p.nfields * p.elem;
     return LB_OK;
@@ -369,7 +371,8 @@ int upload_plan(lb_ctx* x, const double* cost) {
     }
     ItemDesc* st_items = static_cast<ItemDesc*>(x->staging);
     ItemDesc* st_queue = st_items + p.nrows;
-    int32_t* st_off = reinterpret_cast<int32_t*>(st_queue + p.nrows);
+    ItemDesc* st_first = st_queue + p.nrows;
+    int32_t* st_off = reinterpret_cast<int32_t*>(st_first + p.nwg_cap);
     int32_t* st_seg = st_off + p.C + 1;
     int32_t* st_n = st_seg + p.Q + 1;
     std::memcpy(st_items, x->items.data(), sizeof(ItemDesc) * n);
@@ -384,6 +387,27 @@ int upload_plan(lb_ctx* x, const double* cost) {
     }
     st_seg[p.Q] = k;
     *st_n = n;
+    // First item of every workgroup: item `rank` of its home queue, with the
+    // same workgroup -> (queue, rank) assignment as the device (home_queue and
+    // queue_rank in kernels.hip).
+    const DevArgs& a = x->args;
+    for (int32_t w = 0; w < p.nwg; ++w) {
+        int home, rank;
+        if (a.xcd_queues) {
+            const int per_xcd = p.Q / 8;
+            home = (w & 7) + 8 * ((w >> 3) % per_xcd);
+            rank = (w >> 3) / per_xcd;
+        } else {
+            home = w % p.Q;
+            rank = w / p.Q;
+        }
+        if (rank < st_seg[home + 1] - st_seg[home]) {
+            st_first[w] = st_queue[st_seg[home] + rank];
+        } else {
+            st_first[w] = ItemDesc{};
+            st_first[w].id = -1;
+        }
+    }
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_items, st_items, sizeof(ItemDesc) * n,
                               hipMemcpyHostToDevice, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_queue, st_queue, sizeof(ItemDesc) * n,
@@ -391,6 +415,8 @@ int upload_plan(lb_ctx* x, const double* cost) {
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_itemoff, st_off, sizeof(int32_t) * (p.C + 1),
                               hipMemcpyHostToDevice, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_seg, st_seg, sizeof(int32_t) * (p.Q + 1),
+                              hipMemcpyHostToDevice, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_first, st_first, sizeof(ItemDesc) * p.nwg,
                               hipMemcpyHostToDevice, x->stream));
     HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_ctrl + offsetof(Ctrl, nitems), st_n, sizeof(int32_t),
                               hipMemcpyHostToDevice, x->stream));
@@ -532,7 +558,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
         return hip_bail(e, "hipStreamCreateWithFlags");
     if ((e = hipEventCreateWithFlags(&x->upload_done, hipEventDisableTiming)) != hipSuccess)
         return hip_bail(e, "hipEventCreateWithFlags");
-    if ((e = hipHostMalloc(&x->staging, sizeof(ItemDesc) * 2 * static_cast<size_t>(P.nrows) +
+    if ((e = hipHostMalloc(&x->staging, sizeof(ItemDesc) * (2 * static_cast<size_t>(P.nrows) + P.nwg_cap) +
                                             sizeof(int32_t) * (static_cast<size_t>(P.C) + P.Q + 3))) != hipSuccess)
         return hip_bail(e, "hipHostMalloc");
 
@@ -555,7 +581,9 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.item_off = reinterpret_cast<const int32_t*>(x->ws + P.off_itemoff);
     a.queue = reinterpret_cast<const ItemDesc*>(x->ws + P.off_queue);
     a.seg = reinterpret_cast<const int32_t*>(x->ws + P.off_seg);
+    a.firstd = reinterpret_cast<const ItemDesc*>(x->ws + P.off_first);
     a.heads = reinterpret_cast<int32_t*>(x->ws + P.off_heads);
+    a.wstep = reinterpret_cast<uint64_t*>(x->ws + P.off_wstep);
     a.ctrl = reinterpret_cast<Ctrl*>(x->ws + P.off_ctrl);
     a.loads_work = reinterpret_cast<double*>(x->ws + P.off_lw);
     a.loads_time = reinterpret_cast<double*>(x->ws + P.off_lt);
@@ -565,6 +593,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.wg_timeline = reinterpret_cast<uint64_t*>(x->ws + P.off_tl);
     a.visits = reinterpret_cast<int32_t*>(x->ws + P.off_visits);
     a.ncells = P.ncells;
+    a.part_stride = P.nrows;
     a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.nfields = P.nfields;
     a.tile_x = P.TX;
     a.block = P.block;
@@ -786,6 +815,8 @@ int lb_fields(lb_ctx* x, int32_t field, void* dst, size_t dst_bytes, double* che
 
 int lb_stats(lb_ctx* x, lb_stats_t* out) {
     if (!x || !out) return fail(x ? &x->err : nullptr, LB_E_INVAL, "ctx and out are required");
+    HIP_TRY(x, hipSetDevice(x->device));
+    LAUNCH_TRY(x, launch_flush(x->args, x->stream));   // the last step's checksum
     int rc = sync(x);
     if (rc != LB_OK) return rc;
     const Plan& p = x->plan;
@@ -850,6 +881,8 @@ int lb_visits(lb_ctx* x, int32_t* out, int32_t n, int32_t reset) {
 
 int lb_checksums(lb_ctx* x, double* out, int32_t n, int32_t* got) {
     if (!x || !out || !got) return fail(x ? &x->err : nullptr, LB_E_INVAL, "ctx, out and got are required");
+    HIP_TRY(x, hipSetDevice(x->device));
+    LAUNCH_TRY(x, launch_flush(x->args, x->stream));   // the last step's checksum
     int rc = sync(x);
     if (rc != LB_OK) return rc;
     const int64_t avail = std::min<int64_t>(x->steps, kHistLen);
