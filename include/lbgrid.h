@@ -118,14 +118,18 @@ typedef struct {
     int32_t item_split;      /* after a rebalance, tiles whose measured cost
                                 exceeds W/(Q*G*item_split) are cut into row
                                 ranges; 0 = never (2)                          */
-    int32_t stage_rows;      /* rows per direct global->LDS batch (nz % 4 == 0
-                                only); 0 = 4 when nz % 4 == 0, else the
-                                register pipeline; -1 = register pipeline      */
+    int32_t stage_rows;      /* > 0: rows per direct global->LDS batch (nz % 4
+                                == 0 only); 0 = 4 when nz % 4 == 0, else the
+                                register pipeline; -1 or -2: register pipeline
+                                with 2 rows in flight; -4, -8: 4 or 8 rows in
+                                flight (nz % 4 == 0, at most 512 threads per
+                                workgroup; -8 in FP32 only)                  */
     int32_t physics;         /* LB_PHYS_POINTWISE | LB_PHYS_VERTICAL (the
                                 latter needs nz/V to divide 64)               */
-    int32_t tail_split;      /* in every queue, the cheapest tiles that make up
-                                the last 1/G of its cost are cut this many
-                                times finer, so a step ends on small items;
+    int32_t tail_split;      /* in every queue, the cheapest tiles whose items
+                                make up the final round of its G workgroups
+                                (its last G items) are cut this many times
+                                finer, so a step ends on small items;
                                 0 or 1 = off (4)                              */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */

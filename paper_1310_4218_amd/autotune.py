@@ -32,7 +32,8 @@ SPACE = {
     "nqueues": [1, 8, 32, 256],
     "wg_per_queue": [0],          # 0: fill the device (resident workgroups / queues)
     "item_split": [0, 1, 2, 4, 8],
-    "stage_rows": [-1, 2, 4, 6, 8],   # -1: register pipeline; n: direct-to-LDS batches of n rows
+    "stage_rows": [-1, -4, -8, 2, 4, 6, 8],   # -1, -4, -8: register pipeline 2/4/8 rows deep;
+                                              # n > 0: direct-to-LDS batches of n rows
     "tail_split": [0, 2, 4, 8],
 }
 

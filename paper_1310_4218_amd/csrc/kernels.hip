@@ -140,11 +140,6 @@ __device__ __forceinline__ void physics_vertical(T eps, int k, int tzq, int NQ, 
 }
 
 // ---- cost field --------------------------------------------------------------
-__device__ __forceinline__ int wrap_mod(int64_t a, int n) {
-    int64_t r = a % n;
-    return static_cast<int>(r < 0 ? r + n : r);
-}
-
 __device__ __forceinline__ int column_k(const DevArgs& a, const int* hcx, const int* hcy, int x,
                                         int y) {
     int k = a.kmin;
@@ -213,6 +208,12 @@ __device__ void block_sum2(double& a, double& b, double* red, int bs) {
 }
 
 // ---- one work item ----------------------------------------------------------------
+constexpr int kPipeDma = 1;   // pipeline template value of the direct global->LDS path
+
+// Largest workgroup of a pipeline.  The deeper register pipelines keep 4 or 8
+// rows in registers, which needs more than the 128 VGPRs a 1024-thread
+// workgroup allows; they are limited to 512 threads (up to 256 VGPRs).
+constexpr int max_block(int pipe) { return pipe >= 4 && pipe != kPipeDma ? kMaxBlockDeep : kMaxBlock; }
 struct ItemOut {
     double checksum;  // sum of the item's outputs over all fields (valid in thread 0)
     double work;      // work units of the item (valid in thread 0)
@@ -242,11 +243,25 @@ __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70)
 
 // One item; `hook` runs in every thread right after the first prologue barrier
 // (the persistent kernel uses it to prefetch the next item's descriptor).
-// PIPE 0: rows move HBM -> registers -> LDS, two rows in flight per workgroup.
-// PIPE 1 (V = 4 only): rows move HBM -> LDS directly, a.stage_rows rows in
-// flight per workgroup, through a ring of 2*stage_rows + 2 LDS rows.
+// PIPE = kPipeDma (V = 4 only): rows move HBM -> LDS directly, a.stage_rows
+//   rows in flight per workgroup, through a ring of 2*stage_rows + 2 LDS rows.
+// PIPE = 2, 4 or 8: rows move HBM -> registers -> LDS with PIPE rows in flight
+//   per workgroup (row r + 2 .. r + 1 + PIPE while row r is computed); the
+//   compiler's own wait counts order each row's registers before its LDS
+//   store, so the pipeline needs no barrier-wide wait for memory.
+// What an item of the direct-load pipeline hands to the next item of its
+// workgroup: during its last block it issues the next item's first rows into
+// the free part of the ring and looks up the next item's trip counts, so that
+// the next item starts with its data in flight or landed.
+struct Carry {
+    int base;   // ring slot of the next item's row -1
+    int pre;    // rows of the next item already issued (rows -1 .. pre - 2); 0 = none
+    int kb;     // trip-count buffer (0 or 1) of the next item
+};
+
 template <typename T, int V, int KAHAN, int PIPE, typename Hook>
-__device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __restrict__ src,
+__device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const ItemDesc& nx_item,
+                                const Carry& cin, Carry& cout, const T* __restrict__ src,
                                 T* __restrict__ dst, const int* hcx, const int* hcy, T* lds,
                                 double* red, Hook hook) {
     const int nz = a.nz, nx = a.nx, ny = a.ny;
@@ -272,19 +287,28 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
     gx1 = gx1 >= nx ? gx1 - nx : gx1;
     const T cc = static_cast<T>(a.cc), cn = static_cast<T>(a.cn), eps = static_cast<T>(a.eps);
 
-    const int RING = PIPE ? 2 * a.stage_rows + 2 : kRingRows;
-    int* kbuf = reinterpret_cast<int*>(lds + RING * RL);
+    constexpr bool kDma = (PIPE == kPipeDma);
+    const int RING = kDma ? 2 * a.stage_rows + 2 : kRingRows;
+    const int KB = TX * a.tile_y;             // one trip-count buffer
+    int* kbuf0 = reinterpret_cast<int*>(lds + RING * RL);
+    int* kbuf = kbuf0 + (kDma ? cin.kb * KB : 0);
+    const int rbase = kDma ? cin.base : 0;
     auto slot = [&](int i) -> T* {              // LDS row of tile-relative row i >= -1
-        return PIPE ? lds + ((i + 1) % RING) * RL : lds + (i & (kRingRows - 1)) * RL;
+        return kDma ? lds + ((rbase + i + 1) % RING) * RL : lds + (i & (kRingRows - 1)) * RL;
     };
-    auto fill_k = [&]() {
-        // Trip counts of the item's columns, looked up once per item; these table
-        // loads are in flight together with the first row loads.
-        for (int i = threadIdx.x; i < w * h; i += BS) {
-            const int r = i / w, c = i - r * w;
-            kbuf[r * TX + c] = column_k(a, hcx, hcy, x0 + c, y0 + r);
+    // Trip counts of an item's columns, looked up once per item; these table
+    // loads are in flight together with row loads.
+    auto fill_k_of = [&](const ItemDesc& it, int* kb) {
+        const int iw = it.wh & 0xffff, ih = it.wh >> 16;
+        for (int i = threadIdx.x; i < iw * ih; i += BS) {
+            const int r = i / iw, c = i - r * iw;
+            kb[r * TX + c] = column_k(a, hcx, hcy, it.x0 + c, it.y0 + r);
         }
     };
+    auto fill_k = [&]() { fill_k_of(d, kbuf); };
+    cout.base = 0;
+    cout.pre = 0;
+    cout.kb = kDma ? cin.kb : 0;
 
     double chk = 0.0, work = 0.0;
     for (int f = 0; f < a.nfields; ++f) {
@@ -345,13 +369,18 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
             if (tzq == 0) work += static_cast<double>(nz) * static_cast<double>(a.alpha + k);
         };
 
-        if constexpr (PIPE == 0) {
-            // Prologue: rows -1, 0, 1 go to the LDS ring, row 2 stays in registers.
-            Vec<T, V> m0, m1, c0, c1, n0, n1, A0, A1, B0, B1;
+        if constexpr (!kDma) {
+            // Prologue: rows -1, 0, 1 go to the LDS ring; rows 2 .. 1 + PIPE stay in
+            // registers, row r in buffer r % PIPE.
+            constexpr int D = PIPE;
+            Vec<T, V> m0, m1, c0, c1, n0, n1;
+            Vec<T, V> R0[D], R1[D];
             fetch(-1, m0, m1);
             fetch(0, c0, c1);
             fetch(1, n0, n1);
-            if (2 <= h) fetch(2, A0, A1);
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if (2 + j <= h) fetch(2 + j, R0[(2 + j) % D], R1[(2 + j) % D]);
             if (f == 0) fill_k();
             put(-1, m0, m1);
             put(0, c0, c1);
@@ -359,60 +388,87 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const T* __
             __syncthreads();
             if (f == 0) hook();
 
-            // Row r: fetch row r+3 (registers), compute row r from the ring, move
-            // row r+2 (fetched one row earlier) into the ring.  Two rows stay in
-            // flight.  Unrolled by two so the register slots keep fixed names.
-            auto row = [&](int r, Vec<T, V>& P0, Vec<T, V>& P1, Vec<T, V>& Q0, Vec<T, V>& Q1) {
-                if (r + 3 <= h) fetch(r + 3, Q0, Q1);
-                compute(r);
-                if (r + 2 <= h) put(r + 2, P0, P1);
-                __syncthreads();
-            };
-            for (int r = 0; r < h; r += 2) {
-                row(r, A0, A1, B0, B1);
-                if (r + 1 < h) row(r + 1, B0, B1, A0, A1);
+            // Row r: compute r from the ring, move row r + 2 from its registers into
+            // the ring (the slot of row r - 2, free since the last barrier) and fetch
+            // row r + 2 + D into the same registers.  Unrolled by D so that every
+            // register buffer keeps a fixed name.
+            for (int r0 = 0; r0 < h; r0 += D) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const int r = r0 + j;
+                    if (r < h) {
+                        const int b = (j + 2) % D;   // == (r + 2) % D: r0 is a multiple of D
+                        compute(r);
+                        if (r + 2 <= h) put(r + 2, R0[b], R1[b]);
+                        if (r + 2 + D <= h) fetch(r + 2 + D, R0[b], R1[b]);
+                        __syncthreads();
+                    }
+                }
             }
         } else {
-            // Direct loads: a row of the item is (w+2) columns of nz*sizeof(T)
+            // Direct loads: a row of an item is (w+2) columns of nz*sizeof(T)
             // bytes, contiguous in LDS, moved as 16-byte chunks.  Chunk c of the
             // row is loaded by thread c mod blockDim; the lanes of one wave fill
             // 64 consecutive chunks, so the wave's LDS base is uniform.
             const int CPC = nz * static_cast<int>(sizeof(T)) / 16;   // chunks per column
-            const int nchunk = (w + 2) * CPC;
             const int lane = threadIdx.x & (kWave - 1);
             const int wave_first0 = threadIdx.x - lane;
             const lds_ptr lds3 = (lds_ptr)lds;  // address-space cast: lds is LDS
-            auto issue = [&](int i) {
-                int gy = y0 + i;
+            // row i of item (ix0, iw, iy0) of field fsrc into ring slot s
+            auto issue_at = [&](const T* fs, int ix0, int iw, int iy0, int i, int s) {
+                const int nchunk = (iw + 2) * CPC;
+                int gy = iy0 + i;
                 gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
                 const unsigned char* row = reinterpret_cast<const unsigned char*>(
-                    fsrc + static_cast<int64_t>(gy) * nx * nz);
-                const int slot_byte = static_cast<int>(
-                    reinterpret_cast<unsigned char*>(slot(i)) - reinterpret_cast<unsigned char*>(lds));
+                    fs + static_cast<int64_t>(gy) * nx * nz);
+                const int slot_byte = s * RL * static_cast<int>(sizeof(T));
                 for (int c0 = 0; c0 < nchunk; c0 += BS) {
                     const int first = c0 + wave_first0;     // wave-uniform
                     if (first >= nchunk) break;
                     const int c = c0 + threadIdx.x;
-                    const int base = __builtin_amdgcn_readfirstlane(slot_byte + first * 16);
+                    const int wbase = __builtin_amdgcn_readfirstlane(slot_byte + first * 16);
                     if (c < nchunk) {
                         const int col = c / CPC, off = c - col * CPC;
-                        int gx = x0 - 1 + col;
+                        int gx = ix0 - 1 + col;
                         gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-                        dma16(row + (static_cast<int64_t>(gx) * nz * sizeof(T) + off * 16), lds3 + base);
+                        dma16(row + (static_cast<int64_t>(gx) * nz * sizeof(T) + off * 16), lds3 + wbase);
                     }
                 }
             };
+            auto issue = [&](int i) { issue_at(fsrc, x0, w, y0, i, (rbase + i + 1) % RING); };
             const int B = a.stage_rows;
-            for (int i = -1; i <= min(B, h); ++i) issue(i);        // rows -1 .. B
-            if (f == 0) fill_k();
+            const bool last_field = (f == a.nfields - 1);
+            // rows -1 .. B, less those the previous item already issued
+            for (int i = (f == 0 ? cin.pre - 1 : -1); i <= min(B, h); ++i) issue(i);
+            if (f == 0 && cin.pre == 0) fill_k();
             for (int r0 = 0; r0 < h; r0 += B) {
                 wait_vmem();            // this thread's loads of rows <= r0 + B have landed
                 __syncthreads();        // ... everyone's; and block r0 - B is done
                 if (f == 0 && r0 == 0) hook();
-                for (int i = r0 + B + 1; i <= min(r0 + 2 * B, h); ++i) issue(i);
+                const bool last_block = r0 + B >= h;
+                bool ahead = false;
+                if (last_block && last_field && nx_item.id >= 0) {
+                    // The ring slots this block does not read (at least B of the
+                    // 2B + 2) take the next item's first rows, in the ring order the
+                    // next item expects: its row -1 right after this item's row h.
+                    const int nh = nx_item.wh >> 16;
+                    const int nb = (rbase + h + 2) % RING;
+                    const int np = min(RING - (h - r0 + 2), min(B, nh) + 2);
+                    for (int i = -1; i <= np - 2; ++i)
+                        issue_at(src, nx_item.x0, nx_item.wh & 0xffff, nx_item.y0, i, (nb + i + 1) % RING);
+                    cout.base = nb;
+                    cout.pre = np;
+                    cout.kb = cin.kb ^ 1;
+                    ahead = true;
+                } else {
+                    for (int i = r0 + B + 1; i <= min(r0 + 2 * B, h); ++i) issue(i);
+                }
                 for (int r = r0; r < min(r0 + B, h); ++r) compute(r);
+                // after the compute, so that waiting for these table loads does not
+                // hold up this block
+                if (ahead) fill_k_of(nx_item, kbuf0 + cout.kb * KB);
             }
-            __syncthreads();            // the ring is free again
+            __syncthreads();            // the ring rows of this item are free again
         }
     }
     block_sum2(chk, work, red, BS);
@@ -429,20 +485,33 @@ struct StepInfo {
     int hcx[kMaxHot], hcy[kMaxHot];
 };
 
-__device__ __forceinline__ StepInfo step_info(const DevArgs& a, uint64_t step) {
+__device__ __forceinline__ StepInfo step_info(const WgState& w) {
     StepInfo s;
-    s.step = step;
-    const int64_t t = a.t0 + static_cast<int64_t>(step);
+    s.step = w.step;
 #pragma unroll
     for (int h = 0; h < kMaxHot; ++h) {
-        s.hcx[h] = h < a.nhot ? wrap_mod(a.hx0[h] + static_cast<int64_t>(a.hvx[h]) * t, a.nx) : 0;
-        s.hcy[h] = h < a.nhot ? wrap_mod(a.hy0[h] + static_cast<int64_t>(a.hvy[h]) * t, a.ny) : 0;
+        s.hcx[h] = w.hx[h];
+        s.hcy[h] = w.hy[h];
     }
     return s;
 }
 
+// The state of the step after `w`: each hotspot moves by its velocity, wrapped.
+__device__ __forceinline__ WgState next_state(const DevArgs& a, const WgState& w) {
+    WgState n;
+    n.step = w.step + 1;
+#pragma unroll
+    for (int h = 0; h < kMaxHot; ++h) {
+        int x = w.hx[h] + a.hvx[h], y = w.hy[h] + a.hvy[h];
+        n.hx[h] = x >= a.nx ? x - a.nx : x;
+        n.hy[h] = y >= a.ny ? y - a.ny : y;
+    }
+    return n;
+}
+
 // Called by every thread after an item.  Thread 0 writes the item's checksum
-// partial and adds its work and ticks to the chunk's loads; the tile rows the
+// partial, adds its work and ticks to the chunk's loads and its work to the
+// tile's (from which the host cuts the next plan's items); the tile rows the
 // item covered each get one visit, one thread per row.  None of these waits
 // for a reply (stores and non-returning atomics), so an item's bookkeeping
 // costs no memory latency.  Exactly one workgroup owns a row in a step, so a
@@ -453,6 +522,7 @@ __device__ __forceinline__ void record_item(const DevArgs& a, double* partials, 
         partials[d.id] = o.checksum;
         unsafeAtomicAdd(&a.loads_work[d.chunk], o.work);
         unsafeAtomicAdd(&a.loads_time[d.chunk], ticks);
+        unsafeAtomicAdd(&a.tile_work[d.tile], o.work);
     }
     for (int r = threadIdx.x; r < (d.wh >> 16); r += a.block)
         __hip_atomic_fetch_add(&a.visits[d.vbase + r], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -583,28 +653,35 @@ __device__ __forceinline__ ItemDesc no_item() {
 }
 
 // ---- kernels ----------------------------------------------------------------------
-// One launch per step.  Workgroup (queue q, rank j) starts with item j of its
-// queue (its descriptor is precomputed, so no atomic and no dependent load),
-// then claims the next item of its queue at the start of each item (the claim
-// and the next descriptor load overlap the item's own work); once its queue is
-// drained it claims through `claim` (stealing).  A step needs no end-of-launch
-// work: the step number is kept per workgroup, the claim counters alternate
-// between two sets by step parity (workgroup 0 resets the set of the next
-// step), and the checksum partials of the step are summed by the last
-// workgroup of the next step (or by k_flush), so workgroups simply exit and
-// the launch boundary orders one step before the next.
+// One launch per step.  The first two rounds of every queue are assigned
+// statically: workgroup (queue q, rank j) starts with item j of its queue and
+// goes on with item 2G - 1 - j (the largest first items pair with the smallest
+// second ones, as a longest-first schedule of two rounds would); both
+// descriptors are precomputed, so the step starts with no atomic and no
+// dependent load.  After that, claims run two items ahead: at the start of
+// every item a workgroup claims one more item of its queue, so that during an
+// item it always knows the item after it and the direct-load pipeline can
+// issue that item's first rows from the current item's last block.  Once its
+// queue is drained a workgroup claims through `claim` (stealing), one item at
+// a time.  A step needs no
+// end-of-launch work: the step number is kept per workgroup, the claim
+// counters alternate between two sets by step parity (workgroup 0 resets the
+// set of the next step), and the checksum partials of the step are summed by
+// the last workgroup of the next step (or by k_flush), so workgroups simply
+// exit and the launch boundary orders one step before the next.
 template <typename T, int V, int KAHAN, int PIPE>
-__global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
+__global__ __launch_bounds__(max_block(PIPE)) void k_persistent(DevArgs a) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
     __shared__ double red[kRedLen];
-    __shared__ ItemDesc s_desc;
+    __shared__ ItemDesc s_cur, s_nxt;
 
     const uint64_t t_launch = wall_clock64();
     const int wg = blockIdx.x;
-    const uint64_t step = a.wstep[wg];          // equal in every workgroup of the launch
+    const WgState ws = a.wstate[wg];            // equal in every workgroup of the launch
+    const uint64_t step = ws.step;
     const int par = static_cast<int>(step & 1);
-    const StepInfo si = step_info(a, step);
+    const StepInfo si = step_info(ws);
     const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
     T* dst = static_cast<T*>(par ? a.field0 : a.field1);
     int* heads = a.heads + par * a.nqueues;
@@ -615,7 +692,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     double busy = 0.0;
 
     uint64_t t_first = 0, t_last = 0;
-    if (threadIdx.x == 0) s_desc = a.firstd[wg];
+    if (threadIdx.x == 0) {
+        s_cur = a.firstd[2 * wg];
+        s_nxt = a.firstd[2 * wg + 1];
+    }
     if (wg == 0) {
         // the previous step, which used the other set, has ended; the next one uses it
         int* other = a.heads + (par ^ 1) * a.nqueues;
@@ -627,35 +707,48 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
     }
     if (wg == a.nwg - 1) settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
     __syncthreads();
+    Carry carry{0, 0, 0};
+    bool drained = false;    // (thread 0) the home queue has nothing left to claim
     for (;;) {
-        ItemDesc d = s_desc;
-        if (d.id < 0) {                      // home queue drained: claim with stealing
+        ItemDesc d = s_cur;
+        ItemDesc nx = s_nxt;
+        if (d.id < 0) {                      // nothing claimed ahead: claim with stealing
             __syncthreads();
             if (threadIdx.x < kWave) {
                 const int qi = claim(a, heads, home);
-                if (threadIdx.x == 0) s_desc = qi >= 0 ? a.queue[qi] : no_item();
+                if (threadIdx.x == 0) s_cur = qi >= 0 ? a.queue[qi] : no_item();
             }
             __syncthreads();
-            d = s_desc;
+            d = s_cur;
+            nx = no_item();
+            carry.pre = 0;
+            drained = true;
             if (d.id < 0) break;
         }
-        __syncthreads();                     // every thread holds d before s_desc changes
+        __syncthreads();                     // every thread holds d and nx before they change
         int nidx = hn;
-        if (threadIdx.x == 0) nidx = atomicAdd(&heads[home], 1);
-        ItemDesc nd = no_item();
+        if (threadIdx.x == 0 && !drained) {
+            nidx = atomicAdd(&heads[home], 1);
+            drained = nidx + 1 >= hn;
+        }
+        ItemDesc na = no_item();
         auto ahead = [&]() {
-            if (threadIdx.x == 0 && nidx < hn) nd = a.queue[hbeg + nidx];
+            if (threadIdx.x == 0 && nidx < hn) na = a.queue[hbeg + nidx];
         };
         const uint64_t t_start = wall_clock64();
         if (t_first == 0) t_first = t_start;
-        const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, src, dst, si.hcx, si.hcy, lds, red, ahead);
+        Carry next;
+        const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, nx, carry, next, src, dst, si.hcx, si.hcy,
+                                                          lds, red, ahead);
         t_last = wall_clock64();
         const double ticks = static_cast<double>(t_last - t_start);  // used by thread 0
         record_item(a, partials, d, o, ticks);
         if (threadIdx.x == 0) {
             busy += ticks;
-            s_desc = nd;
+            s_cur = nx;
+            s_nxt = na;
         }
+        carry = next;
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -665,26 +758,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_persistent(DevArgs a) {
         tl[1] = t_first ? t_first : t_launch;
         tl[2] = t_last ? t_last : t_launch;
         tl[3] = wall_clock64();
-        a.wstep[wg] = step + 1;
+        a.wstate[wg] = next_state(a, ws);
     }
 }
 
 template <typename T, int V, int KAHAN, int PIPE>
-__global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
+__global__ __launch_bounds__(max_block(PIPE)) void k_plain(DevArgs a, int chunk) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
     __shared__ double red[2 * kMaxBlock / kWave];
 
-    const uint64_t step = a.wstep[0];
+    const WgState ws = a.wstate[0];
+    const uint64_t step = ws.step;
     const int par = static_cast<int>(step & 1);
-    const StepInfo si = step_info(a, step);
+    const StepInfo si = step_info(ws);
     const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
     T* dst = static_cast<T*>(par ? a.field0 : a.field1);
     const int item = a.item_off[chunk] + blockIdx.x;
     if (item >= a.item_off[chunk + 1]) return;  // grid sized for a larger plan
     const ItemDesc d = a.items[item];
     const uint64_t t_start = wall_clock64();
-    const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
+    const Carry none{0, 0, 0};
+    Carry unused;
+    const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, no_item(), none, unused, src, dst, si.hcx,
+                                                      si.hcy, lds, red, NoHook{});
     record_item(a, a.partials + static_cast<int64_t>(par) * a.part_stride, d, o,
                 static_cast<double>(wall_clock64() - t_start));
 }
@@ -694,7 +791,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_plain(DevArgs a, int chunk) {
 // sets, and move every workgroup's step number on.
 __global__ __launch_bounds__(kSumThreads) void k_finish(DevArgs a) {
     __shared__ double red[kRedLen];
-    const uint64_t step = a.wstep[0];
+    const WgState ws = a.wstate[0];
+    const uint64_t step = ws.step;
     const int par = static_cast<int>(step & 1);
     settle_partials(a, par ^ 1, red, kSumThreads);
     const double total = sum_partials(a.partials + static_cast<int64_t>(par) * a.part_stride,
@@ -704,8 +802,9 @@ __global__ __launch_bounds__(kSumThreads) void k_finish(DevArgs a) {
         a.ctrl->pend_step[par] = 0;
     }
     for (int q = threadIdx.x; q < 2 * a.nqueues; q += kSumThreads) a.heads[q] = a.head0;
-    __syncthreads();                  // every thread has read wstep[0]
-    for (int w = threadIdx.x; w < a.nwg; w += kSumThreads) a.wstep[w] = step + 1;
+    __syncthreads();                  // every thread has read wstate[0]
+    const WgState nx = next_state(a, ws);
+    for (int w = threadIdx.x; w < a.nwg; w += kSumThreads) a.wstate[w] = nx;
 }
 
 // Sums the checksum of any persistent step still pending (one workgroup).
@@ -739,10 +838,31 @@ __global__ void k_zero(uint32_t* p, size_t nwords) {
 
 __global__ void k_reset_control(DevArgs a) {
     for (int q = threadIdx.x; q < 2 * a.nqueues; q += blockDim.x) a.heads[q] = a.head0;
-    for (int w = threadIdx.x; w < a.nwg; w += blockDim.x) a.wstep[w] = 0;
+    WgState first;
+    first.step = 0;
+#pragma unroll
+    for (int h = 0; h < kMaxHot; ++h) {
+        first.hx[h] = a.hx_first[h];
+        first.hy[h] = a.hy_first[h];
+    }
+    for (int w = threadIdx.x; w < a.nwg; w += blockDim.x) a.wstate[w] = first;
     if (threadIdx.x == 0) {
         a.ctrl->pend_step[0] = 0;
         a.ctrl->pend_step[1] = 0;
+    }
+}
+
+// Table upload: every segment copied word by word, grid-stride.
+struct GatherArgs {
+    GatherSeg seg[kMaxGather];
+    int n;
+};
+__global__ __launch_bounds__(256) void k_gather(GatherArgs g) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (int s = 0; s < g.n; ++s) {
+        const GatherSeg sg = g.seg[s];
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.words; i += stride)
+            sg.dst[i] = sg.src[i];
     }
 }
 
@@ -770,23 +890,31 @@ __global__ __launch_bounds__(256) void k_sum2(const double* partial, int nb, dou
 using PersistentFn = void (*)(DevArgs);
 using PlainFn = void (*)(DevArgs, int);
 
+// pipe: kPipeDma, or the register pipeline's depth (2, 4 or 8 with V = 4, where
+// the host allows 8 in FP32 only: eight FP64 rows do not fit in registers; 2 otherwise)
 template <typename T, int KAHAN>
 PersistentFn persistent_for(int vec, int pipe) {
-    if (pipe) return k_persistent<T, 4, KAHAN, 1>;
-    switch (vec) {
-        case 4: return k_persistent<T, 4, KAHAN, 0>;
-        case 2: return k_persistent<T, 2, KAHAN, 0>;
-        default: return k_persistent<T, 1, KAHAN, 0>;
+    if (vec == 4) {
+        switch (pipe) {
+            case kPipeDma: return k_persistent<T, 4, KAHAN, kPipeDma>;
+            case 8: return k_persistent<T, 4, KAHAN, sizeof(T) == 4 ? 8 : 4>;
+            case 4: return k_persistent<T, 4, KAHAN, 4>;
+            default: return k_persistent<T, 4, KAHAN, 2>;
+        }
     }
+    return vec == 2 ? k_persistent<T, 2, KAHAN, 2> : k_persistent<T, 1, KAHAN, 2>;
 }
 template <typename T, int KAHAN>
 PlainFn plain_for(int vec, int pipe) {
-    if (pipe) return k_plain<T, 4, KAHAN, 1>;
-    switch (vec) {
-        case 4: return k_plain<T, 4, KAHAN, 0>;
-        case 2: return k_plain<T, 2, KAHAN, 0>;
-        default: return k_plain<T, 1, KAHAN, 0>;
+    if (vec == 4) {
+        switch (pipe) {
+            case kPipeDma: return k_plain<T, 4, KAHAN, kPipeDma>;
+            case 8: return k_plain<T, 4, KAHAN, sizeof(T) == 4 ? 8 : 4>;
+            case 4: return k_plain<T, 4, KAHAN, 4>;
+            default: return k_plain<T, 4, KAHAN, 2>;
+        }
     }
+    return vec == 2 ? k_plain<T, 2, KAHAN, 2> : k_plain<T, 1, KAHAN, 2>;
 }
 
 PersistentFn pick_persistent(int prec, int vec, int pipe) {
@@ -800,12 +928,15 @@ PlainFn pick_plain(int prec, int vec, int pipe) {
     return plain_for<float, 0>(vec, pipe);
 }
 
+// the pipeline a launch uses
+int pipe_of(const DevArgs& a) { return a.stage_rows > 0 ? kPipeDma : a.reg_depth; }
+
 }  // namespace
 
 int persistent_occupancy(const DevArgs& a, int prec, int vec, int block, size_t lds) {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(pick_persistent(prec, vec, a.stage_rows > 0)), block,
+            &n, reinterpret_cast<const void*>(pick_persistent(prec, vec, pipe_of(a))), block,
             lds) != hipSuccess)
         return -1;
     return n;
@@ -813,14 +944,14 @@ int persistent_occupancy(const DevArgs& a, int prec, int vec, int block, size_t 
 
 int launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, size_t lds,
                       void* stream) {
-    hipLaunchKernelGGL(pick_persistent(prec, vec, a.stage_rows > 0), dim3(nwg), dim3(block), lds,
+    hipLaunchKernelGGL(pick_persistent(prec, vec, pipe_of(a)), dim3(nwg), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a);
     return static_cast<int>(hipGetLastError());
 }
 
 int launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitems_chunk,
                        int block, size_t lds, void* stream) {
-    hipLaunchKernelGGL(pick_plain(prec, vec, a.stage_rows > 0), dim3(nitems_chunk), dim3(block), lds,
+    hipLaunchKernelGGL(pick_plain(prec, vec, pipe_of(a)), dim3(nitems_chunk), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a, chunk);
     return static_cast<int>(hipGetLastError());
 }
@@ -832,6 +963,21 @@ int launch_finish(const DevArgs& a, void* stream) {
 
 int launch_flush(const DevArgs& a, void* stream) {
     hipLaunchKernelGGL(k_flush, dim3(1), dim3(kSumThreads), 0, static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_gather(const GatherSeg* segs, int n, void* stream) {
+    if (n < 0 || n > kMaxGather) return static_cast<int>(hipErrorInvalidValue);
+    GatherArgs g{};
+    uint32_t most = 0;
+    for (int s = 0; s < n; ++s) {
+        g.seg[s] = segs[s];
+        most = segs[s].words > most ? segs[s].words : most;
+    }
+    g.n = n;
+    const uint32_t want = (most + 255) / 256;
+    const dim3 grid(want < 256 ? (want > 0 ? want : 1) : 256);
+    hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, static_cast<hipStream_t>(stream), g);
     return static_cast<int>(hipGetLastError());
 }
 

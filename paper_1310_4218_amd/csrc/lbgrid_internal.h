@@ -13,6 +13,7 @@ constexpr int kHistLen = 1024;      // per-step checksum ring
 constexpr int kSumBlocks = 1024;    // first pass of the field sum
 constexpr int kRingRows = 4;        // LDS row ring of the tile kernel
 constexpr int kMaxBlock = 1024;
+constexpr int kMaxBlockDeep = 512;  // workgroup limit of the 4- and 8-row register pipelines
 constexpr size_t kMaxLds = 160 * 1024;  // gfx950: 160 KiB of LDS per CU
 
 // Device control block (first bytes of the workspace).
@@ -27,6 +28,15 @@ struct Ctrl {
     uint64_t pad1[4];
 };
 
+// What each workgroup of the persistent launch carries from one step to the
+// next (all workgroups hold the same values between launches): the steps done
+// and the hotspot centres of the next step, so that a launch needs one small
+// load and no division to know its step.
+struct alignas(64) WgState {
+    uint64_t step;
+    int32_t hx[kMaxHot], hy[kMaxHot];
+};
+
 // One work item: a range of rows of one tile, self-contained so that a claim
 // needs a single dependent load.
 struct alignas(16) ItemDesc {
@@ -35,7 +45,8 @@ struct alignas(16) ItemDesc {
     int32_t chunk;
     int32_t id;             // index in chunk order (its checksum partial); -1 = none
     int32_t vbase;          // visit counter of the item's first row
-    int32_t pad0, pad1;
+    int32_t tile;           // the tile the rows belong to (its measured work)
+    int32_t pad1;
 };
 
 // Kernel arguments: every pointer is device memory inside the caller's buffers.
@@ -47,14 +58,15 @@ struct DevArgs {
     const int32_t* item_off;   // C + 1: items of chunk c are [item_off[c], item_off[c+1])
     const ItemDesc* queue;     // the same items grouped by queue, each queue's in cost order
     const int32_t* seg;        // Q + 1 offsets into queue
-    const ItemDesc* firstd;    // nwg: the first item of each workgroup in a step (id -1: none)
+    const ItemDesc* firstd;    // 2 x nwg: the first two items of each workgroup in a step
+                               // (id -1: none)
     int32_t* heads;            // 2 x Q claim counters, one set per step parity; a step finds
                                // its set at head0 and resets the other set for the next step
-    uint64_t* wstep;           // nwg: steps completed, kept by each workgroup (all equal
-                               // between launches)
+    WgState* wstate;           // nwg: step and hotspot centres, kept by each workgroup
     Ctrl* ctrl;
     double* loads_work;        // C
     double* loads_time;        // C
+    double* tile_work;         // ntiles: work units of each tile (rebuilds items from it)
     double* partials;          // 2 x part_stride, by step parity: per item, the sum of its
                                // outputs in that step
     double* hist;              // kHistLen per-step sums
@@ -66,20 +78,31 @@ struct DevArgs {
     int32_t part_stride;       // items a partials buffer can hold
     int32_t nx, ny, nz, nfields;
     int32_t nqueues, nwg, steal;
-    int32_t head0;             // G: the first G items of a queue go one to each of its workgroups
+    int32_t head0;             // 2G: the first 2G items of a queue go two to each of its workgroups
     int32_t tile_x;            // TX
+    int32_t tile_y;            // TY (the trip-count buffers hold TX * TY entries)
     int32_t block;             // threads per workgroup = TX * nz / V (== blockDim.x)
     int32_t stage_rows;        // > 0: rows per direct global->LDS batch (V = 4 only); 0: registers
+    int32_t reg_depth;         // register pipeline: rows in flight (2, 4 or 8; 2 unless V = 4)
     int32_t vertical;          // 1: column physics with the vertical dependency
     int32_t r2cut;
     int32_t kmin;
     int32_t alpha;
     int32_t nhot;
     int32_t xcd_queues;        // 1: queue q is served by workgroups on XCD q % 8
-    int32_t hx0[kMaxHot], hy0[kMaxHot], hvx[kMaxHot], hvy[kMaxHot];
-    int64_t t0;
+    int32_t hx_first[kMaxHot], hy_first[kMaxHot];  // hotspot centres at step 0 (t = t0)
+    int32_t hvx[kMaxHot], hvy[kMaxHot];             // cells per step, reduced to [0, nx), [0, ny)
     double cc, cn, eps;
 };
+
+// One segment of a table upload: `words` 32-bit words from src (pinned host
+// memory as the device addresses it) to dst (device memory).
+struct GatherSeg {
+    const uint32_t* src;
+    uint32_t* dst;
+    uint32_t words;
+};
+constexpr int kMaxGather = 8;
 
 // Kernel launchers (kernels.hip).  prec: 0 FP32, 1 FP32 Kahan, 2 FP64.
 int  launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, size_t lds,
@@ -88,6 +111,7 @@ int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nite
                         int block, size_t lds, void* stream);
 int  launch_finish(const DevArgs& a, void* stream);
 int  launch_flush(const DevArgs& a, void* stream);
+int  launch_gather(const GatherSeg* segs, int n, void* stream);   // n <= kMaxGather
 int  launch_init_field(void* q, int prec, int64_t n, uint64_t seed, void* stream);
 int  launch_zero(void* p, size_t bytes, void* stream);
 int  launch_field_sum(const void* q, int prec, int64_t n, double* partial, double* out,

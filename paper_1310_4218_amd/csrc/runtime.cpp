@@ -41,6 +41,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Plan {
     int32_t nx = 0, ny = 0, nz = 0, nfields = 1, px = 0, py = 0, C = 0, S = 0, Q = 0, G = 0, nwg = 0;
     int32_t nwg_cap = 0;    // workgroup counters sized for this many
+    int32_t RD = 2;         // register pipeline depth (rows in flight)
     int32_t prec = 0, vec = 1, elem = 4, TX = 16, TY = 16, block = 0, ntiles = 0;
     int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
     int32_t B = 0;          // rows per direct global->LDS batch; 0 = register pipeline
@@ -51,8 +52,10 @@ struct Plan {
     std::vector<int32_t> xs, ys;
     // workspace layout (byte offsets)
     size_t off_ctrl = 0, off_ktab = 0, off_items = 0, off_itemoff = 0, off_queue = 0, off_seg = 0,
-           off_heads = 0, off_lw = 0, off_lt = 0, off_part = 0, off_hist = 0, off_busy = 0, off_tl = 0,
-           off_visits = 0, off_sum = 0, off_first = 0, off_wstep = 0, ws_bytes = 0;
+           off_heads = 0, off_lw = 0, off_lt = 0, off_tw = 0, off_part = 0, off_hist = 0, off_busy = 0, off_tl = 0,
+           off_visits = 0, off_sum = 0, off_first = 0, off_wstate = 0, ws_bytes = 0;
+    size_t st_loads = 0, st_tiles = 0, st_items = 0, st_queue = 0, st_first = 0, st_off = 0, st_seg = 0, st_n = 0,
+           st_bytes = 0;  // pinned staging layout
     size_t field_bytes = 0;
 };
 
@@ -61,6 +64,18 @@ bool strictly_increasing(const std::vector<int32_t>& s, int32_t n) {
     for (size_t i = 1; i < s.size(); ++i)
         if (s[i] <= s[i - 1]) return false;
     return true;
+}
+
+// a mod n in [0, n)
+int32_t wrap(int64_t a, int32_t n) {
+    const int64_t r = a % n;
+    return static_cast<int32_t>(r < 0 ? r + n : r);
+}
+
+// (x0 + v*t) mod n without overflow: every factor is reduced first, so the
+// product stays below n^2 <= 2^62.
+int32_t moved(int32_t x0, int32_t v, int64_t t, int32_t n) {
+    return wrap(static_cast<int64_t>(wrap(x0, n)) + static_cast<int64_t>(wrap(v, n)) * wrap(t, n), n);
 }
 
 // Largest r^2 whose table entry can exceed kmin, plus one: beyond it
@@ -92,7 +107,9 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->steal != 0 && c->steal != 1) return bad("steal must be 0 or 1");
     if (c->item_split < 0 || c->item_split > 64) return bad("item_split must be in [0, 64]");
     if (c->tail_split < 0 || c->tail_split > 64) return bad("tail_split must be in [0, 64]");
-    if (c->stage_rows < -1 || c->stage_rows > 32) return bad("stage_rows must be in [-1, 32]");
+    if (c->stage_rows < -8 || c->stage_rows > 32 ||
+        (c->stage_rows < -2 && c->stage_rows != -4 && c->stage_rows != -8))
+        return bad("stage_rows must be -8, -4, -2, -1 (register pipeline) or in [0, 32]");
     if (c->physics != LB_PHYS_POINTWISE && c->physics != LB_PHYS_VERTICAL) return bad("physics");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
@@ -117,22 +134,30 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
                     "vertical physics needs nz / V to divide 64 (V = 4, 2 or 1 by divisibility of nz)");
     // pipeline: direct global->LDS batches of B rows (V = 4 only) or the register path
     if (c->stage_rows > 0 && p.vec != 4) return bad("stage_rows > 0 needs nz divisible by 4");
+    if (c->stage_rows < -2 && p.vec != 4) return bad("register pipeline depth 4 or 8 needs nz divisible by 4");
+    if (c->stage_rows == -8 && p.prec == LB_FP64) return bad("register pipeline depth 8 is FP32 only");
     p.B = c->stage_rows > 0 ? c->stage_rows : (c->stage_rows == 0 && p.vec == 4 ? 4 : 0);
+    p.RD = c->stage_rows < -2 ? -c->stage_rows : 2;
     p.ring = p.B > 0 ? 2 * p.B + 2 : kRingRows;
     p.TY = c->tile_y > 0 ? c->tile_y : 16;
     const size_t col_bytes = static_cast<size_t>(p.nz) * p.elem;
-    auto lds_for = [&](int tx) {  // LDS: the row ring, then one trip count per tile column
-        return static_cast<size_t>(p.ring) * (tx + 2) * col_bytes + sizeof(int32_t) * static_cast<size_t>(tx) * p.TY;
+    auto lds_for = [&](int tx) {  // LDS: the row ring, then trip counts of one tile (two for
+                                  // the direct-load pipeline, which looks one item ahead)
+        return static_cast<size_t>(p.ring) * (tx + 2) * col_bytes +
+               sizeof(int32_t) * static_cast<size_t>(tx) * p.TY * (p.B > 0 ? 2 : 1);
     };
     if (c->tile_x > 0) {
         p.TX = c->tile_x;
     } else {
         p.TX = 16;
-        while (p.TX > 1 && (p.TX * NQ > kMaxBlock || lds_for(p.TX) > 64 * 1024)) --p.TX;
+        const int most = (p.B == 0 && p.RD >= 4) ? kMaxBlockDeep : kMaxBlock;
+        while (p.TX > 1 && (p.TX * NQ > most || lds_for(p.TX) > 64 * 1024)) --p.TX;
     }
     if (p.TX > 1024 || p.TY > 256) return bad("tile sizes must be at most 1024 x 256");
     p.block = p.TX * NQ;
     if (p.block > kMaxBlock) return bad("tile_x * nz / vector width exceeds 1024 threads");
+    if (p.B == 0 && p.RD >= 4 && p.block > kMaxBlockDeep)
+        return bad("register pipeline depth 4 or 8 needs tile_x * nz / 4 <= 512 threads");
     p.lds = lds_for(p.TX);
     if (p.lds > kMaxLds) return bad("tile too large: the LDS row ring and trip counts exceed 160 KiB");
 
@@ -171,17 +196,31 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_queue = take(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
     p.off_seg = take(sizeof(int32_t) * (static_cast<size_t>(p.Q) + 1));
     p.off_heads = take(sizeof(int32_t) * 2 * static_cast<size_t>(p.Q));
+    // loads (work, time) and busy time are adjacent: a measurement clears them in one launch
     p.off_lw = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_lt = take(sizeof(double) * static_cast<size_t>(p.C));
+    p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg_cap));
+    p.off_tw = take(sizeof(double) * static_cast<size_t>(p.ntiles));
     p.off_part = take(sizeof(double) * 2 * static_cast<size_t>(p.nrows));
     p.off_hist = take(sizeof(double) * kHistLen);
-    p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg_cap));
     p.off_tl = take(sizeof(uint64_t) * 4 * static_cast<size_t>(p.nwg_cap));
     p.off_visits = take(sizeof(int32_t) * static_cast<size_t>(p.nrows));
     p.off_sum = take(sizeof(double) * (kSumBlocks + 1));
-    p.off_first = take(sizeof(ItemDesc) * static_cast<size_t>(p.nwg_cap));
-    p.off_wstep = take(sizeof(uint64_t) * static_cast<size_t>(p.nwg_cap));
+    p.off_first = take(sizeof(ItemDesc) * 2 * static_cast<size_t>(p.nwg_cap));
+    p.off_wstate = take(sizeof(WgState) * static_cast<size_t>(p.nwg_cap));
     p.ws_bytes = o;
+    // pinned staging: measured loads, then the plan tables of an upload
+    size_t h = 0;
+    auto htake = [&](size_t bytes) { size_t at = h; h = (h + bytes + 31) & ~size_t{31}; return at; };
+    p.st_loads = htake(sizeof(double) * static_cast<size_t>(p.C));
+    p.st_tiles = htake(sizeof(double) * static_cast<size_t>(p.ntiles));
+    p.st_items = htake(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
+    p.st_queue = htake(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
+    p.st_first = htake(sizeof(ItemDesc) * 2 * static_cast<size_t>(p.nwg_cap));
+    p.st_off = htake(sizeof(int32_t) * (static_cast<size_t>(p.C) + 1));
+    p.st_seg = htake(sizeof(int32_t) * (static_cast<size_t>(p.Q) + 1));
+    p.st_n = htake(sizeof(int32_t));
+    p.st_bytes = h;
     p.field_bytes = static_cast<size_t>(p.ncells) * p.nfields * p.elem;
     return LB_OK;
 }
@@ -206,11 +245,13 @@ struct lb_ctx {
     int64_t plain_graph_version = -1;
     std::vector<int32_t> map;         // C
     std::vector<double> measured;     // loads kept by the last lb_measure
+    std::vector<double> tile_measured;  // work of every tile in the same window
     bool have_measured = false;
     int64_t steps = 0;
     int64_t window_steps = 0;
     double clock_hz = 100e6;
-    void* staging = nullptr;          // pinned: items, queue, item_off, seg, nitems
+    char* staging = nullptr;          // pinned: measured loads and the plan tables (Plan::st_*)
+    const char* staging_dev = nullptr;  // the same memory as the device addresses it
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
@@ -283,53 +324,57 @@ std::vector<int32_t> build_cost_table(const lb_config& c, int32_t r2cut) {
 }
 
 // Work plan for a map and per-chunk costs (NULL: equal costs, no splitting).
-//  - Items: a tile whose estimated cost exceeds W / (nwg * item_split) is cut into
-//    that many row ranges (at most one per row), so that no single item outlasts
-//    the rest of the step; cheap tiles stay whole, which keeps their halo
-//    overhead low.  Tile cost = chunk cost * tile area / chunk area.
+//  - Items: a tile whose cost exceeds W / (nwg * item_split) is cut into that
+//    many row ranges (at most one per row), so that no single item outlasts the
+//    rest of the step; cheap tiles stay whole, which keeps their halo overhead
+//    low.  After a measurement the tile cost is the tile's own measured work
+//    (the load measurement of Section V taken per tile as well as per chunk);
+//    with caller-given chunk costs it is chunk cost * tile area / chunk area.
 //  - Queues: each slot gets the items of its chunks in descending item cost,
 //    ties in item order (chunk id, tile raster, first row).
-int upload_plan(lb_ctx* x, const double* cost) {
+int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     const Plan& p = x->plan;
-    double W = 0.0;
-    if (cost)
-        for (int32_t c = 0; c < p.C; ++c) W += cost[c];
-    const int split = x->cfg.item_split;
-    const double target = (cost && split > 0 && W > 0.0) ? W / (static_cast<double>(p.nwg) * split) : 0.0;
 
-    // Estimated cost of every tile: its chunk's measured cost times its share of
-    // the chunk's area; without measurements, the tile's area.
+    // Cost of every tile: its measured work when the plan follows a measurement;
+    // else its chunk's cost times its share of the chunk's area; without costs,
+    // the tile's area (and no splitting).
     std::vector<double> tcost(static_cast<size_t>(p.ntiles));
     std::vector<int> pieces(static_cast<size_t>(p.ntiles), 1);
+    double W = 0.0;
     for (int32_t c = 0; c < p.C; ++c) {
         const int i = c % p.px, j = c / p.px;
         const double area_c = static_cast<double>(p.xs[i + 1] - p.xs[i]) * (p.ys[j + 1] - p.ys[j]);
         for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) {
             const int w = x->tiles[4 * t + 2] & 0xffff, h = x->tiles[4 * t + 2] >> 16;
             const double area_t = static_cast<double>(w) * h;
-            tcost[t] = cost ? cost[c] * (area_t / area_c) : area_t;
-            if (target > 0.0 && tcost[t] > target)
-                pieces[t] = static_cast<int>(std::min<double>(h, std::ceil(tcost[t] / target)));
+            tcost[t] = tile_cost ? tile_cost[t] : cost ? cost[c] * (area_t / area_c) : area_t;
+            W += tcost[t];
         }
     }
-    // Tail: in every queue, the cheapest tiles whose pieces make up the last
-    // 1/G of the queue's cost (the final round of its G workgroups) are cut
-    // tail_split times finer, so the step ends on small items.
+    const int split = x->cfg.item_split;
+    const bool costed = (cost || tile_cost) && split > 0 && W > 0.0;
+    const double target = costed ? W / (static_cast<double>(p.nwg) * split) : 0.0;
+    if (target > 0.0)
+        for (int32_t t = 0; t < p.ntiles; ++t) {
+            const int h = x->tiles[4 * t + 2] >> 16;
+            if (tcost[t] > target) pieces[t] = static_cast<int>(std::min<double>(h, std::ceil(tcost[t] / target)));
+        }
+    // Tail: in every queue, the cheapest tiles whose pieces make up the final
+    // round of its G workgroups (the last G items in cost order) are cut
+    // tail_split times finer, so the step ends on small items and the
+    // workgroups finish together instead of one item apart.
     const int tail = x->cfg.tail_split;
     if (tail > 1) {
         std::vector<std::vector<int32_t>> qt(static_cast<size_t>(p.Q));
         for (int32_t c = 0; c < p.C; ++c)
             for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) qt[x->map[c] % p.Q].push_back(t);
         for (auto& v : qt) {
-            double Wq = 0.0;
-            for (int32_t t : v) Wq += tcost[t];
             std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
                 return tcost[a] / pieces[a] > tcost[b] / pieces[b];
             });
-            const double share = Wq / std::max(p.G, 1);
-            double acc = 0.0;
-            for (auto it = v.rbegin(); it != v.rend() && acc < share; ++it) {
-                acc += tcost[*it];
+            int64_t covered = 0;
+            for (auto it = v.rbegin(); it != v.rend() && covered < p.G; ++it) {
+                covered += pieces[*it];
                 const int h = x->tiles[4 * *it + 2] >> 16;
                 pieces[*it] = std::min(h, pieces[*it] * tail);
             }
@@ -352,6 +397,7 @@ int upload_plan(lb_ctx* x, const double* cost) {
                 d.chunk = c;
                 d.id = static_cast<int32_t>(x->items.size());
                 d.vbase = x->row_base[t] + r0;
+                d.tile = t;
                 x->items.push_back(d);
                 item_cost.push_back(tcost[t] * (r1 - r0) / h);
             }
@@ -369,12 +415,12 @@ int upload_plan(lb_ctx* x, const double* cost) {
         HIP_TRY(x, hipEventSynchronize(x->upload_done));
         x->upload_pending = false;
     }
-    ItemDesc* st_items = static_cast<ItemDesc*>(x->staging);
-    ItemDesc* st_queue = st_items + p.nrows;
-    ItemDesc* st_first = st_queue + p.nrows;
-    int32_t* st_off = reinterpret_cast<int32_t*>(st_first + p.nwg_cap);
-    int32_t* st_seg = st_off + p.C + 1;
-    int32_t* st_n = st_seg + p.Q + 1;
+    ItemDesc* st_items = reinterpret_cast<ItemDesc*>(x->staging + p.st_items);
+    ItemDesc* st_queue = reinterpret_cast<ItemDesc*>(x->staging + p.st_queue);
+    ItemDesc* st_first = reinterpret_cast<ItemDesc*>(x->staging + p.st_first);
+    int32_t* st_off = reinterpret_cast<int32_t*>(x->staging + p.st_off);
+    int32_t* st_seg = reinterpret_cast<int32_t*>(x->staging + p.st_seg);
+    int32_t* st_n = reinterpret_cast<int32_t*>(x->staging + p.st_n);
     std::memcpy(st_items, x->items.data(), sizeof(ItemDesc) * n);
     std::memcpy(st_off, x->item_off.data(), sizeof(int32_t) * x->item_off.size());
     int32_t k = 0;
@@ -387,10 +433,12 @@ int upload_plan(lb_ctx* x, const double* cost) {
     }
     st_seg[p.Q] = k;
     *st_n = n;
-    // First item of every workgroup: item `rank` of its home queue, with the
-    // same workgroup -> (queue, rank) assignment as the device (home_queue and
-    // queue_rank in kernels.hip).
+    // First two items of every workgroup: items `rank` and 2G - 1 - rank of its
+    // home queue, with the same workgroup -> (queue, rank) assignment as the
+    // device (home_queue in kernels.hip).
     const DevArgs& a = x->args;
+    ItemDesc none{};
+    none.id = -1;
     for (int32_t w = 0; w < p.nwg; ++w) {
         int home, rank;
         if (a.xcd_queues) {
@@ -401,25 +449,26 @@ int upload_plan(lb_ctx* x, const double* cost) {
             home = w % p.Q;
             rank = w / p.Q;
         }
-        if (rank < st_seg[home + 1] - st_seg[home]) {
-            st_first[w] = st_queue[st_seg[home] + rank];
-        } else {
-            st_first[w] = ItemDesc{};
-            st_first[w].id = -1;
-        }
+        const int nq = st_seg[home + 1] - st_seg[home];
+        const int second = 2 * p.G - 1 - rank;
+        st_first[2 * w] = rank < nq ? st_queue[st_seg[home] + rank] : none;
+        st_first[2 * w + 1] = second < nq ? st_queue[st_seg[home] + second] : none;
     }
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_items, st_items, sizeof(ItemDesc) * n,
-                              hipMemcpyHostToDevice, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_queue, st_queue, sizeof(ItemDesc) * n,
-                              hipMemcpyHostToDevice, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_itemoff, st_off, sizeof(int32_t) * (p.C + 1),
-                              hipMemcpyHostToDevice, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_seg, st_seg, sizeof(int32_t) * (p.Q + 1),
-                              hipMemcpyHostToDevice, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_first, st_first, sizeof(ItemDesc) * p.nwg,
-                              hipMemcpyHostToDevice, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(x->ws + p.off_ctrl + offsetof(Ctrl, nitems), st_n, sizeof(int32_t),
-                              hipMemcpyHostToDevice, x->stream));
+    // One kernel moves all tables from the pinned staging (read over the bus) into
+    // the workspace: a single launch instead of one copy per table.
+    auto seg = [&](size_t st, size_t off, size_t bytes) {
+        return GatherSeg{reinterpret_cast<const uint32_t*>(x->staging_dev + st),
+                         reinterpret_cast<uint32_t*>(x->ws + off), static_cast<uint32_t>(bytes / 4)};
+    };
+    const GatherSeg segs[] = {
+        seg(p.st_items, p.off_items, sizeof(ItemDesc) * n),
+        seg(p.st_queue, p.off_queue, sizeof(ItemDesc) * n),
+        seg(p.st_first, p.off_first, sizeof(ItemDesc) * 2 * p.nwg),
+        seg(p.st_off, p.off_itemoff, sizeof(int32_t) * (p.C + 1)),
+        seg(p.st_seg, p.off_seg, sizeof(int32_t) * (p.Q + 1)),
+        seg(p.st_n, p.off_ctrl + offsetof(Ctrl, nitems), sizeof(int32_t)),
+    };
+    LAUNCH_TRY(x, launch_gather(segs, static_cast<int>(sizeof(segs) / sizeof(segs[0])), x->stream));
     HIP_TRY(x, hipEventRecord(x->upload_done, x->stream));
     x->upload_pending = true;
     ++x->plan_version;
@@ -558,9 +607,15 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
         return hip_bail(e, "hipStreamCreateWithFlags");
     if ((e = hipEventCreateWithFlags(&x->upload_done, hipEventDisableTiming)) != hipSuccess)
         return hip_bail(e, "hipEventCreateWithFlags");
-    if ((e = hipHostMalloc(&x->staging, sizeof(ItemDesc) * (2 * static_cast<size_t>(P.nrows) + P.nwg_cap) +
-                                            sizeof(int32_t) * (static_cast<size_t>(P.C) + P.Q + 3))) != hipSuccess)
-        return hip_bail(e, "hipHostMalloc");
+    {
+        void* st = nullptr;
+        if ((e = hipHostMalloc(&st, P.st_bytes, hipHostMallocMapped | hipHostMallocPortable)) != hipSuccess)
+            return hip_bail(e, "hipHostMalloc");
+        x->staging = static_cast<char*>(st);
+        void* dev = nullptr;
+        if ((e = hipHostGetDevicePointer(&dev, st, 0)) != hipSuccess) return hip_bail(e, "hipHostGetDevicePointer");
+        x->staging_dev = static_cast<const char*>(dev);
+    }
 
     int lds_limit = 0;
     if ((e = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, x->device)) != hipSuccess)
@@ -583,10 +638,11 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.seg = reinterpret_cast<const int32_t*>(x->ws + P.off_seg);
     a.firstd = reinterpret_cast<const ItemDesc*>(x->ws + P.off_first);
     a.heads = reinterpret_cast<int32_t*>(x->ws + P.off_heads);
-    a.wstep = reinterpret_cast<uint64_t*>(x->ws + P.off_wstep);
+    a.wstate = reinterpret_cast<WgState*>(x->ws + P.off_wstate);
     a.ctrl = reinterpret_cast<Ctrl*>(x->ws + P.off_ctrl);
     a.loads_work = reinterpret_cast<double*>(x->ws + P.off_lw);
     a.loads_time = reinterpret_cast<double*>(x->ws + P.off_lt);
+    a.tile_work = reinterpret_cast<double*>(x->ws + P.off_tw);
     a.partials = reinterpret_cast<double*>(x->ws + P.off_part);
     a.hist = reinterpret_cast<double*>(x->ws + P.off_hist);
     a.wg_busy = reinterpret_cast<double*>(x->ws + P.off_busy);
@@ -596,8 +652,10 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.part_stride = P.nrows;
     a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.nfields = P.nfields;
     a.tile_x = P.TX;
+    a.tile_y = P.TY;
     a.block = P.block;
     a.stage_rows = P.B;
+    a.reg_depth = P.RD;
     a.vertical = cfg->physics == LB_PHYS_VERTICAL ? 1 : 0;
     if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
         int ncu = 0;
@@ -616,17 +674,20 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
             W.nwg = W.Q * W.G;
         }
     }
-    a.nqueues = P.Q; a.nwg = P.nwg; a.steal = cfg->steal; a.head0 = P.G;
+    a.nqueues = P.Q; a.nwg = P.nwg; a.steal = cfg->steal; a.head0 = 2 * P.G;
     a.r2cut = P.r2cut;
     a.kmin = cfg->kmin;
     a.alpha = cfg->alpha_work;
     a.nhot = cfg->nhot;
     a.xcd_queues = (P.Q % 8 == 0 && P.nwg % 8 == 0) ? 1 : 0;
     for (int h = 0; h < kMaxHot; ++h) {
-        a.hx0[h] = cfg->hx0[h]; a.hy0[h] = cfg->hy0[h];
-        a.hvx[h] = cfg->hvx[h]; a.hvy[h] = cfg->hvy[h];
+        // centres at step 0 (t = t0) and velocities, reduced into the grid on the host
+        const bool on = h < cfg->nhot;
+        a.hx_first[h] = on ? moved(cfg->hx0[h], cfg->hvx[h], cfg->t0, P.nx) : 0;
+        a.hy_first[h] = on ? moved(cfg->hy0[h], cfg->hvy[h], cfg->t0, P.ny) : 0;
+        a.hvx[h] = on ? wrap(cfg->hvx[h], P.nx) : 0;
+        a.hvy[h] = on ? wrap(cfg->hvy[h], P.ny) : 0;
     }
-    a.t0 = cfg->t0;
     a.cc = cfg->c_center; a.cn = cfg->c_nbr; a.eps = cfg->eps;
 
     x->err.clear();
@@ -645,7 +706,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     }
     x->map.assign(static_cast<size_t>(P.C), 0);
     block_map(P.C, P.S, x->map.data());
-    if ((r = upload_plan(x, nullptr)) != LB_OK) {
+    if ((r = upload_plan(x, nullptr, nullptr)) != LB_OK) {
         g_err = x->err;
         return bail(r);
     }
@@ -704,20 +765,25 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
 int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
     if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
     if (source != LB_LOAD_WORK && source != LB_LOAD_TIME) return fail(&x->err, LB_E_INVAL, "unknown load source");
+    const Plan& p = x->plan;
+    HIP_TRY(x, hipSetDevice(x->device));
+    // the loads land in pinned staging after the window's last step, the counters
+    // are cleared behind them, and one synchronisation covers both
+    double* st = reinterpret_cast<double*>(x->staging + p.st_loads);
+    double* stt = reinterpret_cast<double*>(x->staging + p.st_tiles);
+    HIP_TRY(x, hipMemcpyAsync(st, x->ws + (source == LB_LOAD_WORK ? p.off_lw : p.off_lt),
+                              sizeof(double) * p.C, hipMemcpyDeviceToHost, x->stream));
+    HIP_TRY(x, hipMemcpyAsync(stt, x->ws + p.off_tw, sizeof(double) * p.ntiles, hipMemcpyDeviceToHost,
+                              x->stream));
+    if (reset)  // work, time, busy and tile counters are adjacent in the workspace
+        LAUNCH_TRY(x, launch_zero(x->ws + p.off_lw, p.off_tw + sizeof(double) * p.ntiles - p.off_lw, x->stream));
     int rc = sync(x);
     if (rc != LB_OK) return rc;
-    const Plan& p = x->plan;
-    x->measured.resize(static_cast<size_t>(p.C));
-    HIP_TRY(x, hipMemcpy(x->measured.data(), x->ws + (source == LB_LOAD_WORK ? p.off_lw : p.off_lt),
-                         sizeof(double) * p.C, hipMemcpyDeviceToHost));
+    x->measured.assign(st, st + p.C);
+    x->tile_measured.assign(stt, stt + p.ntiles);
     x->have_measured = true;
     if (loads_out) std::memcpy(loads_out, x->measured.data(), sizeof(double) * p.C);
-    if (reset) {
-        LAUNCH_TRY(x, launch_zero(x->ws + p.off_lw, sizeof(double) * p.C, x->stream));
-        LAUNCH_TRY(x, launch_zero(x->ws + p.off_lt, sizeof(double) * p.C, x->stream));
-        LAUNCH_TRY(x, launch_zero(x->ws + p.off_busy, sizeof(double) * p.nwg, x->stream));
-        x->window_steps = 0;
-    }
+    if (reset) x->window_steps = 0;
     return LB_OK;
 }
 
@@ -768,7 +834,9 @@ int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* lo
     const double after = imbalance(w, nm.data(), p.C, p.S);
     x->map = nm;
     HIP_TRY(x, hipSetDevice(x->device));
-    if ((rc = upload_plan(x, w)) != LB_OK) return rc;
+    // measured loads come with the measured work of every tile, which cuts the items
+    const double* tw = (!loads && !x->tile_measured.empty()) ? x->tile_measured.data() : nullptr;
+    if ((rc = upload_plan(x, w, tw)) != LB_OK) return rc;
     if (map_out) std::memcpy(map_out, nm.data(), sizeof(int32_t) * p.C);
     if (nmigrated) *nmigrated = mig;
     if (lam) {
@@ -789,7 +857,7 @@ int lb_set_map(lb_ctx* x, const int32_t* map, const double* cost) {
             if (!(cost[c] >= 0.0)) return fail(&x->err, LB_E_INVAL, "costs must be >= 0");
     x->map.assign(map, map + p.C);
     HIP_TRY(x, hipSetDevice(x->device));
-    return upload_plan(x, cost);
+    return upload_plan(x, cost, nullptr);
 }
 
 int lb_fields(lb_ctx* x, int32_t field, void* dst, size_t dst_bytes, double* checksum_out) {

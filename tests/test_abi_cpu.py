@@ -69,6 +69,33 @@ def test_query_rejects_bad_config(lib, field, value, msg):
     assert msg in lib.lb_last_error(None).decode()
 
 
+@pytest.mark.parametrize("over,msg", [
+    (dict(stage_rows=-3), "stage_rows"), (dict(stage_rows=-16), "stage_rows"),
+    (dict(stage_rows=33), "stage_rows"), (dict(stage_rows=-8, precision=2), "FP32 only"),
+    (dict(stage_rows=-4, nz=6), "divisible by 4"), (dict(stage_rows=2, nz=6), "divisible by 4"),
+    (dict(stage_rows=-4, tile_x=80), "512 threads"),
+])
+def test_query_rejects_bad_pipeline(lib, over, msg):
+    """Register pipeline depths are 2, 4 or 8 rows; the deep ones need V = 4 and
+    workgroups of at most 512 threads, and depth 8 is FP32 only."""
+    cfg, keep = _abi.config_from_workload(W.small())
+    for k, v in over.items():
+        setattr(cfg, k, v)
+    b = _abi.LbBuffers()
+    assert lib.lb_query(C.byref(cfg), C.byref(b)) == _abi.LB_E_INVAL
+    assert msg in lib.lb_last_error(None).decode()
+
+
+def test_query_accepts_pipeline_depths(lib):
+    for over in (dict(stage_rows=-1), dict(stage_rows=-2), dict(stage_rows=-4),
+                 dict(stage_rows=-8), dict(stage_rows=-4, precision=2), dict(stage_rows=6)):
+        cfg, keep = _abi.config_from_workload(W.small())
+        for k, v in over.items():
+            setattr(cfg, k, v)
+        b = _abi.LbBuffers()
+        assert lib.lb_query(C.byref(cfg), C.byref(b)) == _abi.LB_OK, over
+
+
 def test_query_rejects_bad_splits(lib):
     for xs in ([0, 10, 10, 64], [0, 20, 40, 63], [1, 20, 40, 64], [0, 30, 20, 64]):
         cfg, keep = _abi.make_config(64, 64, 8, 3, 1, xs, [0, 64])

@@ -133,6 +133,8 @@ def test_launch_forms_bit_identical():
     dict(tile_x=4, tile_y=3), dict(tile_x=7, tile_y=5, nslots=2), dict(tile_x=16, tile_y=1),
     dict(stage_rows=-1), dict(stage_rows=1), dict(stage_rows=3, tile_y=7), dict(stage_rows=8),
     dict(stage_rows=-1, tile_x=5, tile_y=3), dict(stage_rows=2, tile_x=32, tile_y=4),
+    dict(stage_rows=-4), dict(stage_rows=-8), dict(stage_rows=-4, tile_x=5, tile_y=3),
+    dict(stage_rows=-8, tile_y=11), dict(stage_rows=-8, tile_x=40, tile_y=2, nslots=1),
 ])
 def test_schedule_invariance(over):
     wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=3)
@@ -188,8 +190,8 @@ def test_ragged_fp64_bit_exact(shape):
     say("ragged", shape)
     wl = mk(nx, ny, nz, px, py, hot=((nx // 3, ny // 2, 1, -1), (0, 0, 0, 0)), sigma=3.0,
             kmax=25, split="dirichlet" if px > 1 else "equal", steps=3, nslots=3)
-    for tiles in (dict(), dict(tile_x=3, tile_y=2), dict(stage_rows=-1), dict(tile_y=5, stage_rows=2)
-                  if nz % 4 == 0 else dict(tile_y=5)):
+    deep = (dict(tile_y=5, stage_rows=2), dict(tile_y=9, stage_rows=-4), dict(tile_x=3, stage_rows=-4))
+    for tiles in (dict(), dict(tile_x=3, tile_y=2), dict(stage_rows=-1)) + (deep if nz % 4 == 0 else (dict(tile_y=5),)):
         g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **tiles)
         ref, work, _, _ = oracle.run(wl, nsteps=3)
         np.testing.assert_array_equal(q, ref)
@@ -448,7 +450,8 @@ def test_full_size_fp32_step_error_windows(name):
 def test_vertical_physics_fp64_bit_exact(nz):
     wl = mk(40, 36, nz, 4, 3, kmax=40, sigma=5.0, split="dirichlet", steps=3).replace(vertical=1)
     ref, work, _, _ = oracle.run(wl, nsteps=3)
-    for over in (dict(), dict(stage_rows=-1), dict(tile_x=5, tile_y=3)):
+    for over in (dict(), dict(stage_rows=-1), dict(tile_x=5, tile_y=3)) + \
+            ((dict(stage_rows=-4, tile_x=4),) if nz % 4 == 0 else ()):
         g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
         np.testing.assert_array_equal(q, ref)
         np.testing.assert_array_equal(w, work.sum(axis=0))
