@@ -866,6 +866,22 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs g) {
     }
 }
 
+// End of a measurement window: the chosen chunk loads and the tile work go to
+// pinned host memory (the device address of the staging area), and with
+// `reset` the window's counters (chunk work and time, workgroup busy time,
+// tile work: one contiguous range) start again from zero.  Every counter is
+// read before any is cleared: the copy and the clearing are two passes over
+// the same grid-stride range, separated by the end of the copy loop and a
+// grid-wide order given by running in one workgroup.
+__global__ __launch_bounds__(1024) void k_measure_out(const double* loads, const double* tiles, int C,
+                                                     int ntiles, double* out_loads, double* out_tiles,
+                                                     uint32_t* clear, size_t clear_words) {
+    for (int i = threadIdx.x; i < C; i += blockDim.x) out_loads[i] = loads[i];
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) out_tiles[i] = tiles[i];
+    __syncthreads();
+    for (size_t i = threadIdx.x; i < clear_words; i += blockDim.x) clear[i] = 0u;
+}
+
 // Field sum, pass 1: block b sums the contiguous range [b*n/B, (b+1)*n/B).
 template <typename T>
 __global__ __launch_bounds__(256) void k_sum1(const T* q, int64_t n, double* partial) {
@@ -978,6 +994,13 @@ int launch_gather(const GatherSeg* segs, int n, void* stream) {
     const uint32_t want = (most + 255) / 256;
     const dim3 grid(want < 256 ? (want > 0 ? want : 1) : 256);
     hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, static_cast<hipStream_t>(stream), g);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_measure_out(const double* loads, const double* tiles, int C, int ntiles, double* out_loads,
+                       double* out_tiles, void* clear, size_t clear_bytes, void* stream) {
+    hipLaunchKernelGGL(k_measure_out, dim3(1), dim3(1024), 0, static_cast<hipStream_t>(stream), loads,
+                       tiles, C, ntiles, out_loads, out_tiles, static_cast<uint32_t*>(clear), clear_bytes / 4);
     return static_cast<int>(hipGetLastError());
 }
 

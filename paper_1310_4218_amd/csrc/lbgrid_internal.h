@@ -112,6 +112,10 @@ int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nite
 int  launch_finish(const DevArgs& a, void* stream);
 int  launch_flush(const DevArgs& a, void* stream);
 int  launch_gather(const GatherSeg* segs, int n, void* stream);   // n <= kMaxGather
+// loads (C) and tile work (ntiles) to pinned host memory, then clear_bytes of
+// counters from `clear` (0 bytes: keep them)
+int  launch_measure_out(const double* loads, const double* tiles, int C, int ntiles, double* out_loads,
+                        double* out_tiles, void* clear, size_t clear_bytes, void* stream);
 int  launch_init_field(void* q, int prec, int64_t n, uint64_t seed, void* stream);
 int  launch_zero(void* p, size_t bytes, void* stream);
 int  launch_field_sum(const void* q, int prec, int64_t n, double* partial, double* out,

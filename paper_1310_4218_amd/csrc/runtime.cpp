@@ -196,11 +196,12 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_queue = take(sizeof(ItemDesc) * static_cast<size_t>(p.nrows));
     p.off_seg = take(sizeof(int32_t) * (static_cast<size_t>(p.Q) + 1));
     p.off_heads = take(sizeof(int32_t) * 2 * static_cast<size_t>(p.Q));
-    // loads (work, time) and busy time are adjacent: a measurement clears them in one launch
+    // loads (work, time), tile work and busy time are adjacent: a measurement clears
+    // them in one launch (busy last, so that only its nwg used entries are cleared)
     p.off_lw = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_lt = take(sizeof(double) * static_cast<size_t>(p.C));
-    p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg_cap));
     p.off_tw = take(sizeof(double) * static_cast<size_t>(p.ntiles));
+    p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg_cap));
     p.off_part = take(sizeof(double) * 2 * static_cast<size_t>(p.nrows));
     p.off_hist = take(sizeof(double) * kHistLen);
     p.off_tl = take(sizeof(uint64_t) * 4 * static_cast<size_t>(p.nwg_cap));
@@ -330,8 +331,9 @@ std::vector<int32_t> build_cost_table(const lb_config& c, int32_t r2cut) {
 //    low.  After a measurement the tile cost is the tile's own measured work
 //    (the load measurement of Section V taken per tile as well as per chunk);
 //    with caller-given chunk costs it is chunk cost * tile area / chunk area.
-//  - Queues: each slot gets the items of its chunks in descending item cost,
-//    ties in item order (chunk id, tile raster, first row).
+//  - Queues: queue q gets the items of the chunks of the slots s with s mod Q = q,
+//    tile by tile in descending cost per item (ties by tile index), the items of
+//    a tile one after another (first row first).
 int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     const Plan& p = x->plan;
 
@@ -359,35 +361,53 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
             const int h = x->tiles[4 * t + 2] >> 16;
             if (tcost[t] > target) pieces[t] = static_cast<int>(std::min<double>(h, std::ceil(tcost[t] / target)));
         }
-    // Tail: in every queue, the cheapest tiles whose pieces make up the final
-    // round of its G workgroups (the last G items in cost order) are cut
-    // tail_split times finer, so the step ends on small items and the
-    // workgroups finish together instead of one item apart.
-    const int tail = x->cfg.tail_split;
-    if (tail > 1) {
-        std::vector<std::vector<int32_t>> qt(static_cast<size_t>(p.Q));
+    // Tiles of every queue in longest-first order: cost per piece descending,
+    // tile index ascending on ties.  One sort serves the tail split and the
+    // queue order (the items of a tile follow one another, first row first).
+    std::vector<int32_t> qoff(static_cast<size_t>(p.Q) + 1, 0);
+    for (int32_t c = 0; c < p.C; ++c) qoff[x->map[c] % p.Q + 1] += x->tile_off[c + 1] - x->tile_off[c];
+    for (int32_t q = 0; q < p.Q; ++q) qoff[q + 1] += qoff[q];
+    struct Key {
+        double per_piece;
+        int32_t tile;
+    };
+    std::vector<Key> order(static_cast<size_t>(p.ntiles));
+    {
+        std::vector<int32_t> fill(qoff.begin(), qoff.end() - 1);
         for (int32_t c = 0; c < p.C; ++c)
-            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) qt[x->map[c] % p.Q].push_back(t);
-        for (auto& v : qt) {
-            std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
-                return tcost[a] / pieces[a] > tcost[b] / pieces[b];
-            });
+            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t)
+                order[fill[x->map[c] % p.Q]++] = Key{tcost[t] / pieces[t], t};
+    }
+    for (int32_t q = 0; q < p.Q; ++q)
+        std::sort(order.begin() + qoff[q], order.begin() + qoff[q + 1], [](const Key& a, const Key& b) {
+            return a.per_piece > b.per_piece || (a.per_piece == b.per_piece && a.tile < b.tile);
+        });
+    // Tail: in every queue, the cheapest tiles whose pieces make up the final
+    // round of its G workgroups (the last G items in this order) are cut
+    // tail_split times finer, so the step ends on small items and the
+    // workgroups finish together instead of one item apart.  Their cost per
+    // piece only drops, so the order stands.
+    const int tail = x->cfg.tail_split;
+    if (tail > 1)
+        for (int32_t q = 0; q < p.Q; ++q) {
             int64_t covered = 0;
-            for (auto it = v.rbegin(); it != v.rend() && covered < p.G; ++it) {
-                covered += pieces[*it];
-                const int h = x->tiles[4 * *it + 2] >> 16;
-                pieces[*it] = std::min(h, pieces[*it] * tail);
+            for (int32_t i = qoff[q + 1] - 1; i >= qoff[q] && covered < p.G; --i) {
+                const int32_t t = order[i].tile;
+                covered += pieces[t];
+                pieces[t] = std::min(x->tiles[4 * t + 2] >> 16, pieces[t] * tail);
             }
         }
-    }
 
+    // Items in chunk order (tile raster, first row first); item_first[t] is the
+    // first item of tile t.
     x->items.clear();
     x->item_off.assign(static_cast<size_t>(p.C) + 1, 0);
-    std::vector<double> item_cost;
+    std::vector<int32_t> item_first(static_cast<size_t>(p.ntiles));
     for (int32_t c = 0; c < p.C; ++c) {
         x->item_off[c] = static_cast<int32_t>(x->items.size());
         for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) {
             const int w = x->tiles[4 * t + 2] & 0xffff, h = x->tiles[4 * t + 2] >> 16;
+            item_first[t] = static_cast<int32_t>(x->items.size());
             for (int k = 0; k < pieces[t]; ++k) {
                 const int r0 = (k * h) / pieces[t], r1 = ((k + 1) * h) / pieces[t];
                 ItemDesc d{};
@@ -399,17 +419,11 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
                 d.vbase = x->row_base[t] + r0;
                 d.tile = t;
                 x->items.push_back(d);
-                item_cost.push_back(tcost[t] * (r1 - r0) / h);
             }
         }
     }
     const int32_t n = static_cast<int32_t>(x->items.size());
     x->item_off[p.C] = n;
-
-    std::vector<std::vector<int32_t>> by_queue(static_cast<size_t>(p.Q));
-    for (int32_t c = 0; c < p.C; ++c)
-        for (int32_t it = x->item_off[c]; it < x->item_off[c + 1]; ++it)
-            by_queue[x->map[c] % p.Q].push_back(it);
 
     if (x->upload_pending) {
         HIP_TRY(x, hipEventSynchronize(x->upload_done));
@@ -426,10 +440,10 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     int32_t k = 0;
     for (int32_t q = 0; q < p.Q; ++q) {
         st_seg[q] = k;
-        auto& v = by_queue[q];
-        std::stable_sort(v.begin(), v.end(),
-                         [&](int32_t a, int32_t b) { return item_cost[a] > item_cost[b]; });
-        for (int32_t it : v) st_queue[k++] = x->items[it];
+        for (int32_t i = qoff[q]; i < qoff[q + 1]; ++i) {
+            const int32_t t = order[i].tile;
+            for (int32_t j = 0; j < pieces[t]; ++j) st_queue[k++] = x->items[item_first[t] + j];
+        }
     }
     st_seg[p.Q] = k;
     *st_n = n;
@@ -769,14 +783,18 @@ int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
     HIP_TRY(x, hipSetDevice(x->device));
     // the loads land in pinned staging after the window's last step, the counters
     // are cleared behind them, and one synchronisation covers both
+    // one kernel moves the loads and tile work into pinned staging after the
+    // window's last step and clears the counters (work, time, busy and tile
+    // counters are adjacent in the workspace); one synchronisation covers it
     double* st = reinterpret_cast<double*>(x->staging + p.st_loads);
     double* stt = reinterpret_cast<double*>(x->staging + p.st_tiles);
-    HIP_TRY(x, hipMemcpyAsync(st, x->ws + (source == LB_LOAD_WORK ? p.off_lw : p.off_lt),
-                              sizeof(double) * p.C, hipMemcpyDeviceToHost, x->stream));
-    HIP_TRY(x, hipMemcpyAsync(stt, x->ws + p.off_tw, sizeof(double) * p.ntiles, hipMemcpyDeviceToHost,
-                              x->stream));
-    if (reset)  // work, time, busy and tile counters are adjacent in the workspace
-        LAUNCH_TRY(x, launch_zero(x->ws + p.off_lw, p.off_tw + sizeof(double) * p.ntiles - p.off_lw, x->stream));
+    LAUNCH_TRY(x, launch_measure_out(
+                      reinterpret_cast<const double*>(x->ws + (source == LB_LOAD_WORK ? p.off_lw : p.off_lt)),
+                      reinterpret_cast<const double*>(x->ws + p.off_tw), p.C, p.ntiles,
+                      reinterpret_cast<double*>(const_cast<char*>(x->staging_dev) + p.st_loads),
+                      reinterpret_cast<double*>(const_cast<char*>(x->staging_dev) + p.st_tiles),
+                      x->ws + p.off_lw, reset ? p.off_busy + sizeof(double) * p.nwg - p.off_lw : 0,
+                      x->stream));
     int rc = sync(x);
     if (rc != LB_OK) return rc;
     x->measured.assign(st, st + p.C);
