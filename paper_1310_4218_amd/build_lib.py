@@ -3,8 +3,9 @@
     python -m paper_1310_4218_amd.build_lib [-v]
 
 Every source is compiled for gfx950 only, with packed FP32 instructions
-disabled (-packed-fp32-ops) and native FP64 atomics (-munsafe-fp-atomics; the
-workspace is ordinary device memory).  Objects go to ``_build/`` at the
+disabled (-packed-fp32-ops), native FP64 atomics (-munsafe-fp-atomics; the
+workspace is ordinary device memory) and the atomic optimizer off (claims are
+single-lane atomics read late).  Objects go to ``_build/`` at the
 repository root; the library lands next to this file.
 """
 from __future__ import annotations
@@ -26,8 +27,11 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           f"-I{os.path.join(ROOT, 'include')}"]
+# -amdgpu-atomic-optimizer-strategy=None: a claim is one lane's atomic whose
+# result is needed only later in the item; the optimizer would rewrite it as a
+# wave-wide atomic and wait for its reply on the spot.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 
 def hipcc() -> str:

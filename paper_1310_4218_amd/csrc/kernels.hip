@@ -726,14 +726,16 @@ __global__ __launch_bounds__(max_block(PIPE)) void k_persistent(DevArgs a) {
             if (d.id < 0) break;
         }
         __syncthreads();                     // every thread holds d and nx before they change
+        // claim one more item; its index is first used after the item's first
+        // barrier, whose wait covers the atomic anyway
         int nidx = hn;
-        if (threadIdx.x == 0 && !drained) {
-            nidx = atomicAdd(&heads[home], 1);
-            drained = nidx + 1 >= hn;
-        }
+        if (threadIdx.x == 0 && !drained) nidx = atomicAdd(&heads[home], 1);
         ItemDesc na = no_item();
         auto ahead = [&]() {
-            if (threadIdx.x == 0 && nidx < hn) na = a.queue[hbeg + nidx];
+            if (threadIdx.x == 0) {
+                if (nidx < hn) na = a.queue[hbeg + nidx];
+                drained = nidx + 1 >= hn;
+            }
         };
         const uint64_t t_start = wall_clock64();
         if (t_first == 0) t_first = t_start;
