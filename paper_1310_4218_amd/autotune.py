@@ -78,14 +78,14 @@ def measure(wl, params: dict, precision: str, steps: int, warm: int, torch):
     R = wl.rebalance_every or 10
     g = Grid(wl, precision=precision, graph_steps=R, **params)
     for _ in range(max(1, -(-warm // R))):
-        g.step(R, "persistent")
+        g.step(R, "persistent_eager")
         g.measure("work")
         g.rebalance(wl.strategy, wl.threshold)
     evs = []
     for _ in range(max(1, -(-steps // R))):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(g.stream)
-        g.step(R, "persistent")
+        g.step(R, "persistent_eager")
         e1.record(g.stream)
         evs.append((e0, e1))
         g.measure("work")
