@@ -131,6 +131,11 @@ typedef struct {
                                 (its last G items) are cut this many times
                                 finer, so a step ends on small items;
                                 0 or 1 = off (4)                              */
+    int32_t item_alpha;      /* stencil weight per cell when measured tile work
+                                sets item sizes (the balancer's loads keep
+                                alpha_work); -1 = alpha_work (default). A
+                                small value sizes items by their physics,
+                                which one workgroup runs serially            */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;

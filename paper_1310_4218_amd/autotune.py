@@ -3,7 +3,7 @@
     python -m paper_1310_4218_amd.autotune --workload moving [--precision fp32]
 
 Searches the launch parameters that do not change the method (tile_x,
-tile_y, nqueues, wg_per_queue, item_split, stage_rows, tail_split), keeping
+tile_y, nqueues, wg_per_queue, item_split, stage_rows, tail_split, item_alpha), keeping
 everything that defines the problem fixed (grid, chunks, hotspots, number of
 balancer slots S).  Each candidate: a fresh context run in windows of R steps
 with a load measurement and a rebalance after each window, as the benchmark
@@ -36,6 +36,7 @@ SPACE = {
     "stage_rows": [-1, -4, -8, 2, 4, 6, 8],   # -1, -4, -8: register pipeline 2/4/8 rows deep;
                                               # n > 0: direct-to-LDS batches of n rows
     "tail_split": [0, 2, 4, 8],
+    "item_alpha": [-1, 8, 2, 0],  # -1: items sized with the balancer's alpha_work
 }
 
 

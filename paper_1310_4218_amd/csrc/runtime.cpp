@@ -107,6 +107,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->steal != 0 && c->steal != 1) return bad("steal must be 0 or 1");
     if (c->item_split < 0 || c->item_split > 64) return bad("item_split must be in [0, 64]");
     if (c->tail_split < 0 || c->tail_split > 64) return bad("tail_split must be in [0, 64]");
+    if (c->item_alpha < -1 || c->item_alpha > 1000000) return bad("item_alpha must be in [-1, 1e6]");
     if (c->stage_rows < -8 || c->stage_rows > 32 ||
         (c->stage_rows < -2 && c->stage_rows != -4 && c->stage_rows != -8))
         return bad("stage_rows must be -8, -4, -2, -1 (register pipeline) or in [0, 32]");
@@ -247,6 +248,7 @@ struct lb_ctx {
     std::vector<int32_t> map;         // C
     std::vector<double> measured;     // loads kept by the last lb_measure
     std::vector<double> tile_measured;  // work of every tile in the same window
+    int64_t tile_steps = 0;           // steps in that window
     bool have_measured = false;
     int64_t steps = 0;
     int64_t window_steps = 0;
@@ -350,6 +352,9 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
             const int w = x->tiles[4 * t + 2] & 0xffff, h = x->tiles[4 * t + 2] >> 16;
             const double area_t = static_cast<double>(w) * h;
             tcost[t] = tile_cost ? tile_cost[t] : cost ? cost[c] * (area_t / area_c) : area_t;
+            if (tile_cost && x->cfg.item_alpha >= 0)  // count the stencil at item_alpha per cell
+                tcost[t] = std::max(0.0, tcost[t] - static_cast<double>(x->cfg.alpha_work - x->cfg.item_alpha) *
+                                                        p.nz * p.nfields * area_t * static_cast<double>(x->tile_steps));
             W += tcost[t];
         }
     }
@@ -558,6 +563,7 @@ void lb_config_default(lb_config* c) {
     c->stage_rows = 0;
     c->physics = LB_PHYS_POINTWISE;
     c->tail_split = 4;
+    c->item_alpha = -1;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
@@ -799,6 +805,7 @@ int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
     if (rc != LB_OK) return rc;
     x->measured.assign(st, st + p.C);
     x->tile_measured.assign(stt, stt + p.ntiles);
+    x->tile_steps = x->window_steps;
     x->have_measured = true;
     if (loads_out) std::memcpy(loads_out, x->measured.data(), sizeof(double) * p.C);
     if (reset) x->window_steps = 0;
