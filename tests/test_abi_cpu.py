@@ -59,6 +59,7 @@ def test_query_sizes(lib):
     ("nslots", 0, "nslots"), ("kmax", 0, "kmin"), ("nhot", 5, "nhot"), ("graph_steps", 0, "graph"),
     ("steal", 2, "steal"), ("nfields", 0, "nfields"), ("sigma", -1.0, "sigma"),
     ("tile_x", 2000, "1024"), ("alpha_work", -1, "alpha"), ("wg_per_queue", 100000, "65536"),
+    ("item_alpha", -2, "item_alpha"),
 ])
 def test_query_rejects_bad_config(lib, field, value, msg):
     cfg, keep = _abi.config_from_workload(W.small())

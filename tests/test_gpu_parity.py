@@ -164,13 +164,14 @@ def test_split_items_bit_identical():
     every tile row is still computed exactly once per step."""
     wl = mk(64, 48, 16, 4, 3, kmax=150, sigma=6.0, split="dirichlet", steps=6, nslots=4)
     _, base, wb = run_gpu(wl, 6, "plain")
-    for split in (1, 4, 64):
-        g = Grid(wl, item_split=split, wg_per_queue=4)
+    for split, over in ((1, {}), (4, {}), (64, {}), (4, dict(item_alpha=0)),
+                        (8, dict(item_alpha=2, tail_split=8)), (64, dict(item_alpha=0, stage_rows=2))):
+        g = Grid(wl, item_split=split, wg_per_queue=4, **over)
         g.step(2)
         g.measure("work")
         g.rebalance("greedy")
         st = g.stats()
-        say("item_split", split, "items", st["nitems"], "tiles", st["ntiles"])
+        say("item_split", split, over, "items", st["nitems"], "tiles", st["ntiles"])
         assert st["nitems"] >= st["ntiles"]
         g.step(2, "persistent")
         g.step(2, "plain")            # plain launches follow the installed plan too
