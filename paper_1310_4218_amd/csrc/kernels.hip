@@ -27,6 +27,7 @@
 //                the FP64 path bit-identical to a plain sequential evaluation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "lbgrid_internal.h"
@@ -861,27 +862,47 @@ struct GatherArgs {
 };
 __global__ __launch_bounds__(256) void k_gather(GatherArgs g) {
     const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     for (int s = 0; s < g.n; ++s) {
         const GatherSeg sg = g.seg[s];
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.words; i += stride)
-            sg.dst[i] = sg.src[i];
+        // 16-byte words where both ends allow it (every table but the item count)
+        const bool wide = ((reinterpret_cast<uintptr_t>(sg.src) | reinterpret_cast<uintptr_t>(sg.dst)) & 15) == 0;
+        const uint32_t nv = wide ? sg.words / 4 : 0;
+        const uint4* src4 = reinterpret_cast<const uint4*>(sg.src);
+        uint4* dst4 = reinterpret_cast<uint4*>(sg.dst);
+        for (uint32_t i = tid; i < nv; i += stride) dst4[i] = src4[i];
+        for (uint32_t i = 4 * nv + tid; i < sg.words; i += stride) sg.dst[i] = sg.src[i];
     }
 }
 
 // End of a measurement window: the chosen chunk loads and the tile work go to
 // pinned host memory (the device address of the staging area), and with
-// `reset` the window's counters (chunk work and time, workgroup busy time,
-// tile work: one contiguous range) start again from zero.  Every counter is
-// read before any is cleared: the copy and the clearing are two passes over
-// the same grid-stride range, separated by the end of the copy loop and a
-// grid-wide order given by running in one workgroup.
-__global__ __launch_bounds__(1024) void k_measure_out(const double* loads, const double* tiles, int C,
-                                                     int ntiles, double* out_loads, double* out_tiles,
-                                                     uint32_t* clear, size_t clear_words) {
-    for (int i = threadIdx.x; i < C; i += blockDim.x) out_loads[i] = loads[i];
-    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) out_tiles[i] = tiles[i];
-    __syncthreads();
-    for (size_t i = threadIdx.x; i < clear_words; i += blockDim.x) clear[i] = 0u;
+// `reset` the window's counters (chunk work and time, tile work, workgroup
+// busy time: one contiguous range [clear, clear + clear_words)) start again
+// from zero.  A counter that is copied is cleared by the thread that read it,
+// after the read; the others are only cleared.  So any grid works.
+__global__ __launch_bounds__(256) void k_measure_out(double* loads, double* tiles, int C, int ntiles,
+                                                    double* out_loads, double* out_tiles, uint32_t* clear,
+                                                    size_t clear_words) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    const size_t tid = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool reset = clear_words > 0;
+    for (size_t i = tid; i < static_cast<size_t>(C); i += stride) {
+        out_loads[i] = loads[i];
+        if (reset) loads[i] = 0.0;
+    }
+    for (size_t i = tid; i < static_cast<size_t>(ntiles); i += stride) {
+        out_tiles[i] = tiles[i];
+        if (reset) tiles[i] = 0.0;
+    }
+    const uint32_t* lo = reinterpret_cast<const uint32_t*>(loads);
+    const uint32_t* to = reinterpret_cast<const uint32_t*>(tiles);
+    for (size_t i = tid; i < clear_words; i += stride) {
+        const uint32_t* w = clear + i;
+        const bool copied = (w >= lo && w < lo + 2 * static_cast<size_t>(C)) ||
+                            (w >= to && w < to + 2 * static_cast<size_t>(ntiles));
+        if (!copied) clear[i] = 0u;
+    }
 }
 
 // Field sum, pass 1: block b sums the contiguous range [b*n/B, (b+1)*n/B).
@@ -999,10 +1020,13 @@ int launch_gather(const GatherSeg* segs, int n, void* stream) {
     return static_cast<int>(hipGetLastError());
 }
 
-int launch_measure_out(const double* loads, const double* tiles, int C, int ntiles, double* out_loads,
-                       double* out_tiles, void* clear, size_t clear_bytes, void* stream) {
-    hipLaunchKernelGGL(k_measure_out, dim3(1), dim3(1024), 0, static_cast<hipStream_t>(stream), loads,
-                       tiles, C, ntiles, out_loads, out_tiles, static_cast<uint32_t*>(clear), clear_bytes / 4);
+int launch_measure_out(double* loads, double* tiles, int C, int ntiles, double* out_loads, double* out_tiles,
+                       void* clear, size_t clear_bytes, void* stream) {
+    const size_t most = std::max(static_cast<size_t>(std::max(C, ntiles)), clear_bytes / 4);
+    const size_t want = (most + 255) / 256;
+    const dim3 grid(static_cast<unsigned>(want < 256 ? (want > 0 ? want : 1) : 256));
+    hipLaunchKernelGGL(k_measure_out, grid, dim3(256), 0, static_cast<hipStream_t>(stream), loads, tiles, C,
+                       ntiles, out_loads, out_tiles, static_cast<uint32_t*>(clear), clear_bytes / 4);
     return static_cast<int>(hipGetLastError());
 }
 

@@ -114,7 +114,7 @@ int  launch_flush(const DevArgs& a, void* stream);
 int  launch_gather(const GatherSeg* segs, int n, void* stream);   // n <= kMaxGather
 // loads (C) and tile work (ntiles) to pinned host memory, then clear_bytes of
 // counters from `clear` (0 bytes: keep them)
-int  launch_measure_out(const double* loads, const double* tiles, int C, int ntiles, double* out_loads,
+int  launch_measure_out(double* loads, double* tiles, int C, int ntiles, double* out_loads,
                         double* out_tiles, void* clear, size_t clear_bytes, void* stream);
 int  launch_init_field(void* q, int prec, int64_t n, uint64_t seed, void* stream);
 int  launch_zero(void* p, size_t bytes, void* stream);

@@ -66,6 +66,30 @@ bool strictly_increasing(const std::vector<int32_t>& s, int32_t n) {
     return true;
 }
 
+// Ascending sort of keys (hi 32 bits: ~float bits of a non-negative cost,
+// lo 32 bits: index) given in ascending index order: a stable least-
+// significant-digit radix sort on the high half (four 8-bit passes), which
+// leaves equal costs in index order, i.e. the order of the full 64-bit keys.
+void sort_keys(uint64_t* k, int32_t n) {
+    if (n < 2) return;
+    if (n < 64) {
+        std::sort(k, k + n);
+        return;
+    }
+    std::vector<uint64_t> tmp(static_cast<size_t>(n));
+    uint64_t* a = k;
+    uint64_t* b = tmp.data();
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 32 + 8 * pass;
+        int32_t count[257] = {0};
+        for (int32_t i = 0; i < n; ++i) ++count[((a[i] >> shift) & 0xff) + 1];
+        for (int d = 0; d < 256; ++d) count[d + 1] += count[d];
+        for (int32_t i = 0; i < n; ++i) b[count[(a[i] >> shift) & 0xff]++] = a[i];
+        std::swap(a, b);
+    }
+    // four passes: the sorted keys are back in k
+}
+
 // a mod n in [0, n)
 int32_t wrap(int64_t a, int32_t n) {
     const int64_t r = a % n;
@@ -366,27 +390,29 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
             const int h = x->tiles[4 * t + 2] >> 16;
             if (tcost[t] > target) pieces[t] = static_cast<int>(std::min<double>(h, std::ceil(tcost[t] / target)));
         }
-    // Tiles of every queue in longest-first order: cost per piece descending,
-    // tile index ascending on ties.  One sort serves the tail split and the
+    // Tiles of every queue in longest-first order: cost per piece descending
+    // (compared in single precision), tile index ascending on ties.  One sort serves the tail split and the
     // queue order (the items of a tile follow one another, first row first).
     std::vector<int32_t> qoff(static_cast<size_t>(p.Q) + 1, 0);
     for (int32_t c = 0; c < p.C; ++c) qoff[x->map[c] % p.Q + 1] += x->tile_off[c + 1] - x->tile_off[c];
     for (int32_t q = 0; q < p.Q; ++q) qoff[q + 1] += qoff[q];
-    struct Key {
-        double per_piece;
-        int32_t tile;
+    // The sort key is one integer: the complemented bits of the cost per piece
+    // as a float (non-negative floats order like their bit patterns), then the
+    // tile index; plain integer sorting keeps a plan of ~10^4 tiles cheap.
+    auto key_of = [&](int32_t t) -> uint64_t {
+        const float per_piece = static_cast<float>(tcost[t] / pieces[t]);
+        uint32_t bits;
+        std::memcpy(&bits, &per_piece, sizeof(bits));
+        return (static_cast<uint64_t>(~bits) << 32) | static_cast<uint32_t>(t);
     };
-    std::vector<Key> order(static_cast<size_t>(p.ntiles));
+    std::vector<uint64_t> order(static_cast<size_t>(p.ntiles));
     {
         std::vector<int32_t> fill(qoff.begin(), qoff.end() - 1);
         for (int32_t c = 0; c < p.C; ++c)
-            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t)
-                order[fill[x->map[c] % p.Q]++] = Key{tcost[t] / pieces[t], t};
+            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) order[fill[x->map[c] % p.Q]++] = key_of(t);
     }
-    for (int32_t q = 0; q < p.Q; ++q)
-        std::sort(order.begin() + qoff[q], order.begin() + qoff[q + 1], [](const Key& a, const Key& b) {
-            return a.per_piece > b.per_piece || (a.per_piece == b.per_piece && a.tile < b.tile);
-        });
+    for (int32_t q = 0; q < p.Q; ++q) sort_keys(order.data() + qoff[q], qoff[q + 1] - qoff[q]);
+    auto tile_at = [&](int32_t i) { return static_cast<int32_t>(order[i] & 0xffffffffu); };
     // Tail: in every queue, the cheapest tiles whose pieces make up the final
     // round of its G workgroups (the last G items in this order) are cut
     // tail_split times finer, so the step ends on small items and the
@@ -397,7 +423,7 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
         for (int32_t q = 0; q < p.Q; ++q) {
             int64_t covered = 0;
             for (int32_t i = qoff[q + 1] - 1; i >= qoff[q] && covered < p.G; --i) {
-                const int32_t t = order[i].tile;
+                const int32_t t = tile_at(i);
                 covered += pieces[t];
                 pieces[t] = std::min(x->tiles[4 * t + 2] >> 16, pieces[t] * tail);
             }
@@ -446,7 +472,7 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     for (int32_t q = 0; q < p.Q; ++q) {
         st_seg[q] = k;
         for (int32_t i = qoff[q]; i < qoff[q + 1]; ++i) {
-            const int32_t t = order[i].tile;
+            const int32_t t = tile_at(i);
             for (int32_t j = 0; j < pieces[t]; ++j) st_queue[k++] = x->items[item_first[t] + j];
         }
     }
@@ -795,8 +821,8 @@ int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
     double* st = reinterpret_cast<double*>(x->staging + p.st_loads);
     double* stt = reinterpret_cast<double*>(x->staging + p.st_tiles);
     LAUNCH_TRY(x, launch_measure_out(
-                      reinterpret_cast<const double*>(x->ws + (source == LB_LOAD_WORK ? p.off_lw : p.off_lt)),
-                      reinterpret_cast<const double*>(x->ws + p.off_tw), p.C, p.ntiles,
+                      reinterpret_cast<double*>(x->ws + (source == LB_LOAD_WORK ? p.off_lw : p.off_lt)),
+                      reinterpret_cast<double*>(x->ws + p.off_tw), p.C, p.ntiles,
                       reinterpret_cast<double*>(const_cast<char*>(x->staging_dev) + p.st_loads),
                       reinterpret_cast<double*>(const_cast<char*>(x->staging_dev) + p.st_tiles),
                       x->ws + p.off_lw, reset ? p.off_busy + sizeof(double) * p.nwg - p.off_lw : 0,
