@@ -28,11 +28,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 
 SPACE = {
-    "tile_x": [8, 16, 32],
-    "tile_y": [4, 8, 16, 32],
+    "tile_x": [8, 16, 32, 64],
+    "tile_y": [2, 4, 8, 16, 32],
     "nqueues": [1, 8, 32, 256],
     "wg_per_queue": [0],          # 0: fill the device (resident workgroups / queues)
-    "item_split": [0, 1, 2, 4, 8],
+    "item_split": [0, 1, 2, 3, 4, 6, 8],
     "stage_rows": [-1, -4, -8, 2, 4, 6, 8],   # -1, -4, -8: register pipeline 2/4/8 rows deep;
                                               # n > 0: direct-to-LDS batches of n rows
     "tail_split": [0, 2, 4, 8],
