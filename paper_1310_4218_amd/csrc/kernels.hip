@@ -4,7 +4,7 @@
 // (Section V), in two launch forms:
 //   - plain: one launch per chunk over that chunk's items, chunks in id order;
 //   - persistent: one launch per step whose workgroups claim items from work
-//     queues with atomic heads (the chunks of balancer slot s, the paper's
+//     queues with atomic counters (the chunks of balancer slot s, the paper's
 //     processors, feed queue s mod Q), optionally taking work from other
 //     queues once their own is empty.
 //
@@ -13,11 +13,12 @@
 // tile (the whole tile unless the host split a costly tile into row ranges).
 // A workgroup has TX*nz/V threads; thread t owns V consecutive levels of
 // column t / (nz/V) of the current row.  The item is swept row by row (along
-// y) through a ring of four LDS rows, each holding TX+2 columns (one halo
-// column on either side) of all nz levels: rows y-1, y, y+1 are read by the
-// stencil while row y+2 is being fetched from HBM into registers.  Every cell
-// is read from HBM once per item and written once; halo columns and halo rows
-// are re-read by the neighbouring items (mostly from L2 / MALL).
+// y) through a ring of LDS rows, each holding TX+2 columns (one halo column on
+// either side) of all nz levels: rows y-1, y, y+1 are read by the stencil
+// while later rows are in flight, either straight into the ring (direct
+// global->LDS loads, B rows per batch) or through registers (2, 4 or 8 rows).
+// Every cell is read from HBM once per item and written once; halo columns and
+// halo rows are re-read by the neighbouring items (mostly from L2 / MALL).
 //
 // Arithmetic per cell, with s the stencil value and k the column's trip count:
 //   FP32:        q <- fma(eps, fma(-(q*q), q, q), q), k times
@@ -249,7 +250,9 @@ __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70)
 // PIPE = 2, 4 or 8: rows move HBM -> registers -> LDS with PIPE rows in flight
 //   per workgroup (row r + 2 .. r + 1 + PIPE while row r is computed); the
 //   compiler's own wait counts order each row's registers before its LDS
-//   store, so the pipeline needs no barrier-wide wait for memory.
+//   store, so the pipeline needs no barrier-wide wait for memory.  (The
+//   compiler merges its counts conservatively around the conditional row
+//   loads, so in practice depths 4 and 8 wait about as often as depth 2.)
 // What an item of the direct-load pipeline hands to the next item of its
 // workgroup: during its last block it issues the next item's first rows into
 // the free part of the ring and looks up the next item's trip counts, so that
