@@ -82,7 +82,8 @@ enum { LB_PHYS_POINTWISE = 0, LB_PHYS_VERTICAL = 1 };
 /* Load source for lb_measure / lb_rebalance. */
 enum { LB_LOAD_WORK = 0, LB_LOAD_TIME = 1 };
 /* Balancer. */
-enum { LB_GREEDY = 0, LB_REFINE = 1, LB_REFINESWAP = 2 };
+enum { LB_GREEDY = 0, LB_REFINE = 1, LB_REFINESWAP = 2,
+       LB_GREEDY_THEN_REFINESWAP = 3 /* Experiment C's policy: Greedy first, then RefineSwap */ };
 
 typedef struct lb_ctx lb_ctx;
 
@@ -200,8 +201,10 @@ int lb_measure(lb_ctx *ctx, int32_t source, double *loads_out, int32_t reset);
 
 /* Compute a new chunk->slot map with strategy LB_GREEDY (Section VI,
  * Experiment A: heaviest chunk to the least loaded slot), LB_REFINE (move
- * chunks off slots above threshold*average, Experiment B without swaps) or
- * LB_REFINESWAP (refine, then swap pairs where no move fits) from loads
+ * chunks off slots above threshold*average, Experiment B without swaps),
+ * LB_REFINESWAP (refine, then swap pairs where no move fits) or
+ * LB_GREEDY_THEN_REFINESWAP (the policy of Experiment C: Greedy on the
+ * context's first rebalance, RefineSwap on every later one) from loads
  * (C doubles, or NULL for the loads kept by the last lb_measure: LB_E_STATE
  * if there is none), install it and rebuild the per-slot work queues in
  * descending per-tile cost.  Outputs (each may be NULL): map_out[C],
@@ -244,7 +247,8 @@ int lb_checksums(lb_ctx *ctx, double *out, int32_t n, int32_t *got);
 
 /* Host-only balancer (no GPU, no context): the same computation lb_rebalance
  * uses.  old_map may be NULL for LB_GREEDY (then *nmigrated counts chunks off
- * the block map). */
+ * the block map).  LB_GREEDY_THEN_REFINESWAP runs Greedy when old_map is NULL
+ * (a first call) and RefineSwap from old_map otherwise. */
 int lb_balance_host(const double *loads, const int32_t *old_map, int32_t C, int32_t S,
                     int32_t strategy, double threshold, int32_t *map_out, int32_t *nmigrated);
 

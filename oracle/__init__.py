@@ -187,6 +187,13 @@ def refineswap(w, old_map, S, thr) -> np.ndarray:
     return m
 
 
+def greedy_then_refineswap(w, old_map, S, thr, first) -> np.ndarray:
+    """The balancer policy of Experiment C (Section VI, Table V; Section VII): the
+    first rebalance of a run uses Greedy, every later one RefineSwap from the
+    map in force."""
+    return greedy(w, S) if first else refineswap(w, old_map, S, thr)
+
+
 def init_window(wl, ox, oy, nxw, nyw, f=0) -> np.ndarray:
     """Seeded initial values of a window of field f: local column (x, y) is global column
     ((ox + x) mod nx, (oy + y) mod ny)."""

@@ -18,7 +18,7 @@ LB_OK, LB_E_INVAL, LB_E_STATE, LB_E_HIP, LB_E_NOMEM, LB_E_UNSUPPORTED = 0, -1, -
 LB_FP32, LB_FP32_KAHAN, LB_FP64 = 0, 1, 2
 LB_PLAIN, LB_PERSISTENT, LB_PLAIN_GRAPH, LB_PERSISTENT_EAGER = 0, 1, 2, 3
 LB_LOAD_WORK, LB_LOAD_TIME = 0, 1
-LB_GREEDY, LB_REFINE, LB_REFINESWAP = 0, 1, 2
+LB_GREEDY, LB_REFINE, LB_REFINESWAP, LB_GREEDY_THEN_REFINESWAP = 0, 1, 2, 3
 LB_MAX_HOT = 4
 LB_NBUF = 3
 
@@ -26,7 +26,8 @@ PRECISIONS = {"fp32": LB_FP32, "fp32_kahan": LB_FP32_KAHAN, "kahan": LB_FP32_KAH
 MODES = {"plain": LB_PLAIN, "persistent": LB_PERSISTENT, "plain_graph": LB_PLAIN_GRAPH,
          "persistent_eager": LB_PERSISTENT_EAGER}
 SOURCES = {"work": LB_LOAD_WORK, "time": LB_LOAD_TIME}
-STRATEGIES = {"greedy": LB_GREEDY, "refine": LB_REFINE, "refineswap": LB_REFINESWAP}
+STRATEGIES = {"greedy": LB_GREEDY, "refine": LB_REFINE, "refineswap": LB_REFINESWAP,
+              "greedy_then_refineswap": LB_GREEDY_THEN_REFINESWAP}
 
 I32P = C.POINTER(C.c_int32)
 DBLP = C.POINTER(C.c_double)

@@ -273,6 +273,7 @@ struct lb_ctx {
     std::vector<double> measured;     // loads kept by the last lb_measure
     std::vector<double> tile_measured;  // work of every tile in the same window
     int64_t tile_steps = 0;           // steps in that window
+    int64_t rebalances = 0;           // lb_rebalance calls that installed a map
     bool have_measured = false;
     int64_t steps = 0;
     int64_t window_steps = 0;
@@ -842,8 +843,10 @@ int lb_balance_host(const double* loads, const int32_t* old_map, int32_t C, int3
                     int32_t strategy, double threshold, int32_t* map_out, int32_t* nmigrated) {
     if (C < 0 || S < 1) return fail(nullptr, LB_E_INVAL, "need C >= 0 and S >= 1");
     if (C > 0 && (!loads || !map_out)) return fail(nullptr, LB_E_INVAL, "loads and map_out are required");
-    if (strategy != LB_GREEDY && strategy != LB_REFINE && strategy != LB_REFINESWAP)
+    if (strategy != LB_GREEDY && strategy != LB_REFINE && strategy != LB_REFINESWAP &&
+        strategy != LB_GREEDY_THEN_REFINESWAP)
         return fail(nullptr, LB_E_INVAL, "unknown strategy");
+    if (strategy == LB_GREEDY_THEN_REFINESWAP) strategy = old_map ? LB_REFINESWAP : LB_GREEDY;
     std::vector<int32_t> base(static_cast<size_t>(C));
     if (old_map) {
         for (int32_t c = 0; c < C; ++c) {
@@ -876,6 +879,8 @@ int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* lo
     }
     std::vector<int32_t> nm(static_cast<size_t>(p.C));
     int32_t mig = 0;
+    if (strategy == LB_GREEDY_THEN_REFINESWAP)  // Experiment C: Greedy first, RefineSwap later
+        strategy = x->rebalances == 0 ? LB_GREEDY : LB_REFINESWAP;
     int rc = lb_balance_host(w, x->map.data(), p.C, p.S, strategy, threshold, nm.data(), &mig);
     if (rc != LB_OK) {
         x->err = g_err;
@@ -888,6 +893,7 @@ int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* lo
     // measured loads come with the measured work of every tile, which cuts the items
     const double* tw = (!loads && !x->tile_measured.empty()) ? x->tile_measured.data() : nullptr;
     if ((rc = upload_plan(x, w, tw)) != LB_OK) return rc;
+    ++x->rebalances;
     if (map_out) std::memcpy(map_out, nm.data(), sizeof(int32_t) * p.C);
     if (nmigrated) *nmigrated = mig;
     if (lam) {

@@ -54,7 +54,7 @@ class Workload:
     alpha_work: int = 32
     nslots: int = 256
     rebalance_every: int = 0          # 0 = never
-    strategy: str = "greedy"          # greedy | refine | refineswap
+    strategy: str = "greedy"          # greedy | refine | refineswap | greedy_then_refineswap
     threshold: float = 1.05
     t0: int = 0
     seed: int = 0

@@ -189,6 +189,26 @@ def test_host_refineswap_bit_exact_vs_oracle(lib):
             assert nm == int((ref != old).sum())
 
 
+def test_host_greedy_then_refineswap_vs_oracle(lib):
+    """Strategy 3 is Greedy on a first call (no old map) and RefineSwap from the old map
+    otherwise, bit-exact against the oracle's policy."""
+    rng = np.random.default_rng(4)
+    for _ in range(150):
+        C_ = int(rng.integers(1, 200))
+        S = int(rng.integers(1, 30))
+        w = random_loads(rng, C_)
+        m, nm = _abi.balance_host(w, S, "greedy_then_refineswap")
+        ref = oracle.greedy_then_refineswap(w, None, S, 1.05, first=True)
+        np.testing.assert_array_equal(m, ref)
+        assert nm == int((ref != oracle.block_map(C_, S)).sum())
+        old = rng.integers(0, S, size=C_).astype(np.int32)
+        for thr in (1.0, 1.05):
+            m, nm = _abi.balance_host(w, S, "greedy_then_refineswap", old_map=old, threshold=thr)
+            ref = oracle.greedy_then_refineswap(w, old, S, thr, first=False)
+            np.testing.assert_array_equal(m, ref)
+            assert nm == int((ref != old).sum())
+
+
 def test_host_balancer_large_instance(lib):
     wl = W.large()
     k = oracle.kfield(wl.nx, wl.ny, wl.hot, 0, wl.sigma, wl.kmin, wl.kmax)

@@ -277,6 +277,29 @@ def test_measure_rebalance_map_parity():
     assert rel_err(gpu_fields(g), ref_q) <= TOL
 
 
+def test_policy_greedy_then_refineswap_map_parity():
+    """The policy of Experiment C (Table V): the context's first rebalance installs the
+    oracle's Greedy map, each later one the oracle's RefineSwap map from the map in force."""
+    wl = W.shrink(W.moving(), 64, 64, nz=16, steps=40, px=8, py=8).replace(nslots=16)
+    ref_q, work, _, _ = oracle.run(wl)
+    g = Grid(wl)
+    old = oracle.block_map(wl.nchunks, 16)
+    for window in range(4):
+        g.step(10)
+        w = g.measure("work")
+        wref = work[10 * window:10 * (window + 1)].sum(axis=0)
+        np.testing.assert_array_equal(w, wref)
+        if window == 3:
+            break
+        m, nm, _ = g.rebalance("greedy_then_refineswap", 1.05)
+        mref = oracle.greedy_then_refineswap(wref, old, 16, 1.05, first=window == 0)
+        np.testing.assert_array_equal(m, mref)
+        assert nm == int((mref != old).sum())
+        say("window", window, "migrated", nm)
+        old = mref
+    assert rel_err(gpu_fields(g), ref_q) <= TOL
+
+
 def test_time_loads_and_busy_counters():
     wl = W.small()
     g = Grid(wl, nslots=4, wg_per_queue=8)
