@@ -86,15 +86,15 @@ def run_balanced(Grid, wl, steps, warmup, R, params, torch):
         done += n
     g.measure("work")                        # fresh window and busy counters
     torch.cuda.synchronize()
-    evs, wins = [], []
+    # timing events are created before the timed region (creating one is a runtime call)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(-(-steps // R))]
+    wins = []
     t0 = time.perf_counter()
     done = 0
     while done < steps:
         n = min(R, steps - done)
-        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-        loads, nmig, lam = window(n, ev)
-        evs.append(ev)
-        wins.append((loads, nmig, lam))
+        wins.append(window(n, evs[len(wins)]))
         done += n
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

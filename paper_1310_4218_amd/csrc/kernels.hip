@@ -858,7 +858,8 @@ __global__ void k_reset_control(DevArgs a) {
     }
 }
 
-// Table upload: every segment copied word by word, grid-stride.
+// Table upload: segment blockIdx.y copied by the blocks of row y, grid-stride,
+// so that the reads over the bus of all segments are in flight together.
 struct GatherArgs {
     GatherSeg seg[kMaxGather];
     int n;
@@ -866,16 +867,14 @@ struct GatherArgs {
 __global__ __launch_bounds__(256) void k_gather(GatherArgs g) {
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int s = 0; s < g.n; ++s) {
-        const GatherSeg sg = g.seg[s];
-        // 16-byte words where both ends allow it (every table but the item count)
-        const bool wide = ((reinterpret_cast<uintptr_t>(sg.src) | reinterpret_cast<uintptr_t>(sg.dst)) & 15) == 0;
-        const uint32_t nv = wide ? sg.words / 4 : 0;
-        const uint4* src4 = reinterpret_cast<const uint4*>(sg.src);
-        uint4* dst4 = reinterpret_cast<uint4*>(sg.dst);
-        for (uint32_t i = tid; i < nv; i += stride) dst4[i] = src4[i];
-        for (uint32_t i = 4 * nv + tid; i < sg.words; i += stride) sg.dst[i] = sg.src[i];
-    }
+    const GatherSeg sg = g.seg[blockIdx.y];
+    // 16-byte words where both ends allow it (every table but the item count)
+    const bool wide = ((reinterpret_cast<uintptr_t>(sg.src) | reinterpret_cast<uintptr_t>(sg.dst)) & 15) == 0;
+    const uint32_t nv = wide ? sg.words / 4 : 0;
+    const uint4* src4 = reinterpret_cast<const uint4*>(sg.src);
+    uint4* dst4 = reinterpret_cast<uint4*>(sg.dst);
+    for (uint32_t i = tid; i < nv; i += stride) dst4[i] = src4[i];
+    for (uint32_t i = 4 * nv + tid; i < sg.words; i += stride) sg.dst[i] = sg.src[i];
 }
 
 // End of a measurement window: the chosen chunk loads and the tile work go to
@@ -1017,8 +1016,9 @@ int launch_gather(const GatherSeg* segs, int n, void* stream) {
         most = segs[s].words > most ? segs[s].words : most;
     }
     g.n = n;
-    const uint32_t want = (most + 255) / 256;
-    const dim3 grid(want < 256 ? (want > 0 ? want : 1) : 256);
+    if (n == 0) return static_cast<int>(hipSuccess);
+    const uint32_t want = (most / 4 + 255) / 256;   // blocks for the largest segment in 16-byte words
+    const dim3 grid(want < 64 ? (want > 0 ? want : 1) : 64, n);
     hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, static_cast<hipStream_t>(stream), g);
     return static_cast<int>(hipGetLastError());
 }

@@ -68,26 +68,42 @@ bool strictly_increasing(const std::vector<int32_t>& s, int32_t n) {
 
 // Ascending sort of keys (hi 32 bits: ~float bits of a non-negative cost,
 // lo 32 bits: index) given in ascending index order: a stable least-
-// significant-digit radix sort on the high half (four 8-bit passes), which
-// leaves equal costs in index order, i.e. the order of the full 64-bit keys.
+// significant-digit radix sort on the high half (8-bit digits), which leaves
+// equal costs in index order, i.e. the order of the full 64-bit keys.  One
+// read fills the four histograms; a digit that is the same in every key needs
+// no pass.
 void sort_keys(uint64_t* k, int32_t n) {
     if (n < 2) return;
     if (n < 64) {
         std::sort(k, k + n);
         return;
     }
+    int32_t count[4][256];
+    std::memset(count, 0, sizeof(count));
+    for (int32_t i = 0; i < n; ++i) {
+        const uint32_t hi = static_cast<uint32_t>(k[i] >> 32);
+        ++count[0][hi & 0xff];
+        ++count[1][(hi >> 8) & 0xff];
+        ++count[2][(hi >> 16) & 0xff];
+        ++count[3][hi >> 24];
+    }
     std::vector<uint64_t> tmp(static_cast<size_t>(n));
     uint64_t* a = k;
     uint64_t* b = tmp.data();
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 32 + 8 * pass;
-        int32_t count[257] = {0};
-        for (int32_t i = 0; i < n; ++i) ++count[((a[i] >> shift) & 0xff) + 1];
-        for (int d = 0; d < 256; ++d) count[d + 1] += count[d];
-        for (int32_t i = 0; i < n; ++i) b[count[(a[i] >> shift) & 0xff]++] = a[i];
+        int32_t* c = count[pass];
+        if (c[(a[0] >> shift) & 0xff] == n) continue;
+        int32_t run = 0;
+        for (int d = 0; d < 256; ++d) {
+            const int32_t x = c[d];
+            c[d] = run;
+            run += x;
+        }
+        for (int32_t i = 0; i < n; ++i) b[c[(a[i] >> shift) & 0xff]++] = a[i];
         std::swap(a, b);
     }
-    // four passes: the sorted keys are back in k
+    if (a != k) std::memcpy(k, a, sizeof(uint64_t) * static_cast<size_t>(n));
 }
 
 // a mod n in [0, n)

@@ -70,6 +70,13 @@ class Grid:
                                                             st["nslots"], st["nwg"])
         self.nqueues = st["nqueues"]
         self.nrows = st["nrows"]
+        # output buffers of the per-window calls, allocated once (converting a
+        # numpy array to a ctypes pointer costs microseconds per call)
+        n = max(self.nchunks, 1)
+        self._loads_out = (C.c_double * n)()
+        self._map_out = (C.c_int32 * n)()
+        self._nm_out = C.c_int32(0)
+        self._lam_out = (C.c_double * 2)()
 
     # ---- lifecycle -------------------------------------------------------
     def close(self):
@@ -100,23 +107,20 @@ class Grid:
         check(_abi.lib().lb_step(self.handle, int(n), _abi.MODES[mode]), self.handle)
 
     def measure(self, source: str = "work", reset: bool = True) -> np.ndarray:
-        out = np.empty(self.nchunks, dtype=np.float64)
-        check(_abi.lib().lb_measure(self.handle, _abi.SOURCES[source], ptr(out, C.c_double),
-                                    int(reset)), self.handle)
-        return out
+        h = self.handle
+        check(_abi.lib().lb_measure(h, _abi.SOURCES[source], self._loads_out, int(reset)), h)
+        return np.frombuffer(self._loads_out, dtype=np.float64, count=self.nchunks).copy()
 
     def rebalance(self, strategy: str = "greedy", threshold: float = 1.05,
                   loads: Optional[np.ndarray] = None):
         """Returns (map, nmigrated, (lambda_before, lambda_after))."""
-        m = np.empty(self.nchunks, dtype=np.int32)
-        nm = C.c_int32(0)
-        lam = np.zeros(2, dtype=np.float64)
+        h = self.handle
         w = None if loads is None else np.ascontiguousarray(loads, dtype=np.float64)
-        check(_abi.lib().lb_rebalance(self.handle, _abi.STRATEGIES[strategy], threshold,
+        check(_abi.lib().lb_rebalance(h, _abi.STRATEGIES[strategy], threshold,
                                       None if w is None else ptr(w, C.c_double),
-                                      ptr(m, C.c_int32), C.byref(nm), ptr(lam, C.c_double)),
-              self.handle)
-        return m, int(nm.value), (float(lam[0]), float(lam[1]))
+                                      self._map_out, C.byref(self._nm_out), self._lam_out), h)
+        m = np.frombuffer(self._map_out, dtype=np.int32, count=self.nchunks).copy()
+        return m, int(self._nm_out.value), (float(self._lam_out[0]), float(self._lam_out[1]))
 
     def set_map(self, m, cost=None) -> None:
         m = np.ascontiguousarray(m, dtype=np.int32)
