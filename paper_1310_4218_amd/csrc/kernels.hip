@@ -250,9 +250,11 @@ __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70)
 // PIPE = 2, 4 or 8: rows move HBM -> registers -> LDS with PIPE rows in flight
 //   per workgroup (row r + 2 .. r + 1 + PIPE while row r is computed); the
 //   compiler's own wait counts order each row's registers before its LDS
-//   store, so the pipeline needs no barrier-wide wait for memory.  (The
-//   compiler merges its counts conservatively around the conditional row
-//   loads, so in practice depths 4 and 8 wait about as often as depth 2.)
+//   store, so the pipeline needs no barrier-wide wait for memory.  Every lane
+//   issues every row load (lanes without a halo column, and rows past the
+//   item's last, read a valid duplicate): a load inside a divergent or
+//   row-dependent branch makes the compiler wait for all outstanding loads
+//   before the next one, which serialises the pipeline.
 // What an item of the direct-load pipeline hands to the next item of its
 // workgroup: during its last block it issues the next item's first rows into
 // the free part of the ring and looks up the next item's trip counts, so that
@@ -289,6 +291,10 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const ItemD
     gx0 = gx0 < 0 ? gx0 + nx : (gx0 >= nx ? gx0 - nx : gx0);
     int gx1 = x0 - 1 + tcol + TX;
     gx1 = gx1 >= nx ? gx1 - nx : gx1;
+    // Register-path loads are issued by every lane; a lane without a halo
+    // column reads the tile's left halo column instead (and does not store it).
+    const int lx0 = has0 ? gx0 : (x0 == 0 ? nx - 1 : x0 - 1);
+    const int lx1 = has1 ? gx1 : lx0;
     const T cc = static_cast<T>(a.cc), cn = static_cast<T>(a.cn), eps = static_cast<T>(a.eps);
 
     constexpr bool kDma = (PIPE == kPipeDma);
@@ -323,8 +329,8 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const ItemD
             int gy = y0 + i;
             gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
             const T* row = fsrc + static_cast<int64_t>(gy) * nx * nz;
-            if (has0) r0 = ld<T, V>(row + static_cast<int64_t>(gx0) * nz + zoff);
-            if (has1) r1 = ld<T, V>(row + static_cast<int64_t>(gx1) * nz + zoff);
+            r0 = ld<T, V>(row + static_cast<int64_t>(lx0) * nz + zoff);
+            r1 = ld<T, V>(row + static_cast<int64_t>(lx1) * nz + zoff);
         };
         auto put = [&](int i, const Vec<T, V>& r0, const Vec<T, V>& r1) {
             T* row = slot(i);
@@ -383,8 +389,7 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const ItemD
             fetch(0, c0, c1);
             fetch(1, n0, n1);
 #pragma unroll
-            for (int j = 0; j < D; ++j)
-                if (2 + j <= h) fetch(2 + j, R0[(2 + j) % D], R1[(2 + j) % D]);
+            for (int j = 0; j < D; ++j) fetch(min(2 + j, h), R0[(2 + j) % D], R1[(2 + j) % D]);
             if (f == 0) fill_k();
             put(-1, m0, m1);
             put(0, c0, c1);
@@ -404,7 +409,7 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const ItemD
                         const int b = (j + 2) % D;   // == (r + 2) % D: r0 is a multiple of D
                         compute(r);
                         if (r + 2 <= h) put(r + 2, R0[b], R1[b]);
-                        if (r + 2 + D <= h) fetch(r + 2 + D, R0[b], R1[b]);
+                        fetch(min(r + 2 + D, h), R0[b], R1[b]);
                         __syncthreads();
                     }
                 }
