@@ -48,15 +48,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, precision: str, launch: dict):
     """HBM bytes per launch of the persistent kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    counter summary, if it was taken on the current kernel source, in this
+    precision and with this launch shape; else None."""
+    name = workload if precision == "fp32" else f"{workload}_{precision}"
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if (t.get("kernel_source_hash") != kernel_source_hash() or t.get("precision", "fp32") != precision
+            or t.get("launch") != launch):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -243,7 +246,8 @@ def main(argv=None) -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload),
+            "traffic": measured_traffic(args.workload, args.precision,
+                                        {k: v for k, v in params.items() if k != "precision"}),
             "kernel": "k_persistent",
             "bytes_per_launch": bytes_per_step,
             "us_per_launch_events": kernel_step_s * 1e6,

@@ -11,8 +11,10 @@ Both counters are reported in KiB per dispatch.  Each is scaled by what the
 same counter reads for the plain device copy of known size that bench.py runs
 in the same process (--calibration-copy), so the result is in bytes as the
 counter sees them for a kernel whose true traffic is known.  Writes
-profiles/traffic_<workload>.json (per-launch bytes, the scale factors, and a
-hash of the kernel source so that stale numbers are not reported).
+profiles/traffic_<workload>.json (traffic_<workload>_<precision>.json outside
+FP32): per-launch bytes, the scale factors, the precision, the launch shape
+from tuned.json and a hash of the kernel source, so that bench.py reports the
+figure only for the kernel, precision and launch shape it was taken on.
 """
 from __future__ import annotations
 
@@ -23,6 +25,8 @@ import hashlib
 import json
 import os
 import sys
+
+from .autotune import tuned_params
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -113,6 +117,7 @@ def main(argv=None) -> int:
     ap.add_argument("--write", required=True)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--copy-mib", type=float, required=True)
+    ap.add_argument("--precision", default="fp32")
     ap.add_argument("--command", default="", help="command lines that produced the runs")
     args = ap.parse_args(argv)
 
@@ -139,8 +144,10 @@ def main(argv=None) -> int:
                raw_kib_per_launch=dict(fetch=mean(kf), write=mean(kw)),
                calibration=dict(copy_bytes=copy_bytes, fetch_kib=max(cf), write_kib=max(cw),
                                 fetch_scale=f_scale, write_scale=w_scale),
+               precision=args.precision, launch=tuned_params(args.workload, args.precision),
                kernel_source_hash=kernel_source_hash(), command=args.command)
-    path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    name = args.workload if args.precision == "fp32" else f"{args.workload}_{args.precision}"
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))

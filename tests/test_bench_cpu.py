@@ -1,0 +1,38 @@
+"""Host-side pieces of bench.py: the counted-traffic record is reported only for
+the kernel source, precision and launch shape it was taken on."""
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import pytest  # noqa: E402
+
+import bench  # noqa: E402
+from paper_1310_4218_amd.autotune import tuned_params  # noqa: E402
+
+
+def test_traffic_record_matches_current_kernel_and_launch():
+    for w in ("moving", "precision", "large"):
+        path = os.path.join(ROOT, "profiles", f"traffic_{w}.json")
+        with open(path) as f:
+            rec = json.load(f)
+        launch = tuned_params(w, "fp32")
+        if rec["kernel_source_hash"] != bench.kernel_source_hash():
+            pytest.skip(f"traffic_{w}.json was taken on an earlier kernel source (bench reports null)")
+        assert rec["launch"] == launch, w
+        got = bench.measured_traffic(w, "fp32", launch)
+        assert got == rec["hbm_bytes_per_launch"]
+        # the algorithmic bytes are a lower bound of what the counters see
+        wl_bytes = {"moving": 8 * 256 * 256 * 64, "precision": 8 * 1024 * 1024 * 64,
+                    "large": 8 * 2048 * 2048 * 80}[w]
+        assert got > wl_bytes
+
+
+def test_traffic_record_not_reported_for_other_precision_or_launch():
+    launch = tuned_params("moving", "fp32")
+    assert bench.measured_traffic("moving", "fp64", launch) is None
+    other = dict(launch, tile_y=launch.get("tile_y", 8) * 2)
+    assert bench.measured_traffic("moving", "fp32", other) is None
+    assert bench.measured_traffic("no-such-workload", "fp32", launch) is None
