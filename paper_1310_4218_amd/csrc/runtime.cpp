@@ -297,6 +297,7 @@ struct lb_ctx {
     char* staging = nullptr;          // pinned: measured loads and the plan tables (Plan::st_*)
     const char* staging_dev = nullptr;  // the same memory as the device addresses it
     hipEvent_t upload_done = nullptr;
+    hipEvent_t measured_ev = nullptr;   // end of the last measurement's copy
     bool upload_pending = false;
     hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
     hipGraphExec_t g_pers1 = nullptr; // one persistent step
@@ -571,6 +572,21 @@ int sync(lb_ctx* x) {
     return LB_OK;
 }
 
+// Wait for everything enqueued on the stream so far by polling an event
+// recorded behind it.  The measurement sits on the critical path between two
+// windows; polling returns about 10 us sooner per window than
+// hipStreamSynchronize on this system.
+int sync_spin(lb_ctx* x, hipEvent_t ev) {
+    HIP_TRY(x, hipSetDevice(x->device));
+    if (forced_failure("sync")) return fail(&x->err, LB_E_HIP, "forced failure at sync (LBGRID_FAIL_AT)");
+    HIP_TRY(x, hipEventRecord(ev, x->stream));
+    hipError_t q;
+    while ((q = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    if (q != hipSuccess) return fail(&x->err, LB_E_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    return LB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -669,6 +685,8 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     if ((e = hipStreamCreateWithFlags(&x->cap, hipStreamNonBlocking)) != hipSuccess)
         return hip_bail(e, "hipStreamCreateWithFlags");
     if ((e = hipEventCreateWithFlags(&x->upload_done, hipEventDisableTiming)) != hipSuccess)
+        return hip_bail(e, "hipEventCreateWithFlags");
+    if ((e = hipEventCreateWithFlags(&x->measured_ev, hipEventDisableTiming)) != hipSuccess)
         return hip_bail(e, "hipEventCreateWithFlags");
     {
         void* st = nullptr;
@@ -830,8 +848,6 @@ int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
     if (source != LB_LOAD_WORK && source != LB_LOAD_TIME) return fail(&x->err, LB_E_INVAL, "unknown load source");
     const Plan& p = x->plan;
     HIP_TRY(x, hipSetDevice(x->device));
-    // the loads land in pinned staging after the window's last step, the counters
-    // are cleared behind them, and one synchronisation covers both
     // one kernel moves the loads and tile work into pinned staging after the
     // window's last step and clears the counters (work, time, busy and tile
     // counters are adjacent in the workspace); one synchronisation covers it
@@ -844,7 +860,7 @@ int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
                       reinterpret_cast<double*>(const_cast<char*>(x->staging_dev) + p.st_tiles),
                       x->ws + p.off_lw, reset ? p.off_busy + sizeof(double) * p.nwg - p.off_lw : 0,
                       x->stream));
-    int rc = sync(x);
+    int rc = sync_spin(x, x->measured_ev);
     if (rc != LB_OK) return rc;
     x->measured.assign(st, st + p.C);
     x->tile_measured.assign(stt, stt + p.ntiles);
@@ -1043,6 +1059,7 @@ void lb_destroy(lb_ctx* x) {
     if (x->g_pers1) (void)hipGraphExecDestroy(x->g_pers1);
     if (x->g_plain) (void)hipGraphExecDestroy(x->g_plain);
     if (x->upload_done) (void)hipEventDestroy(x->upload_done);
+    if (x->measured_ev) (void)hipEventDestroy(x->measured_ev);
     if (x->staging) (void)hipHostFree(x->staging);
     if (x->cap) (void)hipStreamDestroy(x->cap);
     delete x;
