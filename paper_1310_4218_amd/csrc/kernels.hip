@@ -61,44 +61,49 @@ __device__ __forceinline__ double combine(double cc, double cn, double c, double
     return cc * c + cn * sum;
 }
 
-template <int KAHAN>
-__device__ __forceinline__ void physics(float eps, int k, float& q0) {
-    if (KAHAN) {
-        float q = q0, comp = 0.0f;
-        for (int it = 0; it < k; ++it) {
-            float d = eps * (q - (q * q) * q);
-            float y = d - comp;
-            float t = q + y;
-            comp = (t - q) - y;
-            q = t;
-        }
-        q0 = q;
-    } else {
-        float q = q0;
-        for (int it = 0; it < k; ++it) q = q + eps * (q - (q * q) * q);
-        q0 = q;
-    }
-}
-
-template <int KAHAN>
-__device__ __forceinline__ void physics(double eps, int k, double& q0) {
+// Physics of the V cells of one thread (the per-cell arithmetic in the file
+// header), with the V chains interleaved for ILP; each cell's operations and
+// their order are those of a plain loop over its k iterations.
+template <int V>
+__device__ __forceinline__ void physics_vec_fp64(double eps, int k, double (&q)[V]) {
 #pragma clang fp contract(off)
-    double q = q0;
     for (int it = 0; it < k; ++it) {
-        double q3 = (q * q) * q;
-        q = q + eps * (q - q3);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const double q3 = (q[v] * q[v]) * q[v];
+            q[v] = q[v] + eps * (q[v] - q3);
+        }
     }
-    q0 = q;
 }
 
-// V cells of one thread, with all V chains interleaved for ILP.
 template <int KAHAN, typename T, int V>
 __device__ __forceinline__ void physics_vec(T eps, int k, T (&q)[V]) {
-    if constexpr (KAHAN || sizeof(T) == 8) {
+    if constexpr (sizeof(T) == 8) {
+        physics_vec_fp64<V>(eps, k, q);
+    } else if constexpr (KAHAN) {
+        float comp[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) physics<KAHAN>(eps, k, q[v]);
-    } else {
+        for (int v = 0; v < V; ++v) comp[v] = 0.0f;
         for (int it = 0; it < k; ++it) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float d = eps * (q[v] - (q[v] * q[v]) * q[v]);
+                const float y = d - comp[v];
+                const float t = q[v] + y;
+                comp[v] = (t - q[v]) - y;
+                q[v] = t;
+            }
+        }
+    } else {
+        // two iterations per trip: half the loop-control instructions
+        int it = 0;
+        for (; it + 1 < k; it += 2) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) q[v] = q[v] + eps * (q[v] - (q[v] * q[v]) * q[v]);
+#pragma unroll
+            for (int v = 0; v < V; ++v) q[v] = q[v] + eps * (q[v] - (q[v] * q[v]) * q[v]);
+        }
+        if (it < k) {
 #pragma unroll
             for (int v = 0; v < V; ++v) q[v] = q[v] + eps * (q[v] - (q[v] * q[v]) * q[v]);
         }
