@@ -45,14 +45,19 @@ def _key(arch: str, workload: str, precision: str) -> str:
 
 
 def tuned_params(workload_name: str, precision: str = "fp32", arch: str = None) -> dict:
-    """Cached launch parameters for a workload, or {} when none were tuned."""
+    """Cached launch parameters for a workload, or {} when none were tuned.  FP32
+    with Kahan summation has the FP32 data layout and kernels; without an entry
+    of its own it takes the FP32 one."""
     if not os.path.exists(CACHE):
         return {}
     with open(CACHE) as f:
         cache = json.load(f)
     if arch is None:
         arch = "gfx950"
-    return dict(cache.get(_key(arch, workload_name, precision), {}).get("params", {}))
+    entry = cache.get(_key(arch, workload_name, precision))
+    if entry is None and precision in ("fp32_kahan", "kahan"):
+        entry = cache.get(_key(arch, workload_name, "fp32"))
+    return dict((entry or {}).get("params", {}))
 
 
 def _feasible(wl, p: dict) -> bool:
