@@ -426,8 +426,10 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     std::vector<uint64_t> order(static_cast<size_t>(p.ntiles));
     {
         std::vector<int32_t> fill(qoff.begin(), qoff.end() - 1);
-        for (int32_t c = 0; c < p.C; ++c)
-            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) order[fill[x->map[c] % p.Q]++] = key_of(t);
+        for (int32_t c = 0; c < p.C; ++c) {
+            int32_t& at = fill[x->map[c] % p.Q];
+            for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) order[at++] = key_of(t);
+        }
     }
     for (int32_t q = 0; q < p.Q; ++q) sort_keys(order.data() + qoff[q], qoff[q + 1] - qoff[q]);
     auto tile_at = [&](int32_t i) { return static_cast<int32_t>(order[i] & 0xffffffffu); };
@@ -457,8 +459,17 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
         for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) {
             const int w = x->tiles[4 * t + 2] & 0xffff, h = x->tiles[4 * t + 2] >> 16;
             item_first[t] = static_cast<int32_t>(x->items.size());
-            for (int k = 0; k < pieces[t]; ++k) {
-                const int r0 = (k * h) / pieces[t], r1 = ((k + 1) * h) / pieces[t];
+            // piece k covers rows [floor(k h / parts), floor((k + 1) h / parts)),
+            // stepped exactly with one division per tile: the next bound is the
+            // last one plus h / parts, plus one when the kept remainder
+            // k h mod parts wraps
+            const int parts = pieces[t], step = h / parts, extra = h - step * parts;
+            int r1 = 0, rem = 0;
+            for (int k = 0; k < parts; ++k) {
+                const int r0 = r1;
+                rem += extra;
+                r1 = r0 + step + (rem >= parts ? 1 : 0);
+                if (rem >= parts) rem -= parts;
                 ItemDesc d{};
                 d.x0 = x->tiles[4 * t + 0];
                 d.y0 = x->tiles[4 * t + 1] + r0;
@@ -502,15 +513,27 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     const DevArgs& a = x->args;
     ItemDesc none{};
     none.id = -1;
+    // (home, rank) of workgroup w, stepped with counters rather than two
+    // divisions per workgroup: qh, qr are (w >> 3) mod and div Q / 8 with XCD
+    // queues, else w mod and div Q
+    const int per_xcd = a.xcd_queues ? p.Q / 8 : 1;
+    int qh = 0, qr = 0;
     for (int32_t w = 0; w < p.nwg; ++w) {
         int home, rank;
         if (a.xcd_queues) {
-            const int per_xcd = p.Q / 8;
-            home = (w & 7) + 8 * ((w >> 3) % per_xcd);
-            rank = (w >> 3) / per_xcd;
+            home = (w & 7) + 8 * qh;
+            rank = qr;
+            if ((w & 7) == 7 && ++qh == per_xcd) {
+                qh = 0;
+                ++qr;
+            }
         } else {
-            home = w % p.Q;
-            rank = w / p.Q;
+            home = qh;
+            rank = qr;
+            if (++qh == p.Q) {
+                qh = 0;
+                ++qr;
+            }
         }
         const int nq = st_seg[home + 1] - st_seg[home];
         const int second = 2 * p.G - 1 - rank;
