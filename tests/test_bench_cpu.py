@@ -36,3 +36,9 @@ def test_traffic_record_not_reported_for_other_precision_or_launch():
     other = dict(launch, tile_y=launch.get("tile_y", 8) * 2)
     assert bench.measured_traffic("moving", "fp32", other) is None
     assert bench.measured_traffic("no-such-workload", "fp32", launch) is None
+
+
+def test_kahan_takes_the_fp32_launch_shape():
+    for w in ("moving", "precision", "large"):
+        assert tuned_params(w, "fp32_kahan") == tuned_params(w, "fp32")
+    assert tuned_params("no-such-workload", "fp32_kahan") == {}
