@@ -32,11 +32,11 @@ SPACE = {
     "tile_y": [2, 4, 8, 16, 32],
     "nqueues": [1, 8, 32, 256],
     "wg_per_queue": [0],          # 0: fill the device (resident workgroups / queues)
-    "item_split": [0, 1, 2, 3, 4, 6, 8],
+    "item_split": [0, 1, 2, 3, 4, 5, 6, 8],
     "stage_rows": [-1, -4, -8, 2, 4, 6, 8],   # -1, -4, -8: register pipeline 2/4/8 rows deep;
                                               # n > 0: direct-to-LDS batches of n rows
     "tail_split": [0, 2, 4, 8],
-    "item_alpha": [-1, 8, 2, 0],  # -1: items sized with the balancer's alpha_work
+    "item_alpha": [-1, 8, 4, 2, 1, 0],  # -1: items sized with the balancer's alpha_work
 }
 
 
