@@ -33,8 +33,10 @@ std::vector<int32_t> heavy_first(const double* w, int32_t C) {
 // (load, slot) pairs gives the lowest load with the lowest index on ties.
 void greedy(const double* w, int32_t C, int32_t S, int32_t* map) {
     using Entry = std::pair<double, int32_t>;
-    std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> heap;
-    for (int32_t s = 0; s < S; ++s) heap.push({0.0, s});
+    std::vector<Entry> empty(static_cast<size_t>(S));
+    for (int32_t s = 0; s < S; ++s) empty[s] = {0.0, s};   // ascending: already a min-heap
+    std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> heap(std::greater<Entry>(),
+                                                                             std::move(empty));
     for (int32_t c : heavy_first(w, C)) {
         Entry e = heap.top();
         heap.pop();
