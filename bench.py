@@ -21,7 +21,6 @@ moving one cell per step (k in 1..200, sigma 24), balanced onto 256 slots.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from paper_1310_4218_amd.traffic import kernel_source_hash  # noqa: E402
+
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid point-updates/s and max/avg chunk-load ratio, balanced vs plain, 1 MI355X"
 # Steps of a window are launched one by one (LB_PERSISTENT_EAGER): after each
@@ -38,14 +39,6 @@ METRIC = "grid point-updates/s and max/avg chunk-load ratio, balanced vs plain, 
 # a graph replay first submits all R launches; measured on the default
 # workload this saves about 1 us per step (the kernels are identical).
 MODE = "persistent_eager"
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "lbgrid_internal.h"):
-        with open(os.path.join(ROOT, "paper_1310_4218_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str, precision: str, launch: dict):

@@ -24,6 +24,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 from .autotune import tuned_params
@@ -32,10 +33,16 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device code's tokens (comments and layout removed), so that a
+    counter record stays valid across comment-only edits and no longer after a
+    code change."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "lbgrid_internal.h"):
-        with open(os.path.join(ROOT, "paper_1310_4218_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1310_4218_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
