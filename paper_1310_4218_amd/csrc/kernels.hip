@@ -18,7 +18,9 @@
 // while later rows are in flight, either straight into the ring (direct
 // global->LDS loads, B rows per batch) or through registers (2, 4 or 8 rows).
 // Every cell is read from HBM once per item and written once; halo columns and
-// halo rows are re-read by the neighbouring items (mostly from L2 / MALL).
+// halo rows are re-read by the neighbouring items, and the register pipeline
+// re-reads an item's last halo row in place of rows past the item (mostly
+// from L2 / MALL).
 //
 // Arithmetic per cell, with s the stencil value and k the column's trip count:
 //   FP32:        q <- fma(eps, fma(-(q*q), q, q), q), k times
