@@ -13,7 +13,8 @@ paths are timed on the same inputs:
             cost-ordered queues, measurement + rebalance every R steps, all
             inside the timed region;
   plain:    one launch per chunk over its tiles, in chunk-id order, no
-            balancing (the static decomposition).
+            balancing (the static decomposition); timed twice, with the
+            launches enqueued one by one and replayed from a captured graph.
 ``value`` is the balanced path's point-updates/s (cells x steps / wall time).
 The default workload is the 256x256x64 grid with 64 equal chunks and a hotspot
 moving one cell per step (k in 1..200, sigma 24), balanced onto 256 slots.
@@ -104,13 +105,16 @@ def run_balanced(Grid, wl, steps, warmup, R, params, torch):
     return dict(wall=wall, kernel_s=kernel_s, wins=wins, busy=busy, stats=st)
 
 
-def run_plain(Grid, wl, steps, warmup, params, torch):
+def run_plain(Grid, wl, steps, warmup, params, torch, mode="plain"):
+    """The paper's static form: one launch per chunk and step (mode "plain"), or
+    the same launches replayed from a captured graph ("plain_graph"), which
+    separates the cost of launching from the cost of imbalance."""
     p = {k: v for k, v in params.items() if k in ("tile_x", "tile_y")}
     g = Grid(wl, **p)
-    g.step(warmup, "plain")
+    g.step(warmup, mode)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g.step(steps, "plain")
+    g.step(steps, mode)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     g.close()
@@ -178,15 +182,18 @@ def main(argv=None) -> int:
     bal = run_balanced(Grid, wl, args.steps, args.warmup, R, params, torch)
     log(f"balanced: {bal['wall'] * 1e3 / args.steps:.4f} ms/step, "
         f"kernel {bal['kernel_s'] * 1e6 / args.steps:.2f} us/step")
-    plain = None
+    plain = plain_graph = None
     if not args.no_plain:
         ps = args.plain_steps or min(args.steps, 100)
         plain = run_plain(Grid, wl, ps, max(1, args.warmup // 4), params, torch)
         log(f"plain: {plain['wall'] * 1e3 / ps:.4f} ms/step")
+        plain_graph = run_plain(Grid, wl, ps, max(1, args.warmup // 4), params, torch, "plain_graph")
+        log(f"plain, graph replay: {plain_graph['wall'] * 1e3 / ps:.4f} ms/step")
 
     cells = wl.ncells * wl.nfields
     value = cells * args.steps / bal["wall"]
     plain_value = cells * plain["steps"] / plain["wall"] if plain else None
+    plain_graph_value = cells * plain_graph["steps"] / plain_graph["wall"] if plain_graph else None
 
     def lam_of(w, m):
         L = np.bincount(m, weights=w, minlength=S)
@@ -227,6 +234,8 @@ def main(argv=None) -> int:
             "balanced_point_updates_per_s": value,
             "plain_point_updates_per_s": plain_value,
             "speedup": value / plain_value if plain_value else None,
+            "plain_graph_point_updates_per_s": plain_graph_value,
+            "speedup_vs_plain_graph": value / plain_graph_value if plain_graph_value else None,
             "lambda_balanced": lam_bal,
             "lambda_plain": lam_plain,
             "lambda_star": lam_star,
