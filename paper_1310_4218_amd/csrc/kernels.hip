@@ -220,9 +220,13 @@ __device__ void block_sum2(double& a, double& b, double* red, int bs) {
 constexpr int kPipeDma = 1;   // pipeline template value of the direct global->LDS path
 
 // Largest workgroup of a pipeline.  The deeper register pipelines keep 4 or 8
-// rows in registers, which needs more than the 128 VGPRs a 1024-thread
-// workgroup allows; they are limited to 512 threads (up to 256 VGPRs).
-constexpr int max_block(int pipe) { return pipe >= 4 && pipe != kPipeDma ? kMaxBlockDeep : kMaxBlock; }
+// rows in registers, and FP64 rows take twice the registers; both need more
+// than the 128 VGPRs a 1024-thread workgroup allows (the FP64 depth-2 kernel
+// spilled at that bound), so they are limited to 512 threads (up to 256 VGPRs).
+template <typename T>
+constexpr int max_block(int pipe) {
+    return pipe != kPipeDma && (pipe >= 4 || sizeof(T) == 8) ? kMaxBlockDeep : kMaxBlock;
+}
 struct ItemOut {
     double checksum;  // sum of the item's outputs over all fields (valid in thread 0)
     double work;      // work units of the item (valid in thread 0)
@@ -686,7 +690,7 @@ __device__ __forceinline__ ItemDesc no_item() {
 // the last workgroup of the next step (or by k_flush), so workgroups simply
 // exit and the launch boundary orders one step before the next.
 template <typename T, int V, int KAHAN, int PIPE>
-__global__ __launch_bounds__(max_block(PIPE)) void k_persistent(DevArgs a) {
+__global__ __launch_bounds__(max_block<T>(PIPE)) void k_persistent(DevArgs a) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
     __shared__ double red[kRedLen];
@@ -781,7 +785,7 @@ __global__ __launch_bounds__(max_block(PIPE)) void k_persistent(DevArgs a) {
 }
 
 template <typename T, int V, int KAHAN, int PIPE>
-__global__ __launch_bounds__(max_block(PIPE)) void k_plain(DevArgs a, int chunk) {
+__global__ __launch_bounds__(max_block<T>(PIPE)) void k_plain(DevArgs a, int chunk) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
     __shared__ double red[2 * kMaxBlock / kWave];

@@ -191,7 +191,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         p.TX = c->tile_x;
     } else {
         p.TX = 16;
-        const int most = (p.B == 0 && p.RD >= 4) ? kMaxBlockDeep : kMaxBlock;
+        const int most = (p.B == 0 && (p.RD >= 4 || p.prec == LB_FP64)) ? kMaxBlockDeep : kMaxBlock;
         while (p.TX > 1 && (p.TX * NQ > most || lds_for(p.TX) > 64 * 1024)) --p.TX;
     }
     if (p.TX > 1024 || p.TY > 256) return bad("tile sizes must be at most 1024 x 256");
@@ -199,6 +199,8 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (p.block > kMaxBlock) return bad("tile_x * nz / vector width exceeds 1024 threads");
     if (p.B == 0 && p.RD >= 4 && p.block > kMaxBlockDeep)
         return bad("register pipeline depth 4 or 8 needs tile_x * nz / 4 <= 512 threads");
+    if (p.B == 0 && p.prec == LB_FP64 && p.block > kMaxBlockDeep)
+        return bad("FP64 with the register pipeline needs tile_x * nz / V <= 512 threads");
     p.lds = lds_for(p.TX);
     if (p.lds > kMaxLds) return bad("tile too large: the LDS row ring and trip counts exceed 160 KiB");
 

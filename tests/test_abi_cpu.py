@@ -75,6 +75,7 @@ def test_query_rejects_bad_config(lib, field, value, msg):
     (dict(stage_rows=33), "stage_rows"), (dict(stage_rows=-8, precision=2), "FP32 only"),
     (dict(stage_rows=-4, nz=6), "divisible by 4"), (dict(stage_rows=2, nz=6), "divisible by 4"),
     (dict(stage_rows=-4, tile_x=80), "512 threads"),
+    (dict(stage_rows=-1, precision=2, tile_x=80), "FP64"),
 ])
 def test_query_rejects_bad_pipeline(lib, over, msg):
     """Register pipeline depths are 2, 4 or 8 rows; the deep ones need V = 4 and
