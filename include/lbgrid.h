@@ -124,7 +124,9 @@ typedef struct {
                                 register pipeline; -1 or -2: register pipeline
                                 with 2 rows in flight; -4, -8: 4 or 8 rows in
                                 flight (nz % 4 == 0, at most 512 threads per
-                                workgroup; -8 in FP32 only)                  */
+                                workgroup; -8 in FP32 only).  In FP64 every
+                                register pipeline allows at most 512 threads
+                                per workgroup (tile_x * nz / V)              */
     int32_t physics;         /* LB_PHYS_POINTWISE | LB_PHYS_VERTICAL (the
                                 latter needs nz/V to divide 64)               */
     int32_t tail_split;      /* in every queue, the cheapest tiles whose items
