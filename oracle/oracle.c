@@ -29,10 +29,10 @@
  *    level below (Fig. 1 / Fig. 4 as written).
  *  - Section V / Section VI: load is measured per virtual processor (chunk);
  *    here in deterministic work units w_c = sum over columns of nz*(alpha+k).
- *  - Section VI, Experiment A: GreedyLB "always assigns the heaviest object to
- *    the least loaded processor".  Experiment B: RefineSwapLB moves objects
- *    away from the most overloaded processors towards the average, swapping
- *    when no single move fits.  Refine is the move-only half.
+ *  - Section VI, Experiment A: GreedyLB places objects heaviest first, each on
+ *    the processor with the least load so far.  Experiment B: RefineSwapLB
+ *    moves objects off the most overloaded processors towards the average,
+ *    swapping when no single move fits.  Refine is the move-only half.
  *
  * Parity status of each function: pinned by the CPU tests (closed-form
  * eigenmodes, constants, mass, symmetry, published generator outputs,
