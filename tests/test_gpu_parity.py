@@ -200,6 +200,19 @@ def test_ragged_fp64_bit_exact(shape):
         g.close()
 
 
+def test_fp64_register_pipeline_at_its_workgroup_limit():
+    """FP64 register-path kernels are built for at most 512 threads: a 32-column tile of
+    64 levels (512 threads) runs at that limit, bit-exact, in every depth that FP64 has."""
+    wl = mk(70, 40, 64, 2, 2, hot=((20, 20, 1, 0),), sigma=5.0, kmax=40, steps=3, nslots=2)
+    ref, work, _, _ = oracle.run(wl, nsteps=3)
+    for over in (dict(tile_x=32, tile_y=4, stage_rows=-1), dict(tile_x=32, tile_y=3, stage_rows=-4)):
+        g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
+        assert g.stats()["block"] == 512
+        np.testing.assert_array_equal(q, ref)
+        np.testing.assert_array_equal(w, work.sum(axis=0))
+        g.close()
+
+
 def test_multi_field_fp64_bit_exact():
     wl = mk(24, 20, 8, 3, 2, steps=3).replace(nfields=3)
     g, q, w = run_gpu(wl, 3, "persistent", precision="fp64")
