@@ -1,13 +1,14 @@
 """Benchmark: grid point-updates/s and max/avg slot-load ratio, balanced vs plain, 1 GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload moving]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
 
 A step is one time step of the whole hot path on the synthetic workload: the
 cost field, the 7-point update, the column physics, the per-chunk load
 measurement and the FP64 checksum, all in the library's HIP kernels; every
-R steps (R = 10 for the default workload) the loads of the window are read
-back and GreedyLB remaps the chunks onto the slots (the paper's migration
-point, Section VI), which also rebuilds the cost-ordered item queues.  Two
+R steps (R = 10 for every workload) the loads of the window are read back and
+the workload's balancer (GreedyLB or RefineLB) remaps the chunks onto the
+slots (the paper's migration point, Section VI), which also rebuilds the
+cost-ordered item queues.  Two
 paths are timed on the same inputs:
   balanced: one persistent launch per step (launched step by step), per-slot
             cost-ordered queues, measurement + rebalance every R steps, all
@@ -16,8 +17,17 @@ paths are timed on the same inputs:
             balancing (the static decomposition); timed twice, with the
             launches enqueued one by one and replayed from a captured graph.
 ``value`` is the balanced path's point-updates/s (cells x steps / wall time).
-The default workload is the 256x256x64 grid with 64 equal chunks and a hotspot
-moving one cell per step (k in 1..200, sigma 24), balanced onto 256 slots.
+The default workload is the largest single-GPU configuration: the 2048x2048x80
+grid in 4096 uneven (Dirichlet) chunks with a hotspot moving diagonally two
+cells per step (k in 1..400, sigma 64), RefineLB (threshold 1.05) onto 256
+slots every 10 steps.
+
+A third, ablation leg isolates the balancer (the paper's before/after
+comparison of Section VI, Tables III-V): the same persistent kernel with one
+queue per slot and no stealing, so that the chunk->slot map alone decides
+which workgroups run which chunk, once with the static block map and once
+with the balancer's map, both re-costed from the same measured loads every
+window.
 """
 from __future__ import annotations
 
@@ -121,20 +131,100 @@ def run_plain(Grid, wl, steps, warmup, params, torch, mode="plain"):
     return dict(wall=wall, steps=steps)
 
 
+def host_description() -> dict:
+    """nproc, the CPUs this process may run on and the CPU model of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), affinity_cpus=len(os.sched_getaffinity(0)), cpu_model=model)
+
+
 def cpu_baseline(wl, budget_s):
+    """The single-threaded FP64 C oracle on the same workload, pinned in-process to one
+    core (the lowest CPU this process may use): steps from the seeded field, as many as
+    fit in about budget_s seconds (at least one).  The timed calls include one copy of
+    the input field per call."""
     import oracle
 
-    t = time.perf_counter()
-    oracle.run(wl, nsteps=1)
-    one = max(time.perf_counter() - t, 1e-6)
-    n = max(1, min(wl.steps, int(budget_s / one)))
-    t = time.perf_counter()
-    oracle.run(wl, nsteps=n)
-    dt = time.perf_counter() - t
+    host = host_description()
+    allowed = os.sched_getaffinity(0)
+    cpu = min(allowed)
+    os.sched_setaffinity(0, {cpu})
+    try:
+        q0 = oracle.init_field(wl.nx, wl.ny, wl.nz, wl.seed, wl.nfields)
+        t = time.perf_counter()
+        oracle.run(wl, q0=q0, nsteps=1)
+        one = max(time.perf_counter() - t, 1e-6)
+        n = max(1, min(wl.steps, int(budget_s / one)))
+        if n == 1:
+            dt = one
+        else:
+            t = time.perf_counter()
+            oracle.run(wl, q0=q0, nsteps=n)
+            dt = time.perf_counter() - t
+    finally:
+        os.sched_setaffinity(0, allowed)
     return dict(value=wl.ncells * wl.nfields * n / dt, unit="point-updates/s", cores=1,
-                kind="oracle",
-                sample=f"{n} steps of the {wl.name} workload from its seeded field "
-                       "(single-threaded FP64 C oracle, one core)")
+                kind="oracle", pinned_cpu=cpu, **host,
+                sample=f"{n} step(s) of the {wl.name} workload from its seeded field "
+                       "(single-threaded FP64 C oracle, pinned to one core)")
+
+
+def run_ablation(Grid, wl, steps, warmup, R, params, torch, balance_host):
+    """The balancer's own effect: one queue per slot, no stealing, the same kernel and
+    items, the static block map against the balancer's map.  Every window both legs
+    measure their loads and re-install their map with those costs (lb_set_map), the
+    balanced leg after remapping with the workload's strategy from the map in force."""
+    import numpy as np
+
+    S = wl.nslots
+    p = {k: v for k, v in params.items() if k not in ("nqueues", "steal", "wg_per_queue")}
+    block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)],
+                     dtype=np.int32)
+    out = {}
+    for leg in ("block", "balanced"):
+        g = Grid(wl, graph_steps=R, nqueues=S, steal=0, wg_per_queue=0, **p)
+        m = block.copy()
+        first = True
+        lam_in_force, lam_star, us = [], [], []
+        done = -warmup
+        while done < steps:
+            n = R
+            timed = done >= 0
+            if timed:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(g.stream)
+            g.step(n, MODE)
+            if timed:
+                e1.record(g.stream)
+            w = g.measure("work")
+            if timed:
+                torch.cuda.synchronize()
+                us.append(e0.elapsed_time(e1) * 1e3 / n)
+                L = np.bincount(m, weights=w, minlength=S)
+                lam_in_force.append(float(L.max() / (w.sum() / S)))
+                lam_star.append(float(max(1.0, S * w.max() / w.sum())))
+            if leg == "balanced":
+                strat = wl.strategy
+                if strat == "greedy_then_refineswap":
+                    strat = "greedy" if first else "refineswap"
+                m, _ = balance_host(w, S, strat, None if (first and strat == "greedy") else m,
+                                    wl.threshold)
+                first = False
+            g.set_map(m, w)
+            done += n
+        st = g.stats()
+        g.close()
+        out[leg] = dict(us_per_step=float(np.mean(us)), lambda_map_in_force=float(np.mean(lam_in_force)),
+                        lambda_star=float(np.mean(lam_star)), queues=st["nqueues"], workgroups=st["nwg"])
+    out["speedup_balanced_over_block"] = out["block"]["us_per_step"] / out["balanced"]["us_per_step"]
+    return out
 
 
 def main(argv=None) -> int:
@@ -142,12 +232,14 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="moving")
+    ap.add_argument("--workload", default="large")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_kahan", "fp64"])
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the block-vs-balanced map leg")
+    ap.add_argument("--ablation-steps", type=int, default=50)
     ap.add_argument("--no-tuned", action="store_true", help="library default launch shape")
     ap.add_argument("--set", action="append", default=[], help="launch override key=value")
     ap.add_argument("--calibration-copy", type=float, default=0.0, metavar="MIB",
@@ -163,6 +255,7 @@ def main(argv=None) -> int:
     import torch
 
     from paper_1310_4218_amd import workloads as W
+    from paper_1310_4218_amd._abi import balance_host
     from paper_1310_4218_amd.autotune import tuned_params
     from paper_1310_4218_amd.grid import Grid
 
@@ -190,6 +283,12 @@ def main(argv=None) -> int:
         plain_graph = run_plain(Grid, wl, ps, max(1, args.warmup // 4), params, torch, "plain_graph")
         log(f"plain, graph replay: {plain_graph['wall'] * 1e3 / ps:.4f} ms/step")
 
+    ablation = None
+    if not args.no_ablation and wl.nchunks > 1:
+        ablation = run_ablation(Grid, wl, args.ablation_steps, R, R, params, torch, balance_host)
+        log(f"ablation (one queue per slot, no stealing): block {ablation['block']['us_per_step']:.1f} "
+            f"us/step, balanced {ablation['balanced']['us_per_step']:.1f} us/step")
+
     cells = wl.ncells * wl.nfields
     value = cells * args.steps / bal["wall"]
     plain_value = cells * plain["steps"] / plain["wall"] if plain else None
@@ -209,6 +308,9 @@ def main(argv=None) -> int:
 
     elem = 8 if args.precision == "fp64" else 4
     bytes_per_step = 2 * elem * cells
+    # both field copies larger than the 256 MB Infinity Cache: every step streams from HBM;
+    # smaller grids stay cache-resident and are bound by latency and fixed costs instead
+    hbm_resident = bytes_per_step > 256 * 2 ** 20
     kernel_step_s = bal["kernel_s"] / args.steps
     achieved = bytes_per_step / kernel_step_s / 1e9
     st = bal["stats"]
@@ -240,10 +342,13 @@ def main(argv=None) -> int:
             "lambda_plain": lam_plain,
             "lambda_star": lam_star,
             "lambda_wg": lam_wg,
+            "queues": st["nqueues"],
+            "map_inert": st["nqueues"] == 1,
             "migrations_per_rebalance": float(np.mean([n for _, n, _ in bal["wins"]])),
         },
+        "ablation_map_only": ablation,
         "roofline": {
-            "bound": "hbm",
+            "bound": "hbm" if hbm_resident else "latency",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -182,9 +182,10 @@ int lb_query(const lb_config *cfg, lb_buffers *sizes_out);
  * ((splitmix64 output n+1) >> 40 - 2^23) * 2^-23), else nfields*ny*nx*nz
  * values of the precision's element type (float for LB_FP32 and
  * LB_FP32_KAHAN, double for LB_FP64), host or device memory.
- * The initial chunk->slot map is the block map floor(c*S/C) (c for C < S)
- * (Section VI, Table V: "0000 1111 2222 3333").  Returns LB_OK and *out, or
- * an error with *out = NULL. */
+ * The initial chunk->slot map is the block map floor(c*S/C) (c for C < S):
+ * every slot holds a contiguous run of chunk ids, the starting placement of
+ * the VPs in Section VI, Table V.  Returns LB_OK and *out, or an error with
+ * *out = NULL. */
 int lb_grid_init(const lb_config *cfg, const lb_buffers *bufs, void *hip_stream,
                  const void *init_field, lb_ctx **out);
 
@@ -194,11 +195,17 @@ int lb_grid_init(const lb_config *cfg, const lb_buffers *bufs, void *hip_stream,
  * current measurement window (Section V: the measured time steps). */
 int lb_step(lb_ctx *ctx, int32_t nsteps, int32_t mode);
 
-/* Synchronize, copy the window's per-chunk loads (C doubles; LB_LOAD_WORK:
+/* The load measurement of Section V: the runtime's per-VP load database,
+ * filled during the instrumented time steps of a migration window (Fig. 2
+ * turns instrumentation on for the window's last steps, which Section V runs
+ * synchronously so that GPU time is attributed to the right VP).  Here every
+ * step is instrumented inside the kernel, with no serialisation.
+ * Synchronize, copy the window's per-chunk loads (C doubles; LB_LOAD_WORK:
  * sum over steps of nz*nfields*(alpha_work + k) per column, exact integers;
- * LB_LOAD_TIME: in-kernel wall-clock ticks) to loads_out (may be NULL) and,
- * when reset != 0, start a new window.  The copy is also kept for
- * lb_rebalance. */
+ * LB_LOAD_TIME: in-kernel wall-clock ticks of the chunk's items) to loads_out
+ * (may be NULL) and, when reset != 0, start a new window.  The copy is also
+ * kept for lb_rebalance.  Errors: LB_E_INVAL (ctx NULL, unknown source),
+ * LB_E_HIP (the synchronisation or the copy failed). */
 int lb_measure(lb_ctx *ctx, int32_t source, double *loads_out, int32_t reset);
 
 /* Compute a new chunk->slot map with strategy LB_GREEDY (Section VI,
@@ -219,10 +226,16 @@ int lb_rebalance(lb_ctx *ctx, int32_t strategy, double threshold, const double *
  * the queue order (NULL: equal costs, chunk id order). */
 int lb_set_map(lb_ctx *ctx, const int32_t *map, const double *cost);
 
-/* Synchronize and copy field `field` of the current step (native precision,
- * ny*nx*nz elements) to dst (host or device, dst_bytes at least that) when
- * dst is not NULL; *checksum_out (may be NULL) receives the FP64 sum of its
- * cells, computed on the device in a fixed order. */
+/* The full-data transfer of Fig. 2: before each migration call the
+ * application copies its fields from the GPU to the host (and back after it).
+ * On one GPU nothing has to move for a migration, so this is the checkpoint
+ * and read-back path.
+ * Synchronize and copy field `field` of the current step (native precision,
+ * ny*nx*nz elements, layout [y][x][z]) to dst (host or device, dst_bytes at
+ * least that) when dst is not NULL; *checksum_out (may be NULL) receives the
+ * FP64 sum of its cells, computed on the device in a fixed order.  Errors:
+ * LB_E_INVAL (field out of range), LB_E_NOMEM (dst_bytes too small),
+ * LB_E_HIP. */
 int lb_fields(lb_ctx *ctx, int32_t field, void *dst, size_t dst_bytes, double *checksum_out);
 
 /* Synchronize and fill *out. */
@@ -247,10 +260,14 @@ int lb_visits(lb_ctx *ctx, int32_t *out, int32_t n, int32_t reset);
  * min(n, 1024, steps) steps, oldest first.  Returns the count in *got. */
 int lb_checksums(lb_ctx *ctx, double *out, int32_t n, int32_t *got);
 
-/* Host-only balancer (no GPU, no context): the same computation lb_rebalance
- * uses.  old_map may be NULL for LB_GREEDY (then *nmigrated counts chunks off
- * the block map).  LB_GREEDY_THEN_REFINESWAP runs Greedy when old_map is NULL
- * (a first call) and RefineSwap from old_map otherwise. */
+/* The balancers of Section VI (Experiment A: GreedyLB; Experiments B and C:
+ * RefineSwapLB and the Greedy-then-RefineSwap policy) without a GPU or a
+ * context: the same computation lb_rebalance uses.  loads: C doubles >= 0;
+ * old_map: C slot indices in [0, S), or NULL for LB_GREEDY (then *nmigrated
+ * counts chunks off the block map); map_out: C int32, caller-allocated.
+ * LB_GREEDY_THEN_REFINESWAP runs Greedy when old_map is NULL (a first call)
+ * and RefineSwap from old_map otherwise.  Errors: LB_E_INVAL (bad sizes,
+ * loads, threshold or map entries). */
 int lb_balance_host(const double *loads, const int32_t *old_map, int32_t C, int32_t S,
                     int32_t strategy, double threshold, int32_t *map_out, int32_t *nmigrated);
 

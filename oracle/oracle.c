@@ -36,7 +36,9 @@
  *
  * Parity status of each function: pinned by the CPU tests (closed-form
  * eigenmodes, constants, mass, symmetry, published generator outputs,
- * exhaustive search for the balancers).
+ * exhaustive search for the balancers).  The order inside a step (stencil,
+ * then physics) is pinned by a delta field; the windowed runner and the
+ * windowed initial field by the whole-grid run they must reproduce.
  */
 #include <math.h>
 #include <stdint.h>

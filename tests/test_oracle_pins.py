@@ -298,3 +298,109 @@ def test_vertical_odd_symmetric_and_bounded():
     assert np.abs(a).max() <= 1.0
     p, _, _, _ = oracle.run(wl.replace(vertical=0), q0=q0)
     assert not np.array_equal(a, p)                   # the two physics differ
+
+
+# ---------------------------------------------------------------- step order and windows
+@pytest.mark.parametrize("k", [1, 5, 37])
+def test_delta_field_pins_stencil_then_physics(k):
+    """One step from a delta field with a uniform trip count k >= 1 (Fig. 2: the Jacobi
+    kernel, then the physics kernel on its output).  Stencil first sends the delta's
+    mass a to seven cells (cc*a at the centre, cn*a at the six neighbours, zero
+    elsewhere since Phi(0) = 0), and the physics then maps each of those values v to
+    Phi^k(v).  Physics first would give cc*Phi^k(a) and cn*Phi^k(a) instead, which
+    differ for every a outside {-1, 0, 1}.  The expected values come from a scalar
+    loop over Python floats (IEEE doubles), evaluated in the paper's order."""
+    nx, ny, nz = 9, 8, 7
+    a = 0.5
+    wl = tiny(nx, ny, nz, kmin=k, kmax=k, steps=1)
+    q0 = np.zeros((1, ny, nx, nz))
+    cx, cy, cz = 4, 3, 3
+    q0[0, cy, cx, cz] = a
+
+    def phi_k(v):
+        for _ in range(k):
+            v = v + 0.01 * (v - (v * v) * v)
+        return v
+
+    want = np.zeros_like(q0)
+    want[0, cy, cx, cz] = phi_k(0.4 * a)
+    for dy, dx, dz in ((0, -1, 0), (0, 1, 0), (-1, 0, 0), (1, 0, 0), (0, 0, -1), (0, 0, 1)):
+        want[0, cy + dy, cx + dx, cz + dz] = phi_k(0.1 * a)
+    q, _, _, _ = oracle.run(wl, q0=q0)
+    np.testing.assert_array_equal(q, want)
+    assert want[0, cy, cx, cz] != 0.4 * phi_k(a)          # the two orders really differ
+
+
+def test_delta_field_on_the_mirror_boundary():
+    """A delta on the bottom level: the mirror ghost adds the cell's own value to its
+    neighbour sum, so the centre gets (cc + cn)*a before the physics."""
+    nx, ny, nz, k = 6, 5, 4, 3
+    wl = tiny(nx, ny, nz, kmin=k, kmax=k, steps=1)
+    q0 = np.zeros((1, ny, nx, nz))
+    q0[0, 2, 3, 0] = 0.75
+
+    def phi_k(v):
+        for _ in range(k):
+            v = v + 0.01 * (v - (v * v) * v)
+        return v
+
+    q, _, _, _ = oracle.run(wl, q0=q0)
+    assert q[0, 2, 3, 0] == phi_k(0.4 * 0.75 + 0.1 * 0.75)
+    assert q[0, 2, 3, 1] == phi_k(0.1 * 0.75)
+    assert np.count_nonzero(q) == 6                       # centre, 4 in-plane, 1 above
+
+
+def _global_slice(full, ox, oy, nxw, nyw):
+    ny, nx = full.shape[-3], full.shape[-2]
+    ys = (oy + np.arange(nyw)) % ny
+    xs = (ox + np.arange(nxw)) % nx
+    return full[..., ys, :, :][..., :, xs, :]
+
+
+@pytest.mark.parametrize("ox,oy", [(-5, -4), (7, 2), (15, 13), (0, 0)])
+def test_init_window_is_a_slice_of_the_field(ox, oy):
+    """The windowed initial field equals the matching slice of the whole seeded field
+    (local column (x, y) = global ((ox + x) mod nx, (oy + y) mod ny)), for a window that
+    wraps the periodic corner and for interior windows, in every field."""
+    wl = tiny(20, 16, 5, steps=1).replace(nfields=2)
+    full = oracle.init_field(wl.nx, wl.ny, wl.nz, wl.seed, nfields=2)
+    for f in range(2):
+        win = oracle.init_window(wl, ox, oy, 11, 9, f=f)
+        np.testing.assert_array_equal(win, _global_slice(full[f], ox, oy, 11, 9))
+
+
+@pytest.mark.parametrize("ox,oy,hot", [
+    (-5, -4, ((3, 17, 1, -1),)),                 # wraps the corner; moving hotspot
+    (9, 6, ((14, 10, 2, 1), (2, 3, 0, 0))),      # interior; two hotspots
+    (18, 12, ((20, 15, -1, 2),)),                # wraps both edges
+])
+def test_window_runner_matches_the_whole_grid(ox, oy, hot):
+    """After T steps the windowed runner holds the whole-grid run's values bit for bit in
+    every column at least T columns away from its border: the window is advanced as if
+    it were periodic, the cost field is evaluated at global coordinates and time, and
+    the 7-point update reaches one column further per step."""
+    T = 3
+    wl = tiny(24, 20, 6, kmin=1, kmax=20, hot=hot, sigma=3.0, steps=T)
+    full, _, _, _ = oracle.run(wl)
+    nxw, nyw = 14, 12
+    q0 = oracle.init_window(wl, ox, oy, nxw, nyw)
+    win = oracle.run_window(wl, q0, ox, oy, T)
+    got = win[T:nyw - T, T:nxw - T]
+    want = _global_slice(full[0], ox + T, oy + T, nxw - 2 * T, nyw - 2 * T)
+    np.testing.assert_array_equal(got, want)
+    # the border columns are not exact (the window's own wrap), so the interior test bites
+    assert not np.array_equal(win, _global_slice(full[0], ox, oy, nxw, nyw))
+
+
+def test_window_runner_honours_t0():
+    """A window advanced from time t0 (a moving hotspot) equals the whole grid advanced
+    t0 steps and then T more, in its interior."""
+    t0, T = 4, 2
+    wl = tiny(16, 14, 4, kmin=1, kmax=15, hot=((2, 12, 3, -2),), sigma=2.5, steps=t0 + T)
+    full, _, _, _ = oracle.run(wl)
+    mid, _, _, _ = oracle.run(wl, nsteps=t0)
+    ox, oy, nxw, nyw = -3, 9, 10, 9
+    q0 = _global_slice(mid[0], ox, oy, nxw, nyw)
+    win = oracle.run_window(wl, q0, ox, oy, T, t0=wl.t0 + t0)
+    np.testing.assert_array_equal(win[T:nyw - T, T:nxw - T],
+                                  _global_slice(full[0], ox + T, oy + T, nxw - 2 * T, nyw - 2 * T))
