@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 1
+#define LB_ABI_VERSION 2
 #define LB_MAX_HOT 4
 #define LB_NBUF 3
 
@@ -139,6 +139,11 @@ typedef struct {
                                 alpha_work); -1 = alpha_work (default). A
                                 small value sizes items by their physics,
                                 which one workgroup runs serially            */
+    int32_t march;           /* > 0: the column-march pipeline with this many
+                                rows in flight (2, 4 or 8; nz % 4 == 0, every
+                                field below 4 GiB, (tile_x + 2) * nz / 4
+                                threads per workgroup, at most 512 in FP64);
+                                overrides stage_rows.  0 = off (default)      */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;
@@ -189,10 +194,16 @@ int lb_query(const lb_config *cfg, lb_buffers *sizes_out);
 int lb_grid_init(const lb_config *cfg, const lb_buffers *bufs, void *hip_stream,
                  const void *init_field, lb_ctx **out);
 
-/* Enqueue nsteps >= 0 time steps in the given mode (LB_PLAIN, LB_PERSISTENT,
- * LB_PLAIN_GRAPH, LB_PERSISTENT_EAGER); asynchronous.  Every mode gives
- * bit-identical fields and loads.  Loads of every step are added to the
- * current measurement window (Section V: the measured time steps). */
+/* The time-step loop of Fig. 2.  Enqueue nsteps >= 0 time steps in the given
+ * mode (LB_PLAIN, LB_PERSISTENT, LB_PLAIN_GRAPH, LB_PERSISTENT_EAGER);
+ * asynchronous.  Every mode gives bit-identical fields and loads.  Loads of
+ * every step are added to the current measurement window (Section V: the
+ * measured time steps).  Errors: LB_E_INVAL (nsteps < 0, unknown mode),
+ * LB_E_HIP (a capture or launch failed).  After LB_E_HIP the steps whose
+ * launches were all enqueued count as done (lb_stats); if a plain step had
+ * some of its per-chunk launches enqueued, the context is left unusable and
+ * every later call but lb_stats, lb_destroy and lb_last_error returns
+ * LB_E_STATE. */
 int lb_step(lb_ctx *ctx, int32_t nsteps, int32_t mode);
 
 /* The load measurement of Section V: the runtime's per-VP load database,

@@ -225,6 +225,7 @@ constexpr int kPipeDma = 1;   // pipeline template value of the direct global->L
 // spilled at that bound), so they are limited to 512 threads (up to 256 VGPRs).
 template <typename T>
 constexpr int max_block(int pipe) {
+    if (pipe >= 100) return sizeof(T) == 8 ? kMaxBlockDeep : kMaxBlock;   // column march
     return pipe != kPipeDma && (pipe >= 4 || sizeof(T) == 8) ? kMaxBlockDeep : kMaxBlock;
 }
 struct ItemOut {
@@ -491,6 +492,195 @@ __device__ ItemOut process_item(const DevArgs& a, const ItemDesc& d, const ItemD
             __syncthreads();            // the ring rows of this item are free again
         }
     }
+    block_sum2(chk, work, red, BS);
+    ItemOut o;
+    o.checksum = chk;
+    o.work = work;
+    o.chunk = d.chunk;
+    return o;
+}
+
+// ---- one work item, column-march pipeline -----------------------------------------
+// Template tag of the march pipeline with D rows in flight: kPipeMarch + D.
+constexpr int kPipeMarch = 100;
+
+// Raw buffer access to one field: 32-bit byte offsets from the field's base,
+// range-checked by the hardware against the field's size.  A lane that must
+// not touch memory passes kOutOfRange: its load returns zeros and its store is
+// dropped, with no memory traffic, so every lane can issue every load and store
+// and the compiler counts outstanding memory operations exactly (no divergent
+// branch around them).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr uint32_t kOutOfRange = 0xFFFFFFE0u;
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9 buffer format word: 32-bit data, no swizzle
+
+__device__ __forceinline__ rsrc_t field_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kRsrcWord3);
+}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> bload(rsrc_t r, uint32_t off) {
+    constexpr int B = static_cast<int>(sizeof(T)) * V;
+    Vec<T, V> x;
+    if constexpr (B == 32) {
+        const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0);
+        const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off + 16u), 0, 0);
+        __builtin_memcpy(&x, &lo, 16);
+        __builtin_memcpy(reinterpret_cast<char*>(&x) + 16, &hi, 16);
+    } else if constexpr (B == 16) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0);
+        __builtin_memcpy(&x, &v, 16);
+    } else if constexpr (B == 8) {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0);
+        __builtin_memcpy(&x, &v, 8);
+    } else {
+        static_assert(B == 4, "element group of 4, 8, 16 or 32 bytes");
+        const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0);
+        __builtin_memcpy(&x, &v, 4);
+    }
+    return x;
+}
+template <typename T, int V>
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, const Vec<T, V>& x) {
+    constexpr int B = static_cast<int>(sizeof(T)) * V;
+    if constexpr (B == 32) {
+        u32x4 lo, hi;
+        __builtin_memcpy(&lo, &x, 16);
+        __builtin_memcpy(&hi, reinterpret_cast<const char*>(&x) + 16, 16);
+        __builtin_amdgcn_raw_buffer_store_b128(lo, r, static_cast<int>(off), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(hi, r, static_cast<int>(off + 16u), 0, 0);
+    } else if constexpr (B == 16) {
+        u32x4 v;
+        __builtin_memcpy(&v, &x, 16);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, static_cast<int>(off), 0, 0);
+    } else if constexpr (B == 8) {
+        u32x2 v;
+        __builtin_memcpy(&v, &x, 8);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, static_cast<int>(off), 0, 0);
+    } else {
+        unsigned v;
+        __builtin_memcpy(&v, &x, 4);
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, static_cast<int>(off), 0, 0);
+    }
+}
+
+// One item with the column-march pipeline.  The workgroup has (TX+2)*NQ
+// threads: thread column tcol (0..TX+1) streams grid column x0 - 1 + tcol of
+// the item's rows -1 .. h (the item's own w columns and one halo column on
+// either side), V levels per thread, and threads 1..w of each row compute.
+// Each thread keeps rows y-1, y, y+1 of its column in registers and D more
+// rows in flight; only the current row goes through LDS (double-buffered, one
+// barrier per row), for the x neighbours and the z neighbours across lanes.
+// Every cell is read once per item and written once; the halo columns and the
+// two halo rows are re-read by the neighbouring items.
+template <typename T, int V, int KAHAN, int D, typename Hook>
+__device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const T* __restrict__ src,
+                                      T* __restrict__ dst, const int* hcx, const int* hcy, T* lds,
+                                      double* red, Hook hook) {
+    const int nz = a.nz, nx = a.nx, ny = a.ny;
+    const int NQ = nz / V;
+    const int TX = a.tile_x;
+    const int BS = a.block;                   // (TX + 2) * NQ == blockDim.x
+    const int tcol = threadIdx.x / NQ;
+    const int tzq = threadIdx.x - tcol * NQ;
+    const int zoff = tzq * V;
+    const int x0 = d.x0, y0 = d.y0;
+    const int w = d.wh & 0xffff;
+    const int h = d.wh >> 16;
+    const bool streams = tcol < w + 2;        // this thread loads grid column x0 - 1 + tcol
+    const bool active = tcol >= 1 && tcol <= w;
+    int gx = x0 - 1 + tcol;
+    gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+    const uint32_t rowbytes = static_cast<uint32_t>(nx) * static_cast<uint32_t>(nz) * sizeof(T);
+    const uint32_t colbytes = (static_cast<uint32_t>(gx) * nz + zoff) * sizeof(T);
+    const T cc = static_cast<T>(a.cc), cn = static_cast<T>(a.cn), eps = static_cast<T>(a.eps);
+    const int RL = (TX + 2) * nz;             // LDS row (elements)
+    int* kbuf = reinterpret_cast<int*>(lds + 2 * RL);
+    // byte offset of row i (-1 .. h) of this thread's column; out of range for
+    // threads without a column and for rows past the item's last halo row
+    auto row_off = [&](int i) -> uint32_t {
+        int gy = y0 + i;
+        gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        return (streams && i <= h) ? colbytes + static_cast<uint32_t>(gy) * rowbytes : kOutOfRange;
+    };
+    for (int i = threadIdx.x; i < w * h; i += BS) {
+        const int r = i / w, cx = i - r * w;
+        kbuf[r * TX + cx] = column_k(a, hcx, hcy, x0 + cx, y0 + r);
+    }
+    double chk = 0.0;
+    int ksum = 0, krows = 0;                  // trip counts and rows of this thread's column (field 0)
+    for (int f = 0; f < a.nfields; ++f) {
+        const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+        const rsrc_t out = field_rsrc(dst + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+        Vec<T, V> ym = bload<T, V>(in, row_off(-1));
+        Vec<T, V> c = bload<T, V>(in, row_off(0));
+        Vec<T, V> R[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) R[j] = bload<T, V>(in, row_off(1 + j));
+        // row r: publish row r in LDS buffer r & 1, take row r + 1 from the ring
+        // and refill its slot with row r + 1 + D, compute row r, store it
+        for (int r0 = 0; r0 < h; r0 += D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int r = r0 + j;
+                if (r < h) {
+                    T* L = lds + (r & 1) * RL;
+                    if (streams) st<T, V>(L + tcol * nz + zoff, c);
+                    __syncthreads();
+                    if (f == 0 && r == 0) hook();
+                    const Vec<T, V> yp = R[j];
+                    R[j] = bload<T, V>(in, row_off(r + 1 + D));
+                    Vec<T, V> o;
+                    uint32_t so = kOutOfRange;
+                    if (active) {
+                        const T* Lc = L + tcol * nz + zoff;
+                        const Vec<T, V> xm = ld<T, V>(Lc - nz);
+                        const Vec<T, V> xp = ld<T, V>(Lc + nz);
+                        const T below = Lc[-1];   // the column's level zoff - 1 when tzq > 0
+                        const T above = Lc[V];    // ... zoff + V when tzq < NQ - 1
+                        const T zlo = (tzq == 0) ? c.v[0] : below;
+                        const T zhi = (tzq == NQ - 1) ? c.v[V - 1] : above;
+                        const int k = kbuf[r * TX + tcol - 1];
+                        T q[V];
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            const T zm = (v == 0) ? zlo : c.v[v - 1];
+                            const T zp = (v == V - 1) ? zhi : c.v[v + 1];
+                            T sum = xm.v[v] + xp.v[v];
+                            sum = sum + ym.v[v];
+                            sum = sum + yp.v[v];
+                            sum = sum + zm;
+                            sum = sum + zp;
+                            q[v] = combine(cc, cn, c.v[v], sum);
+                        }
+                        if (a.vertical)
+                            physics_vertical<T, V>(eps, k, tzq, NQ, q);
+                        else
+                            physics_vec<KAHAN, T, V>(eps, k, q);
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            o.v[v] = q[v];
+                            chk += static_cast<double>(q[v]);
+                        }
+                        if (f == 0 && tzq == 0) {
+                            ksum += k;
+                            ++krows;
+                        }
+                        int gy = y0 + r;
+                        gy = gy >= ny ? gy - ny : gy;
+                        so = colbytes + static_cast<uint32_t>(gy) * rowbytes;
+                    }
+                    bstore<T, V>(out, so, o);
+                    ym = c;
+                    c = yp;
+                }
+            }
+        }
+    }
+    double work = static_cast<double>(nz) * static_cast<double>(a.nfields) *
+                  (static_cast<double>(a.alpha) * static_cast<double>(krows) + static_cast<double>(ksum));
     block_sum2(chk, work, red, BS);
     ItemOut o;
     o.checksum = chk;
@@ -784,6 +974,120 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_persistent(DevArgs a) {
     }
 }
 
+// Wave-uniform copies (scalar registers) of values every lane holds the same.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ ItemDesc uni(const ItemDesc& d) {
+    ItemDesc u;
+    u.x0 = uni(d.x0);
+    u.y0 = uni(d.y0);
+    u.wh = uni(d.wh);
+    u.chunk = uni(d.chunk);
+    u.id = uni(d.id);
+    u.vbase = uni(d.vbase);
+    u.tile = uni(d.tile);
+    u.pad1 = 0;
+    return u;
+}
+
+// The persistent launch with the column-march item body.  Same queues, static
+// start, claims and stealing as k_persistent, arranged so that little state
+// lives in vector registers across an item: the step's hotspot centres and the
+// item's descriptor are wave-uniform (scalar registers), the next step's state
+// is written before the first item, and a claim ahead keeps only its index
+// during the item (thread 0 loads that item's descriptor at the item's end).
+template <typename T, int V, int KAHAN, int D>
+__global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_march(DevArgs a) {
+    extern __shared__ __align__(32) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    __shared__ double red[kRedLen];
+    __shared__ ItemDesc s_cur, s_nxt;
+
+    const uint64_t t_launch = wall_clock64();
+    const int wg = blockIdx.x;
+    const WgState ws = a.wstate[wg];            // equal in every workgroup of the launch
+    const uint64_t step = ws.step;
+    const int par = uni(static_cast<int>(step & 1));
+    StepInfo si;
+    si.step = step;
+#pragma unroll
+    for (int h = 0; h < kMaxHot; ++h) {
+        si.hcx[h] = uni(ws.hx[h]);
+        si.hcy[h] = uni(ws.hy[h]);
+    }
+    const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(par ? a.field0 : a.field1);
+    int* heads = a.heads + par * a.nqueues;
+    double* partials = a.partials + static_cast<int64_t>(par) * a.part_stride;
+    const int home = uni(home_queue(a, wg));
+    const int hbeg = uni(a.seg[home]);
+    const int hn = uni(a.seg[home + 1]) - hbeg;
+
+    if (threadIdx.x == 0) {
+        s_cur = a.firstd[2 * wg];
+        s_nxt = a.firstd[2 * wg + 1];
+    }
+    if (wg == 0) {
+        int* other = a.heads + (par ^ 1) * a.nqueues;
+        for (int q = threadIdx.x; q < a.nqueues; q += a.block) other[q] = a.head0;
+        if (threadIdx.x == 0) {
+            a.ctrl->pend_n[par] = a.ctrl->nitems;
+            a.ctrl->pend_step[par] = step + 1;
+        }
+    }
+    if (wg == a.nwg - 1) settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
+    __syncthreads();                             // every thread has read its step state
+    if (threadIdx.x == 0) a.wstate[wg] = next_state(a, ws);
+    double busy = 0.0;
+    uint64_t t_first = 0, t_last = 0;
+    bool drained = false;    // (thread 0) the home queue has nothing left to claim
+    for (;;) {
+        ItemDesc d = uni(s_cur);
+        if (d.id < 0) {                      // nothing claimed ahead: claim with stealing
+            __syncthreads();
+            if (threadIdx.x < kWave) {
+                const int qi = claim(a, heads, home);
+                if (threadIdx.x == 0) {
+                    s_cur = qi >= 0 ? a.queue[qi] : no_item();
+                    s_nxt = no_item();
+                }
+            }
+            __syncthreads();
+            d = uni(s_cur);
+            drained = true;
+            if (d.id < 0) break;
+        }
+        __syncthreads();                     // every thread holds d before s_cur changes
+        int nidx = hn;
+        if (threadIdx.x == 0 && !drained) nidx = atomicAdd(&heads[home], 1);
+        const uint64_t t_start = wall_clock64();
+        if (t_first == 0) t_first = t_start;
+        const ItemOut o = process_item_march<T, V, KAHAN, D>(a, d, src, dst, si.hcx, si.hcy, lds, red,
+                                                             NoHook{});
+        t_last = wall_clock64();
+        const double ticks = static_cast<double>(t_last - t_start);  // used by thread 0
+        record_item(a, partials, d, o, ticks);
+        if (threadIdx.x == 0) {
+            busy += ticks;
+            s_cur = s_nxt;
+            ItemDesc na = no_item();
+            if (!drained) {
+                if (nidx < hn) na = a.queue[hbeg + nidx];
+                drained = nidx + 1 >= hn;
+            }
+            s_nxt = na;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        unsafeAtomicAdd(&a.wg_busy[wg], busy);
+        uint64_t* tl = a.wg_timeline + 4 * static_cast<size_t>(wg);
+        tl[0] = t_launch;
+        tl[1] = t_first ? t_first : t_launch;
+        tl[2] = t_last ? t_last : t_launch;
+        tl[3] = wall_clock64();
+    }
+}
+
 template <typename T, int V, int KAHAN, int PIPE>
 __global__ __launch_bounds__(max_block<T>(PIPE)) void k_plain(DevArgs a, int chunk) {
     extern __shared__ __align__(32) unsigned char smem[];
@@ -802,8 +1106,13 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_plain(DevArgs a, int chu
     const uint64_t t_start = wall_clock64();
     const Carry none{0, 0, 0};
     Carry unused;
-    const ItemOut o = process_item<T, V, KAHAN, PIPE>(a, d, no_item(), none, unused, src, dst, si.hcx,
-                                                      si.hcy, lds, red, NoHook{});
+    ItemOut o;
+    if constexpr (PIPE >= kPipeMarch)
+        o = process_item_march<T, V, KAHAN, PIPE - kPipeMarch>(a, d, src, dst, si.hcx, si.hcy, lds, red,
+                                                             NoHook{});
+    else
+        o = process_item<T, V, KAHAN, PIPE>(a, d, no_item(), none, unused, src, dst, si.hcx, si.hcy, lds,
+                                            red, NoHook{});
     record_item(a, a.partials + static_cast<int64_t>(par) * a.part_stride, d, o,
                 static_cast<double>(wall_clock64() - t_start));
 }
@@ -953,6 +1262,9 @@ template <typename T, int KAHAN>
 PersistentFn persistent_for(int vec, int pipe) {
     if (vec == 4) {
         switch (pipe) {
+            case kPipeMarch + 2: return k_persistent_march<T, 4, KAHAN, 2>;
+            case kPipeMarch + 4: return k_persistent_march<T, 4, KAHAN, 4>;
+            case kPipeMarch + 8: return k_persistent_march<T, 4, KAHAN, 8>;
             case kPipeDma: return k_persistent<T, 4, KAHAN, kPipeDma>;
             case 8: return k_persistent<T, 4, KAHAN, sizeof(T) == 4 ? 8 : 4>;
             case 4: return k_persistent<T, 4, KAHAN, 4>;
@@ -965,6 +1277,9 @@ template <typename T, int KAHAN>
 PlainFn plain_for(int vec, int pipe) {
     if (vec == 4) {
         switch (pipe) {
+            case kPipeMarch + 2: return k_plain<T, 4, KAHAN, kPipeMarch + 2>;
+            case kPipeMarch + 4: return k_plain<T, 4, KAHAN, kPipeMarch + 4>;
+            case kPipeMarch + 8: return k_plain<T, 4, KAHAN, kPipeMarch + 8>;
             case kPipeDma: return k_plain<T, 4, KAHAN, kPipeDma>;
             case 8: return k_plain<T, 4, KAHAN, sizeof(T) == 4 ? 8 : 4>;
             case 4: return k_plain<T, 4, KAHAN, 4>;
@@ -986,7 +1301,10 @@ PlainFn pick_plain(int prec, int vec, int pipe) {
 }
 
 // the pipeline a launch uses
-int pipe_of(const DevArgs& a) { return a.stage_rows > 0 ? kPipeDma : a.reg_depth; }
+int pipe_of(const DevArgs& a) {
+    if (a.march > 0) return kPipeMarch + a.march;
+    return a.stage_rows > 0 ? kPipeDma : a.reg_depth;
+}
 
 }  // namespace
 

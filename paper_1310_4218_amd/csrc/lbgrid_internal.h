@@ -84,6 +84,8 @@ struct DevArgs {
     int32_t block;             // threads per workgroup = TX * nz / V (== blockDim.x)
     int32_t stage_rows;        // > 0: rows per direct global->LDS batch (V = 4 only); 0: registers
     int32_t reg_depth;         // register pipeline: rows in flight (2, 4 or 8; 2 unless V = 4)
+    int32_t march;             // > 0: column-march pipeline with this many rows in flight (2, 4, 8)
+    uint32_t field_bytes;      // bytes of one field (< 4 GiB with the march pipeline)
     int32_t vertical;          // 1: column physics with the vertical dependency
     int32_t r2cut;
     int32_t kmin;

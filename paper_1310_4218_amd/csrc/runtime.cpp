@@ -44,6 +44,7 @@ struct Plan {
     int32_t RD = 2;         // register pipeline depth (rows in flight)
     int32_t prec = 0, vec = 1, elem = 4, TX = 16, TY = 16, block = 0, ntiles = 0;
     int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
+    int32_t M = 0;          // rows in flight of the column march; 0 = another pipeline
     int32_t B = 0;          // rows per direct global->LDS batch; 0 = register pipeline
     int32_t ring = 4;       // LDS ring rows
     int32_t r2cut = 0;
@@ -152,6 +153,8 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         (c->stage_rows < -2 && c->stage_rows != -4 && c->stage_rows != -8))
         return bad("stage_rows must be -8, -4, -2, -1 (register pipeline) or in [0, 32]");
     if (c->physics != LB_PHYS_POINTWISE && c->physics != LB_PHYS_VERTICAL) return bad("physics");
+    if (c->march != 0 && c->march != 2 && c->march != 4 && c->march != 8)
+        return bad("march must be 0 (off), 2, 4 or 8 rows in flight");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
     p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
@@ -173,13 +176,20 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->physics == LB_PHYS_VERTICAL && (NQ > 64 || 64 % NQ != 0))
         return fail(err, LB_E_UNSUPPORTED,
                     "vertical physics needs nz / V to divide 64 (V = 4, 2 or 1 by divisibility of nz)");
-    // pipeline: direct global->LDS batches of B rows (V = 4 only) or the register path
-    if (c->stage_rows > 0 && p.vec != 4) return bad("stage_rows > 0 needs nz divisible by 4");
-    if (c->stage_rows < -2 && p.vec != 4) return bad("register pipeline depth 4 or 8 needs nz divisible by 4");
-    if (c->stage_rows == -8 && p.prec == LB_FP64) return bad("register pipeline depth 8 is FP32 only");
-    p.B = c->stage_rows > 0 ? c->stage_rows : (c->stage_rows == 0 && p.vec == 4 ? 4 : 0);
+    // pipeline: the column march (M rows in flight), direct global->LDS batches of B
+    // rows (V = 4 only) or the register path
+    p.M = c->march;
+    if (p.M > 0) {
+        if (p.vec != 4) return bad("march needs nz divisible by 4");
+        if (static_cast<uint64_t>(p.ncells) * p.elem > 0xFFFFFFE0ull)
+            return bad("march needs every field below 4 GiB (32-bit buffer offsets)");
+    }
+    if (p.M == 0 && c->stage_rows > 0 && p.vec != 4) return bad("stage_rows > 0 needs nz divisible by 4");
+    if (p.M == 0 && c->stage_rows < -2 && p.vec != 4) return bad("register pipeline depth 4 or 8 needs nz divisible by 4");
+    if (p.M == 0 && c->stage_rows == -8 && p.prec == LB_FP64) return bad("register pipeline depth 8 is FP32 only");
+    p.B = p.M > 0 ? 0 : c->stage_rows > 0 ? c->stage_rows : (c->stage_rows == 0 && p.vec == 4 ? 4 : 0);
     p.RD = c->stage_rows < -2 ? -c->stage_rows : 2;
-    p.ring = p.B > 0 ? 2 * p.B + 2 : kRingRows;
+    p.ring = p.M > 0 ? 2 : p.B > 0 ? 2 * p.B + 2 : kRingRows;
     p.TY = c->tile_y > 0 ? c->tile_y : 16;
     const size_t col_bytes = static_cast<size_t>(p.nz) * p.elem;
     auto lds_for = [&](int tx) {  // LDS: the row ring, then trip counts of one tile (two for
@@ -187,19 +197,24 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         return static_cast<size_t>(p.ring) * (tx + 2) * col_bytes +
                sizeof(int32_t) * static_cast<size_t>(tx) * p.TY * (p.B > 0 ? 2 : 1);
     };
+    // threads per workgroup: TX columns (the march adds the two halo columns) of NQ threads
+    auto threads_for = [&](int tx) { return (p.M > 0 ? tx + 2 : tx) * NQ; };
+    const int most = p.M > 0 ? (p.prec == LB_FP64 ? kMaxBlockDeep : kMaxBlock)
+                             : (p.B == 0 && (p.RD >= 4 || p.prec == LB_FP64)) ? kMaxBlockDeep : kMaxBlock;
     if (c->tile_x > 0) {
         p.TX = c->tile_x;
     } else {
-        p.TX = 16;
-        const int most = (p.B == 0 && (p.RD >= 4 || p.prec == LB_FP64)) ? kMaxBlockDeep : kMaxBlock;
-        while (p.TX > 1 && (p.TX * NQ > most || lds_for(p.TX) > 64 * 1024)) --p.TX;
+        p.TX = p.M > 0 ? 32 : 16;
+        while (p.TX > 1 && (threads_for(p.TX) > most || lds_for(p.TX) > 64 * 1024)) --p.TX;
     }
     if (p.TX > 1024 || p.TY > 256) return bad("tile sizes must be at most 1024 x 256");
-    p.block = p.TX * NQ;
+    p.block = threads_for(p.TX);
     if (p.block > kMaxBlock) return bad("tile_x * nz / vector width exceeds 1024 threads");
-    if (p.B == 0 && p.RD >= 4 && p.block > kMaxBlockDeep)
+    if (p.M > 0 && p.block > most)
+        return bad("the FP64 march needs (tile_x + 2) * nz / 4 <= 512 threads");
+    if (p.M == 0 && p.B == 0 && p.RD >= 4 && p.block > kMaxBlockDeep)
         return bad("register pipeline depth 4 or 8 needs tile_x * nz / 4 <= 512 threads");
-    if (p.B == 0 && p.prec == LB_FP64 && p.block > kMaxBlockDeep)
+    if (p.M == 0 && p.B == 0 && p.prec == LB_FP64 && p.block > kMaxBlockDeep)
         return bad("FP64 with the register pipeline needs tile_x * nz / V <= 512 threads");
     p.lds = lds_for(p.TX);
     if (p.lds > kMaxLds) return bad("tile too large: the LDS row ring and trip counts exceed 160 KiB");
@@ -293,6 +308,7 @@ struct lb_ctx {
     int64_t tile_steps = 0;           // steps in that window
     int64_t rebalances = 0;           // lb_rebalance calls that installed a map
     bool have_measured = false;
+    bool broken = false;              // a step failed part-way: device state no longer matches `steps`
     int64_t steps = 0;
     int64_t window_steps = 0;
     double clock_hz = 100e6;
@@ -330,6 +346,13 @@ const char* fail_site() { return std::getenv("LBGRID_FAIL_AT"); }
 bool forced_failure(const char* site) {
     const char* f = fail_site();
     return f && std::strcmp(f, site) == 0;
+}
+// LBGRID_FAIL_AT=launch:N: the N-th kernel or graph launch of each lb_step call
+// fails (N >= 1) as if the runtime had refused it; 0 when not set.
+int forced_launch_failure() {
+    const char* f = fail_site();
+    if (!f || std::strncmp(f, "launch:", 7) != 0) return 0;
+    return std::atoi(f + 7);
 }
 
 void build_tiles(lb_ctx* x) {
@@ -648,6 +671,7 @@ void lb_config_default(lb_config* c) {
     c->physics = LB_PHYS_POINTWISE;
     c->tail_split = 4;
     c->item_alpha = -1;
+    c->march = 0;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
@@ -762,6 +786,8 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.block = P.block;
     a.stage_rows = P.B;
     a.reg_depth = P.RD;
+    a.march = P.M;
+    a.field_bytes = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(P.ncells) * P.elem, 0xFFFFFFFFull));
     a.vertical = cfg->physics == LB_PHYS_VERTICAL ? 1 : 0;
     if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
         int ncu = 0;
@@ -823,25 +849,56 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
 
 int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
     if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, LB_E_STATE, "context unusable: an earlier step failed part-way");
     if (nsteps < 0) return fail(&x->err, LB_E_INVAL, "nsteps must be >= 0");
     if (mode < LB_PLAIN || mode > LB_PERSISTENT_EAGER) return fail(&x->err, LB_E_INVAL, "unknown mode");
     if (forced_failure("step")) return fail(&x->err, LB_E_HIP, "forced failure at step (LBGRID_FAIL_AT)");
     HIP_TRY(x, hipSetDevice(x->device));
     const Plan& p = x->plan;
     if (nsteps == 0) return LB_OK;
+    // Every step is counted as soon as all of its launches are enqueued, so that
+    // on a failure `steps` still names the buffer and checksum slot the device
+    // state is in.  A step that fails after some of its launches (the plain
+    // form's per-chunk launches) leaves a partly applied step behind: the
+    // context is then marked unusable.
+    const int fail_at = forced_launch_failure();
+    int launches = 0;
+    auto forced = [&]() { return fail_at > 0 && ++launches == fail_at; };
+    auto done = [&](int n) {
+        x->steps += n;
+        x->window_steps += n;
+    };
+    auto launch_failed = [&](const char* what, int e, bool partial) {
+        if (partial) x->broken = true;
+        return fail(&x->err, LB_E_HIP, std::string(what) + ": " +
+                                           (e ? hipGetErrorString(static_cast<hipError_t>(e))
+                                              : "forced launch failure (LBGRID_FAIL_AT)"));
+    };
     int rc;
     switch (mode) {
         case LB_PERSISTENT: {
             const int R = x->cfg.graph_steps;
             if (nsteps >= R && !x->g_pers && (rc = capture(x, LB_PERSISTENT, R, &x->g_pers)) != LB_OK) return rc;
             if (nsteps % R && !x->g_pers1 && (rc = capture(x, LB_PERSISTENT, 1, &x->g_pers1)) != LB_OK) return rc;
-            for (int i = 0; i < nsteps / R; ++i) HIP_TRY(x, hipGraphLaunch(x->g_pers, x->stream));
-            for (int i = 0; i < nsteps % R; ++i) HIP_TRY(x, hipGraphLaunch(x->g_pers1, x->stream));
+            for (int i = 0; i < nsteps / R; ++i) {
+                if (forced()) return launch_failed("hipGraphLaunch", 0, false);
+                if (int e = hipGraphLaunch(x->g_pers, x->stream)) return launch_failed("hipGraphLaunch", e, false);
+                done(R);
+            }
+            for (int i = 0; i < nsteps % R; ++i) {
+                if (forced()) return launch_failed("hipGraphLaunch", 0, false);
+                if (int e = hipGraphLaunch(x->g_pers1, x->stream)) return launch_failed("hipGraphLaunch", e, false);
+                done(1);
+            }
             break;
         }
         case LB_PERSISTENT_EAGER:
-            for (int i = 0; i < nsteps; ++i)
-                LAUNCH_TRY(x, launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, x->stream));
+            for (int i = 0; i < nsteps; ++i) {
+                if (forced()) return launch_failed("launch_persistent", 0, false);
+                if (int e = launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, x->stream))
+                    return launch_failed("launch_persistent", e, false);
+                done(1);
+            }
             break;
         case LB_PLAIN_GRAPH:
             if (x->g_plain && x->plain_graph_version != x->plan_version) {  // grid sizes changed
@@ -852,24 +909,32 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
                 if ((rc = capture(x, LB_PLAIN, 1, &x->g_plain)) != LB_OK) return rc;
                 x->plain_graph_version = x->plan_version;
             }
-            for (int i = 0; i < nsteps; ++i) HIP_TRY(x, hipGraphLaunch(x->g_plain, x->stream));
-            break;
-        default:  // LB_PLAIN
             for (int i = 0; i < nsteps; ++i) {
-                for (int32_t c = 0; c < p.C; ++c)
-                    LAUNCH_TRY(x, launch_plain_chunk(x->args, p.prec, p.vec, c,
-                                                     x->item_off[c + 1] - x->item_off[c], p.block, p.lds,
-                                                     x->stream));
-                LAUNCH_TRY(x, launch_finish(x->args, x->stream));
+                if (forced()) return launch_failed("hipGraphLaunch", 0, false);
+                if (int e = hipGraphLaunch(x->g_plain, x->stream)) return launch_failed("hipGraphLaunch", e, false);
+                done(1);
+            }
+            break;
+        default:  // LB_PLAIN: C launches and a finisher per step
+            for (int i = 0; i < nsteps; ++i) {
+                for (int32_t c = 0; c <= p.C; ++c) {
+                    const bool partial = c > 0;   // some of this step's launches are already enqueued
+                    if (forced()) return launch_failed(c < p.C ? "launch_plain_chunk" : "launch_finish", 0, partial);
+                    const int e = c < p.C ? launch_plain_chunk(x->args, p.prec, p.vec, c,
+                                                               x->item_off[c + 1] - x->item_off[c], p.block,
+                                                               p.lds, x->stream)
+                                          : launch_finish(x->args, x->stream);
+                    if (e) return launch_failed(c < p.C ? "launch_plain_chunk" : "launch_finish", e, partial);
+                }
+                done(1);
             }
     }
-    x->steps += nsteps;
-    x->window_steps += nsteps;
     return LB_OK;
 }
 
 int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
     if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, LB_E_STATE, "context unusable: an earlier step failed part-way");
     if (source != LB_LOAD_WORK && source != LB_LOAD_TIME) return fail(&x->err, LB_E_INVAL, "unknown load source");
     const Plan& p = x->plan;
     HIP_TRY(x, hipSetDevice(x->device));
@@ -928,6 +993,7 @@ int lb_balance_host(const double* loads, const int32_t* old_map, int32_t C, int3
 int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* loads,
                  int32_t* map_out, int32_t* nmigrated, double* lam) {
     if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, LB_E_STATE, "context unusable: an earlier step failed part-way");
     const Plan& p = x->plan;
     const double* w = loads;
     if (!w) {
@@ -962,6 +1028,7 @@ int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* lo
 
 int lb_set_map(lb_ctx* x, const int32_t* map, const double* cost) {
     if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, LB_E_STATE, "context unusable: an earlier step failed part-way");
     if (!map) return fail(&x->err, LB_E_INVAL, "map is NULL");
     const Plan& p = x->plan;
     for (int32_t c = 0; c < p.C; ++c)
@@ -976,6 +1043,7 @@ int lb_set_map(lb_ctx* x, const int32_t* map, const double* cost) {
 
 int lb_fields(lb_ctx* x, int32_t field, void* dst, size_t dst_bytes, double* checksum_out) {
     if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, LB_E_STATE, "context unusable: an earlier step failed part-way");
     const Plan& p = x->plan;
     if (field < 0 || field >= p.nfields) return fail(&x->err, LB_E_INVAL, "field index out of range");
     const size_t bytes = static_cast<size_t>(p.ncells) * p.elem;
@@ -1063,6 +1131,7 @@ int lb_visits(lb_ctx* x, int32_t* out, int32_t n, int32_t reset) {
 
 int lb_checksums(lb_ctx* x, double* out, int32_t n, int32_t* got) {
     if (!x || !out || !got) return fail(x ? &x->err : nullptr, LB_E_INVAL, "ctx, out and got are required");
+    if (x->broken) return fail(&x->err, LB_E_STATE, "context unusable: an earlier step failed part-way");
     HIP_TRY(x, hipSetDevice(x->device));
     LAUNCH_TRY(x, launch_flush(x->args, x->stream));   // the last step's checksum
     int rc = sync(x);

@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_struct_layout_and_version(lib):
-    assert lib.lb_abi_version() == 1
+    assert lib.lb_abi_version() == 2
     assert lib.lb_config_bytes() == C.sizeof(_abi.LbConfig)
     assert lib.lb_stats_bytes() == C.sizeof(_abi.LbStats)
 
@@ -76,10 +76,14 @@ def test_query_rejects_bad_config(lib, field, value, msg):
     (dict(stage_rows=-4, nz=6), "divisible by 4"), (dict(stage_rows=2, nz=6), "divisible by 4"),
     (dict(stage_rows=-4, tile_x=80), "512 threads"),
     (dict(stage_rows=-1, precision=2, tile_x=80), "FP64"),
+    (dict(march=3), "march must be"), (dict(march=2, nz=6), "march needs nz divisible by 4"),
+    (dict(march=4, precision=2, tile_x=70), "FP64 march"), (dict(march=8, tile_x=200), "1024 threads"),
 ])
 def test_query_rejects_bad_pipeline(lib, over, msg):
     """Register pipeline depths are 2, 4 or 8 rows; the deep ones need V = 4 and
-    workgroups of at most 512 threads, and depth 8 is FP32 only."""
+    workgroups of at most 512 threads, and depth 8 is FP32 only.  The column march
+    takes 2, 4 or 8 rows in flight, needs V = 4 and (tile_x + 2) * nz / 4 threads, at
+    most 512 in FP64."""
     cfg, keep = _abi.config_from_workload(W.small())
     for k, v in over.items():
         setattr(cfg, k, v)

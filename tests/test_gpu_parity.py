@@ -135,6 +135,9 @@ def test_launch_forms_bit_identical():
     dict(stage_rows=-1, tile_x=5, tile_y=3), dict(stage_rows=2, tile_x=32, tile_y=4),
     dict(stage_rows=-4), dict(stage_rows=-8), dict(stage_rows=-4, tile_x=5, tile_y=3),
     dict(stage_rows=-8, tile_y=11), dict(stage_rows=-8, tile_x=40, tile_y=2, nslots=1),
+    dict(march=2), dict(march=4, tile_x=5, tile_y=3), dict(march=8, tile_y=11),
+    dict(march=2, nslots=1, wg_per_queue=8), dict(march=4, nslots=16, nqueues=16, wg_per_queue=1),
+    dict(march=2, tile_x=40, tile_y=2, nslots=3, nqueues=3, steal=0),
 ])
 def test_schedule_invariance(over):
     wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=3)
@@ -191,13 +194,16 @@ def test_ragged_fp64_bit_exact(shape):
     say("ragged", shape)
     wl = mk(nx, ny, nz, px, py, hot=((nx // 3, ny // 2, 1, -1), (0, 0, 0, 0)), sigma=3.0,
             kmax=25, split="dirichlet" if px > 1 else "equal", steps=3, nslots=3)
-    deep = (dict(tile_y=5, stage_rows=2), dict(tile_y=9, stage_rows=-4), dict(tile_x=3, stage_rows=-4))
+    deep = (dict(tile_y=5, stage_rows=2), dict(tile_y=9, stage_rows=-4), dict(tile_x=3, stage_rows=-4),
+            dict(march=2), dict(march=4, tile_x=3, tile_y=2), dict(march=8, tile_x=7, tile_y=9))
+    ref, work, _, _ = oracle.run(wl, nsteps=3)
     for tiles in (dict(), dict(tile_x=3, tile_y=2), dict(stage_rows=-1)) + (deep if nz % 4 == 0 else (dict(tile_y=5),)):
-        g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **tiles)
-        ref, work, _, _ = oracle.run(wl, nsteps=3)
-        np.testing.assert_array_equal(q, ref)
-        np.testing.assert_array_equal(w, work.sum(axis=0))
-        g.close()
+        for mode in (("persistent", "plain") if "march" in tiles else ("persistent",)):
+            g, q, w = run_gpu(wl, 3, mode, precision="fp64", **tiles)
+            np.testing.assert_array_equal(q, ref)
+            np.testing.assert_array_equal(w, work.sum(axis=0))
+            assert np.all(g.visits() == 3)
+            g.close()
 
 
 def test_fp64_register_pipeline_at_its_workgroup_limit():
@@ -213,9 +219,10 @@ def test_fp64_register_pipeline_at_its_workgroup_limit():
         g.close()
 
 
-def test_multi_field_fp64_bit_exact():
+@pytest.mark.parametrize("over", [dict(), dict(march=4), dict(march=2, tile_x=5, tile_y=3)])
+def test_multi_field_fp64_bit_exact(over):
     wl = mk(24, 20, 8, 3, 2, steps=3).replace(nfields=3)
-    g, q, w = run_gpu(wl, 3, "persistent", precision="fp64")
+    g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     np.testing.assert_array_equal(q, ref)
     np.testing.assert_array_equal(w, work.sum(axis=0))
@@ -328,6 +335,39 @@ def test_time_loads_and_busy_counters():
     g.measure("work", reset=True)
     assert g.stats()["measured_steps"] == 0
     assert np.all(g.measure("work") == 0)
+
+
+def test_failed_launch_keeps_the_step_count(monkeypatch):
+    """A launch refused part-way through lb_step (forced from the host): the steps fully
+    enqueued before it count, the context keeps working from there, and its fields
+    equal a run of that many steps.  A plain step refused after some of its per-chunk
+    launches leaves the context unusable (LB_E_STATE) instead of out of step."""
+    from paper_1310_4218_amd._abi import LbError, LB_E_HIP, LB_E_STATE
+    wl = W.small()
+    ref = Grid(wl)
+    ref.step(3, "persistent_eager")
+    g = Grid(wl)
+    monkeypatch.setenv("LBGRID_FAIL_AT", "launch:3")
+    with pytest.raises(LbError) as e:
+        g.step(5, "persistent_eager")
+    assert e.value.code == LB_E_HIP
+    monkeypatch.delenv("LBGRID_FAIL_AT")
+    assert g.stats()["steps"] == 2
+    g.step(1, "persistent_eager")
+    np.testing.assert_array_equal(g.field().numpy(), ref.field().numpy())
+    np.testing.assert_array_equal(g.checksums(3), ref.checksums(3))
+    p = Grid(wl)
+    monkeypatch.setenv("LBGRID_FAIL_AT", f"launch:{wl.nchunks + 4}")   # inside the second step
+    with pytest.raises(LbError) as e:
+        p.step(3, "plain")
+    monkeypatch.delenv("LBGRID_FAIL_AT")
+    assert e.value.code == LB_E_HIP and p.stats()["steps"] == 1
+    with pytest.raises(LbError) as e:
+        p.step(1, "plain")
+    assert e.value.code == LB_E_STATE
+    with pytest.raises(LbError) as e:
+        p.field()
+    assert e.value.code == LB_E_STATE
 
 
 def test_rebalance_needs_measurement():
@@ -489,7 +529,8 @@ def test_vertical_physics_fp64_bit_exact(nz):
     wl = mk(40, 36, nz, 4, 3, kmax=40, sigma=5.0, split="dirichlet", steps=3).replace(vertical=1)
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     for over in (dict(), dict(stage_rows=-1), dict(tile_x=5, tile_y=3)) + \
-            ((dict(stage_rows=-4, tile_x=4),) if nz % 4 == 0 else ()):
+            ((dict(stage_rows=-4, tile_x=4), dict(march=2), dict(march=4, tile_x=3, tile_y=4))
+             if nz % 4 == 0 else ()):
         g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
         np.testing.assert_array_equal(q, ref)
         np.testing.assert_array_equal(w, work.sum(axis=0))
