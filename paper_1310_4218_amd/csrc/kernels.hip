@@ -511,7 +511,9 @@ constexpr int kPipeMarch = 100;
 // and the compiler counts outstanding memory operations exactly (no divergent
 // branch around them).
 using rsrc_t = __amdgpu_buffer_rsrc_t;
-constexpr uint32_t kOutOfRange = 0xFFFFFFE0u;
+// Far enough above every field (fields are limited to 0xFFFFFE00 bytes) that no
+// part of a 32-byte access from it wraps round to a valid offset.
+constexpr uint32_t kOutOfRange = 0xFFFFFF00u;
 constexpr int kRsrcWord3 = 0x00020000;   // gfx9 buffer format word: 32-bit data, no swizzle
 
 __device__ __forceinline__ rsrc_t field_rsrc(const void* base, uint32_t bytes) {
@@ -611,6 +613,7 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
     }
     double chk = 0.0;
     int ksum = 0, krows = 0;                  // trip counts and rows of this thread's column (field 0)
+    int lpar = 0;                             // LDS buffer of the next row
     for (int f = 0; f < a.nfields; ++f) {
         const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
         const rsrc_t out = field_rsrc(dst + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
@@ -619,14 +622,17 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
         Vec<T, V> R[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) R[j] = bload<T, V>(in, row_off(1 + j));
-        // row r: publish row r in LDS buffer r & 1, take row r + 1 from the ring
-        // and refill its slot with row r + 1 + D, compute row r, store it
+        // row r: publish row r in the LDS buffer of this row's parity, take row
+        // r + 1 from the ring and refill its slot with row r + 1 + D, compute row
+        // r, store it.  The parity runs on across fields, so consecutive rows
+        // always use different buffers and one barrier per row suffices.
         for (int r0 = 0; r0 < h; r0 += D) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 const int r = r0 + j;
                 if (r < h) {
-                    T* L = lds + (r & 1) * RL;
+                    T* L = lds + lpar * RL;
+                    lpar ^= 1;
                     if (streams) st<T, V>(L + tcol * nz + zoff, c);
                     __syncthreads();
                     if (f == 0 && r == 0) hook();

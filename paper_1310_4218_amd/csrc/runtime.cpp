@@ -181,7 +181,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.M = c->march;
     if (p.M > 0) {
         if (p.vec != 4) return bad("march needs nz divisible by 4");
-        if (static_cast<uint64_t>(p.ncells) * p.elem > 0xFFFFFFE0ull)
+        if (static_cast<uint64_t>(p.ncells) * p.elem > 0xFFFFFE00ull)
             return bad("march needs every field below 4 GiB (32-bit buffer offsets)");
     }
     if (p.M == 0 && c->stage_rows > 0 && p.vec != 4) return bad("stage_rows > 0 needs nz divisible by 4");
