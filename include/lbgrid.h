@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 2
+#define LB_ABI_VERSION 3
 #define LB_MAX_HOT 4
 #define LB_NBUF 3
 
@@ -144,6 +144,19 @@ typedef struct {
                                 field below 4 GiB, (tile_x + 2) * nz / 4
                                 threads per workgroup, at most 512 in FP64);
                                 overrides stage_rows.  0 = off (default)      */
+    int32_t queue_order;     /* order of the items of a queue: 0 = longest
+                                first (cost per item descending); 1 = the hot
+                                items (cost per item above twice the queue's
+                                mean) longest first, then all others by their
+                                position (first row, then first column), so
+                                that workgroups running at the same time read
+                                neighbouring rows (default 0)                 */
+    int32_t item_grid;       /* 1: a balanced step (LB_PERSISTENT,
+                                LB_PERSISTENT_EAGER) launches one workgroup
+                                per item, in queue order, and the hardware
+                                dispatcher schedules them instead of claims on
+                                the queues; needs march > 0.  0 = persistent
+                                workgroups claiming from the queues (default) */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;

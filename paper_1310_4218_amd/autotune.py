@@ -28,8 +28,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 
 SPACE = {
+    "item_grid": [0, 1],          # 1: one workgroup per item (needs march > 0)
+    "march": [0, 2, 4, 8],        # > 0: column-march pipeline, rows in flight
+    "queue_order": [0, 1],        # 1: hot items longest first, the rest by position
     "tile_x": [8, 16, 32, 64],
-    "tile_y": [2, 4, 8, 16, 32],
+    "tile_y": [2, 4, 8, 12, 16, 24, 32],
     "nqueues": [1, 8, 32, 256],
     "wg_per_queue": [0],          # 0: fill the device (resident workgroups / queues)
     "item_split": [0, 1, 2, 3, 4, 5, 6, 8],
@@ -104,7 +107,7 @@ def measure(wl, params: dict, precision: str, steps: int, warm: int, torch):
 
 
 def tune(wl, precision: str = "fp32", steps: int = 50, warm: int = 20, log=print,
-         seeds=()) -> dict:
+         seeds=(), from_defaults: bool = True) -> dict:
     """Coordinate descent (two sweeps over SPACE) from the library defaults and
     from every extra starting point in `seeds`; the best candidate whose fields
     are bit-identical to the defaults' wins."""
@@ -142,7 +145,7 @@ def tune(wl, precision: str = "fp32", steps: int = 50, warm: int = 20, log=print
                         best, best_t = cand, t
         return best, best_t
 
-    best, best_t = descend(base, t_base)
+    best, best_t = descend(base, t_base) if from_defaults else (base, t_base)
     for seed in seeds:
         seed = {k: v for k, v in seed.items() if k in SPACE}
         key = json.dumps(seed, sort_keys=True)
@@ -165,6 +168,9 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warm", type=int, default=20)
+    ap.add_argument("--seed", action="append", default=[], help="extra starting point (JSON)")
+    ap.add_argument("--seeds-only", action="store_true",
+                    help="descend only from the cached optimum and the --seed points")
     args = ap.parse_args(argv)
 
     import torch
@@ -180,8 +186,10 @@ def main(argv=None) -> int:
         wl = W.get(name)
         print(f"tuning {wl.name} ({args.precision}) on {arch}", flush=True)
         prev = cache.get(_key(arch, name, args.precision), {}).get("params")
+        seeds = ([prev] if prev else []) + [json.loads(j) for j in args.seed]
         res = tune(wl, args.precision, args.steps, args.warm,
-                   log=lambda *a: print(*a, flush=True), seeds=[prev] if prev else [])
+                   log=lambda *a: print(*a, flush=True), seeds=seeds,
+                   from_defaults=not args.seeds_only)
         print(json.dumps(res), flush=True)
         cache[_key(arch, name, args.precision)] = res
         with open(CACHE + ".tmp", "w") as f:

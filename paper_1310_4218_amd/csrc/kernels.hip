@@ -544,27 +544,29 @@ __device__ __forceinline__ Vec<T, V> bload(rsrc_t r, uint32_t off) {
     }
     return x;
 }
-template <typename T, int V>
+// AUX: the store's cache policy; 2 marks it non-temporal (streamed past the
+// caches), for output that is not read again before the whole field has gone by.
+template <typename T, int V, int AUX>
 __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, const Vec<T, V>& x) {
     constexpr int B = static_cast<int>(sizeof(T)) * V;
     if constexpr (B == 32) {
         u32x4 lo, hi;
         __builtin_memcpy(&lo, &x, 16);
         __builtin_memcpy(&hi, reinterpret_cast<const char*>(&x) + 16, 16);
-        __builtin_amdgcn_raw_buffer_store_b128(lo, r, static_cast<int>(off), 0, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(hi, r, static_cast<int>(off + 16u), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(lo, r, static_cast<int>(off), 0, AUX);
+        __builtin_amdgcn_raw_buffer_store_b128(hi, r, static_cast<int>(off + 16u), 0, AUX);
     } else if constexpr (B == 16) {
         u32x4 v;
         __builtin_memcpy(&v, &x, 16);
-        __builtin_amdgcn_raw_buffer_store_b128(v, r, static_cast<int>(off), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, static_cast<int>(off), 0, AUX);
     } else if constexpr (B == 8) {
         u32x2 v;
         __builtin_memcpy(&v, &x, 8);
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, static_cast<int>(off), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, static_cast<int>(off), 0, AUX);
     } else {
         unsigned v;
         __builtin_memcpy(&v, &x, 4);
-        __builtin_amdgcn_raw_buffer_store_b32(v, r, static_cast<int>(off), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, static_cast<int>(off), 0, AUX);
     }
 }
 
@@ -678,7 +680,10 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
                         gy = gy >= ny ? gy - ny : gy;
                         so = colbytes + static_cast<uint32_t>(gy) * rowbytes;
                     }
-                    bstore<T, V>(out, so, o);
+                    if (a.stream_store)
+                        bstore<T, V, 2>(out, so, o);
+                    else
+                        bstore<T, V, 0>(out, so, o);
                     ym = c;
                     c = yp;
                 }
@@ -919,6 +924,7 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_persistent(DevArgs a) {
         if (threadIdx.x == 0) {
             a.ctrl->pend_n[par] = a.ctrl->nitems;
             a.ctrl->pend_step[par] = step + 1;
+            a.pstate[par ^ 1] = next_state(a, ws);
         }
     }
     if (wg == a.nwg - 1) settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
@@ -1038,6 +1044,7 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
         if (threadIdx.x == 0) {
             a.ctrl->pend_n[par] = a.ctrl->nitems;
             a.ctrl->pend_step[par] = step + 1;
+            a.pstate[par ^ 1] = next_state(a, ws);
         }
     }
     if (wg == a.nwg - 1) settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
@@ -1094,6 +1101,48 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
     }
 }
 
+// One launch per step with one workgroup per item: workgroup b runs item b of
+// the queue order (all queues in turn; with one queue, the global longest-first
+// or hot-first-then-by-position order), and the hardware dispatcher starts each
+// workgroup as soon as a previous one leaves the CU.  This keeps every CU full
+// of short-lived workgroups whose loads cover neighbouring rows, the pattern a
+// streaming kernel reads HBM fastest with, and needs no claims.  The step
+// state is the shared copy of the step's parity (par, from the host); workgroup
+// 0 writes the next step's copy, resets the other claim-counter set, records
+// this step's pending checksum and sums the previous step's.
+template <typename T, int V, int KAHAN, int D>
+__global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items(DevArgs a, int par) {
+    extern __shared__ __align__(32) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    __shared__ double red[kRedLen];
+
+    const WgState ws = a.pstate[par];
+    StepInfo si;
+    si.step = ws.step;
+#pragma unroll
+    for (int h = 0; h < kMaxHot; ++h) {
+        si.hcx[h] = uni(ws.hx[h]);
+        si.hcy[h] = uni(ws.hy[h]);
+    }
+    const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(par ? a.field0 : a.field1);
+    double* partials = a.partials + static_cast<int64_t>(par) * a.part_stride;
+    if (blockIdx.x == 0) {
+        settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
+        int* other = a.heads + (par ^ 1) * a.nqueues;
+        for (int q = threadIdx.x; q < a.nqueues; q += a.block) other[q] = a.head0;
+        if (threadIdx.x == 0) {
+            a.ctrl->pend_n[par] = a.ctrl->nitems;
+            a.ctrl->pend_step[par] = ws.step + 1;
+            a.pstate[par ^ 1] = next_state(a, ws);
+        }
+    }
+    const ItemDesc d = uni(a.queue[blockIdx.x]);
+    const uint64_t t_start = wall_clock64();
+    const ItemOut o = process_item_march<T, V, KAHAN, D>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
+    record_item(a, partials, d, o, static_cast<double>(wall_clock64() - t_start));
+}
+
 template <typename T, int V, int KAHAN, int PIPE>
 __global__ __launch_bounds__(max_block<T>(PIPE)) void k_plain(DevArgs a, int chunk) {
     extern __shared__ __align__(32) unsigned char smem[];
@@ -1142,6 +1191,16 @@ __global__ __launch_bounds__(kSumThreads) void k_finish(DevArgs a) {
     __syncthreads();                  // every thread has read wstate[0]
     const WgState nx = next_state(a, ws);
     for (int w = threadIdx.x; w < a.nwg; w += kSumThreads) a.wstate[w] = nx;
+    if (threadIdx.x == 0) a.pstate[par ^ 1] = nx;
+}
+
+// Every workgroup's own copy of the step state from the shared copy of parity
+// par (after steps launched one workgroup per item, which keep only the shared
+// copies, and before a form that reads its own copy).
+__global__ __launch_bounds__(256) void k_seed_state(DevArgs a, int par) {
+    const WgState s = a.pstate[par];
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < a.nwg; w += gridDim.x * blockDim.x)
+        a.wstate[w] = s;
 }
 
 // Sums the checksum of any persistent step still pending (one workgroup).
@@ -1183,6 +1242,7 @@ __global__ void k_reset_control(DevArgs a) {
         first.hy[h] = a.hy_first[h];
     }
     for (int w = threadIdx.x; w < a.nwg; w += blockDim.x) a.wstate[w] = first;
+    if (threadIdx.x < 2) a.pstate[threadIdx.x] = first;
     if (threadIdx.x == 0) {
         a.ctrl->pend_step[0] = 0;
         a.ctrl->pend_step[1] = 0;
@@ -1261,6 +1321,7 @@ __global__ __launch_bounds__(256) void k_sum2(const double* partial, int nb, dou
 // ---- dispatch ------------------------------------------------------------------
 using PersistentFn = void (*)(DevArgs);
 using PlainFn = void (*)(DevArgs, int);
+using ItemsFn = void (*)(DevArgs, int);
 
 // pipe: kPipeDma, or the register pipeline's depth (2, 4 or 8 with V = 4, where
 // the host allows 8 in FP32 only: eight FP64 rows do not fit in registers; 2 otherwise)
@@ -1293,6 +1354,20 @@ PlainFn plain_for(int vec, int pipe) {
         }
     }
     return vec == 2 ? k_plain<T, 2, KAHAN, 2> : k_plain<T, 1, KAHAN, 2>;
+}
+
+template <typename T, int KAHAN>
+ItemsFn items_for(int pipe) {
+    switch (pipe) {
+        case kPipeMarch + 4: return k_items<T, 4, KAHAN, 4>;
+        case kPipeMarch + 8: return k_items<T, 4, KAHAN, 8>;
+        default: return k_items<T, 4, KAHAN, 2>;
+    }
+}
+ItemsFn pick_items(int prec, int pipe) {
+    if (prec == 2) return items_for<double, 0>(pipe);
+    if (prec == 1) return items_for<float, 1>(pipe);
+    return items_for<float, 0>(pipe);
 }
 
 PersistentFn pick_persistent(int prec, int vec, int pipe) {
@@ -1334,6 +1409,21 @@ int launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitem
                        int block, size_t lds, void* stream) {
     hipLaunchKernelGGL(pick_plain(prec, vec, pipe_of(a)), dim3(nitems_chunk), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a, chunk);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int par,
+                 void* stream) {
+    if (vec != 4 || a.march <= 0 || nitems <= 0) return static_cast<int>(hipErrorInvalidValue);
+    hipLaunchKernelGGL(pick_items(prec, pipe_of(a)), dim3(nitems), dim3(block), lds,
+                       static_cast<hipStream_t>(stream), a, par);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_seed_state(const DevArgs& a, int par, void* stream) {
+    const int blocks = (a.nwg + 255) / 256;
+    hipLaunchKernelGGL(k_seed_state, dim3(blocks > 0 ? blocks : 1), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), a, par);
     return static_cast<int>(hipGetLastError());
 }
 

@@ -63,6 +63,9 @@ struct DevArgs {
     int32_t* heads;            // 2 x Q claim counters, one set per step parity; a step finds
                                // its set at head0 and resets the other set for the next step
     WgState* wstate;           // nwg: step and hotspot centres, kept by each workgroup
+    WgState* pstate;           // 2, by step parity: the state of a step whose launch form
+                               // reads one shared copy (one workgroup per item); every form
+                               // writes the next step's copy
     Ctrl* ctrl;
     double* loads_work;        // C
     double* loads_time;        // C
@@ -85,6 +88,9 @@ struct DevArgs {
     int32_t stage_rows;        // > 0: rows per direct global->LDS batch (V = 4 only); 0: registers
     int32_t reg_depth;         // register pipeline: rows in flight (2, 4 or 8; 2 unless V = 4)
     int32_t march;             // > 0: column-march pipeline with this many rows in flight (2, 4, 8)
+    int32_t item_grid;         // 1: a balanced step launches one workgroup per item (queue order)
+    int32_t stream_store;      // 1: the march writes its output non-temporally (both field
+                               // copies exceed the 256 MB last-level cache)
     uint32_t field_bytes;      // bytes of one field (< 4 GiB with the march pipeline)
     int32_t vertical;          // 1: column physics with the vertical dependency
     int32_t r2cut;
@@ -111,6 +117,12 @@ int  launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, 
                        void* stream);
 int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitems_chunk,
                         int block, size_t lds, void* stream);
+// One workgroup per item of the installed plan (nitems of them, in queue order);
+// par is the parity of the step (steps enqueued so far, mod 2).
+int  launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int par,
+                  void* stream);
+// Copy the shared state of a step of parity par into every workgroup's own copy.
+int  launch_seed_state(const DevArgs& a, int par, void* stream);
 int  launch_finish(const DevArgs& a, void* stream);
 int  launch_flush(const DevArgs& a, void* stream);
 int  launch_gather(const GatherSeg* segs, int n, void* stream);   // n <= kMaxGather

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstddef>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -45,6 +46,7 @@ struct Plan {
     int32_t prec = 0, vec = 1, elem = 4, TX = 16, TY = 16, block = 0, ntiles = 0;
     int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
     int32_t M = 0;          // rows in flight of the column march; 0 = another pipeline
+    bool IG = false;        // balanced steps launch one workgroup per item
     int32_t B = 0;          // rows per direct global->LDS batch; 0 = register pipeline
     int32_t ring = 4;       // LDS ring rows
     int32_t r2cut = 0;
@@ -54,7 +56,7 @@ struct Plan {
     // workspace layout (byte offsets)
     size_t off_ctrl = 0, off_ktab = 0, off_items = 0, off_itemoff = 0, off_queue = 0, off_seg = 0,
            off_heads = 0, off_lw = 0, off_lt = 0, off_tw = 0, off_part = 0, off_hist = 0, off_busy = 0, off_tl = 0,
-           off_visits = 0, off_sum = 0, off_first = 0, off_wstate = 0, ws_bytes = 0;
+           off_visits = 0, off_sum = 0, off_first = 0, off_wstate = 0, off_pstate = 0, ws_bytes = 0;
     size_t st_loads = 0, st_tiles = 0, st_items = 0, st_queue = 0, st_first = 0, st_off = 0, st_seg = 0, st_n = 0,
            st_bytes = 0;  // pinned staging layout
     size_t field_bytes = 0;
@@ -155,6 +157,9 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->physics != LB_PHYS_POINTWISE && c->physics != LB_PHYS_VERTICAL) return bad("physics");
     if (c->march != 0 && c->march != 2 && c->march != 4 && c->march != 8)
         return bad("march must be 0 (off), 2, 4 or 8 rows in flight");
+    if (c->queue_order != 0 && c->queue_order != 1) return bad("queue_order must be 0 or 1");
+    if (c->item_grid != 0 && c->item_grid != 1) return bad("item_grid must be 0 or 1");
+    if (c->item_grid == 1 && c->march == 0) return bad("item_grid needs the column-march pipeline (march > 0)");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
     p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
@@ -179,6 +184,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     // pipeline: the column march (M rows in flight), direct global->LDS batches of B
     // rows (V = 4 only) or the register path
     p.M = c->march;
+    p.IG = c->item_grid == 1;
     if (p.M > 0) {
         if (p.vec != 4) return bad("march needs nz divisible by 4");
         if (static_cast<uint64_t>(p.ncells) * p.elem > 0xFFFFFE00ull)
@@ -267,6 +273,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_sum = take(sizeof(double) * (kSumBlocks + 1));
     p.off_first = take(sizeof(ItemDesc) * 2 * static_cast<size_t>(p.nwg_cap));
     p.off_wstate = take(sizeof(WgState) * static_cast<size_t>(p.nwg_cap));
+    p.off_pstate = take(sizeof(WgState) * 2);
     p.ws_bytes = o;
     // pinned staging: measured loads, then the plan tables of an upload
     size_t h = 0;
@@ -298,6 +305,7 @@ struct lb_ctx {
     std::vector<int32_t> tiles;       // 4 per tile
     std::vector<int32_t> tile_off;    // C + 1: tiles of chunk c
     std::vector<int32_t> row_base;    // per tile: its first row in the visit counters
+    std::vector<int32_t> pos_rank;    // per tile: its rank by (first row, first column)
     std::vector<ItemDesc> items;      // the installed plan, chunk order
     std::vector<int32_t> item_off;    // C + 1
     int64_t plan_version = 0;
@@ -319,6 +327,12 @@ struct lb_ctx {
     bool upload_pending = false;
     hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
     hipGraphExec_t g_pers1 = nullptr; // one persistent step
+    // one workgroup per item: graph_steps steps and one step, per parity of the
+    // first step (the parity is a launch argument), for the plan they were taken on
+    hipGraphExec_t g_items[2] = {nullptr, nullptr};
+    hipGraphExec_t g_items1[2] = {nullptr, nullptr};
+    int64_t items_graph_version[2] = {-1, -1};
+    bool wstate_stale = false;        // only the shared per-parity step state is current
     hipGraphExec_t g_plain = nullptr; // one plain step
     std::string err;
 };
@@ -374,6 +388,15 @@ void build_tiles(lb_ctx* x) {
                 }
         }
     x->tile_off[p.C] = t;
+    {
+        std::vector<uint64_t> k(static_cast<size_t>(p.ntiles));
+        for (int32_t i = 0; i < p.ntiles; ++i)   // y0, x0 < 2^16 (validated grid sizes)
+            k[i] = (static_cast<uint64_t>(x->tiles[4 * i + 1]) << 48) |
+                   (static_cast<uint64_t>(x->tiles[4 * i + 0]) << 32) | static_cast<uint32_t>(i);
+        std::sort(k.begin(), k.end());
+        x->pos_rank.resize(static_cast<size_t>(p.ntiles));
+        for (int32_t r = 0; r < p.ntiles; ++r) x->pos_rank[k[r] & 0xffffffffu] = r;
+    }
     x->row_base.resize(static_cast<size_t>(p.ntiles));
     int32_t r = 0;
     for (int32_t i = 0; i < p.ntiles; ++i) {
@@ -442,11 +465,25 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     // The sort key is one integer: the complemented bits of the cost per piece
     // as a float (non-negative floats order like their bit patterns), then the
     // tile index; plain integer sorting keeps a plan of ~10^4 tiles cheap.
+    // With queue_order 1 only the hot tiles (cost per piece above twice the
+    // mean over all pieces) are keyed by cost; every other tile sorts after
+    // them by its position rank (first row, then first column).  Keys: cost
+    // keys have the top bit clear, position keys set.
+    double hot_cut = 0.0;
+    if (x->cfg.queue_order >= 1) {
+        int64_t npieces = 0;
+        for (int32_t t = 0; t < p.ntiles; ++t) npieces += pieces[t];
+        hot_cut = npieces > 0 ? 2.0 * W / static_cast<double>(npieces) : 0.0;
+    }
     auto key_of = [&](int32_t t) -> uint64_t {
-        const float per_piece = static_cast<float>(tcost[t] / pieces[t]);
-        uint32_t bits;
+        const double pp = tcost[t] / pieces[t];
+        if (x->cfg.queue_order >= 1 && !(pp > hot_cut))
+            return (static_cast<uint64_t>(0x80000000u | static_cast<uint32_t>(x->pos_rank[t])) << 32) |
+                   static_cast<uint32_t>(t);
+        const float per_piece = static_cast<float>(pp);
+        uint32_t bits;   // a non-negative float: top bit clear, so ~bits has it set
         std::memcpy(&bits, &per_piece, sizeof(bits));
-        return (static_cast<uint64_t>(~bits) << 32) | static_cast<uint32_t>(t);
+        return (static_cast<uint64_t>(~bits & 0x7fffffffu) << 32) | static_cast<uint32_t>(t);
     };
     std::vector<uint64_t> order(static_cast<size_t>(p.ntiles));
     {
@@ -586,14 +623,22 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     return LB_OK;
 }
 
-int capture(lb_ctx* x, int mode, int nsteps, hipGraphExec_t* out) {
+// Launch of one balanced step (either form); par is the step's parity.
+int launch_balanced(lb_ctx* x, int par, hipStream_t s) {
+    const Plan& p = x->plan;
+    if (p.IG)
+        return launch_items(x->args, p.prec, p.vec, static_cast<int>(x->items.size()), p.block, p.lds, par, s);
+    return launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, s);
+}
+
+int capture(lb_ctx* x, int mode, int nsteps, hipGraphExec_t* out, int par0 = 0) {
     const Plan& p = x->plan;
     hipGraph_t g = nullptr;
     HIP_TRY(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
     int rc = 0;
     for (int i = 0; i < nsteps && rc == 0; ++i) {
         if (mode == LB_PERSISTENT) {
-            rc = launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, x->cap);
+            rc = launch_balanced(x, (par0 + i) & 1, x->cap);
         } else {
             for (int32_t c = 0; c < p.C && rc == 0; ++c)
                 rc = launch_plain_chunk(x->args, p.prec, p.vec, c, x->item_off[c + 1] - x->item_off[c],
@@ -672,6 +717,8 @@ void lb_config_default(lb_config* c) {
     c->tail_split = 4;
     c->item_alpha = -1;
     c->march = 0;
+    c->queue_order = 0;
+    c->item_grid = 0;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
@@ -769,6 +816,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.firstd = reinterpret_cast<const ItemDesc*>(x->ws + P.off_first);
     a.heads = reinterpret_cast<int32_t*>(x->ws + P.off_heads);
     a.wstate = reinterpret_cast<WgState*>(x->ws + P.off_wstate);
+    a.pstate = reinterpret_cast<WgState*>(x->ws + P.off_pstate);
     a.ctrl = reinterpret_cast<Ctrl*>(x->ws + P.off_ctrl);
     a.loads_work = reinterpret_cast<double*>(x->ws + P.off_lw);
     a.loads_time = reinterpret_cast<double*>(x->ws + P.off_lt);
@@ -787,6 +835,10 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.stage_rows = P.B;
     a.reg_depth = P.RD;
     a.march = P.M;
+    a.item_grid = P.IG ? 1 : 0;
+    // the next read of an output cell comes a whole field later: past the
+    // last-level cache (256 MB on this GPU) when the two copies exceed it
+    a.stream_store = 2 * P.field_bytes > (size_t{256} << 20) ? 1 : 0;
     a.field_bytes = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(P.ncells) * P.elem, 0xFFFFFFFFull));
     a.vertical = cfg->physics == LB_PHYS_VERTICAL ? 1 : 0;
     if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
@@ -875,9 +927,44 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
                                               : "forced launch failure (LBGRID_FAIL_AT)"));
     };
     int rc;
+    // Forms that read every workgroup's own copy of the step state need it
+    // refreshed after steps launched one workgroup per item.
+    const bool own_state = !(p.IG && (mode == LB_PERSISTENT || mode == LB_PERSISTENT_EAGER));
+    if (own_state && x->wstate_stale) {
+        LAUNCH_TRY(x, launch_seed_state(x->args, static_cast<int>(x->steps & 1), x->stream));
+        x->wstate_stale = false;
+    }
+    if (!own_state) x->wstate_stale = true;
     switch (mode) {
         case LB_PERSISTENT: {
             const int R = x->cfg.graph_steps;
+            if (p.IG) {
+                // graphs per parity of their first step, retaken when the plan changes
+                for (int k = 0; k < 2; ++k)
+                    if (x->items_graph_version[k] != x->plan_version) {
+                        if (x->g_items[k]) HIP_TRY(x, hipGraphExecDestroy(x->g_items[k]));
+                        if (x->g_items1[k]) HIP_TRY(x, hipGraphExecDestroy(x->g_items1[k]));
+                        x->g_items[k] = x->g_items1[k] = nullptr;
+                        x->items_graph_version[k] = x->plan_version;
+                    }
+                for (int i = 0; i < nsteps / R; ++i) {
+                    const int par = static_cast<int>(x->steps & 1);
+                    if (!x->g_items[par] && (rc = capture(x, LB_PERSISTENT, R, &x->g_items[par], par)) != LB_OK)
+                        return rc;
+                    if (forced()) return launch_failed("hipGraphLaunch", 0, false);
+                    if (int e = hipGraphLaunch(x->g_items[par], x->stream)) return launch_failed("hipGraphLaunch", e, false);
+                    done(R);
+                }
+                for (int i = 0; i < nsteps % R; ++i) {
+                    const int par = static_cast<int>(x->steps & 1);
+                    if (!x->g_items1[par] && (rc = capture(x, LB_PERSISTENT, 1, &x->g_items1[par], par)) != LB_OK)
+                        return rc;
+                    if (forced()) return launch_failed("hipGraphLaunch", 0, false);
+                    if (int e = hipGraphLaunch(x->g_items1[par], x->stream)) return launch_failed("hipGraphLaunch", e, false);
+                    done(1);
+                }
+                break;
+            }
             if (nsteps >= R && !x->g_pers && (rc = capture(x, LB_PERSISTENT, R, &x->g_pers)) != LB_OK) return rc;
             if (nsteps % R && !x->g_pers1 && (rc = capture(x, LB_PERSISTENT, 1, &x->g_pers1)) != LB_OK) return rc;
             for (int i = 0; i < nsteps / R; ++i) {
@@ -894,9 +981,9 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
         }
         case LB_PERSISTENT_EAGER:
             for (int i = 0; i < nsteps; ++i) {
-                if (forced()) return launch_failed("launch_persistent", 0, false);
-                if (int e = launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, x->stream))
-                    return launch_failed("launch_persistent", e, false);
+                if (forced()) return launch_failed("launch_balanced", 0, false);
+                if (int e = launch_balanced(x, static_cast<int>(x->steps & 1), x->stream))
+                    return launch_failed("launch_balanced", e, false);
                 done(1);
             }
             break;
@@ -1151,6 +1238,10 @@ void lb_destroy(lb_ctx* x) {
     if (x->stream || x->cap) (void)hipStreamSynchronize(x->stream);
     if (x->g_pers) (void)hipGraphExecDestroy(x->g_pers);
     if (x->g_pers1) (void)hipGraphExecDestroy(x->g_pers1);
+    for (int k = 0; k < 2; ++k) {
+        if (x->g_items[k]) (void)hipGraphExecDestroy(x->g_items[k]);
+        if (x->g_items1[k]) (void)hipGraphExecDestroy(x->g_items1[k]);
+    }
     if (x->g_plain) (void)hipGraphExecDestroy(x->g_plain);
     if (x->upload_done) (void)hipEventDestroy(x->upload_done);
     if (x->measured_ev) (void)hipEventDestroy(x->measured_ev);

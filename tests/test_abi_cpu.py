@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_struct_layout_and_version(lib):
-    assert lib.lb_abi_version() == 2
+    assert lib.lb_abi_version() == 3
     assert lib.lb_config_bytes() == C.sizeof(_abi.LbConfig)
     assert lib.lb_stats_bytes() == C.sizeof(_abi.LbStats)
 

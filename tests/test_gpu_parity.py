@@ -138,6 +138,9 @@ def test_launch_forms_bit_identical():
     dict(march=2), dict(march=4, tile_x=5, tile_y=3), dict(march=8, tile_y=11),
     dict(march=2, nslots=1, wg_per_queue=8), dict(march=4, nslots=16, nqueues=16, wg_per_queue=1),
     dict(march=2, tile_x=40, tile_y=2, nslots=3, nqueues=3, steal=0),
+    dict(march=2, item_grid=1), dict(march=4, item_grid=1, tile_x=5, tile_y=3),
+    dict(march=8, item_grid=1, tile_y=11, queue_order=1), dict(march=4, item_grid=1, nslots=16, nqueues=16),
+    dict(march=2, queue_order=1, tile_x=4, tile_y=3),
 ])
 def test_schedule_invariance(over):
     wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=3)
@@ -148,6 +151,32 @@ def test_schedule_invariance(over):
     np.testing.assert_array_equal(w, wb)
     v = g.visits()
     assert np.all(v == 3)
+
+
+def test_item_grid_mixed_launch_forms_fp64():
+    """One workgroup per item keeps a shared step state per parity; every other form keeps
+    one per workgroup.  Steps of every form in one context, with graphs of both parities
+    and a rebalance between them, give the oracle's fields bit for bit, its loads and its
+    per-step checksums, and every tile row is computed once per step."""
+    wl = mk(40, 36, 12, 4, 3, hot=((5, 4, 1, 2),), split="dirichlet", steps=12, nslots=5)
+    ref, work, ck, _ = oracle.run(wl, nsteps=12)
+    g = Grid(wl, precision="fp64", march=4, item_grid=1, graph_steps=2, tile_x=6, tile_y=5)
+    g.step(2, "persistent_eager")
+    g.step(1, "plain")
+    g.step(3, "persistent")          # one graph of two steps, then a one-step graph
+    w6 = g.measure("work")
+    g.rebalance("greedy")
+    g.step(1, "persistent_eager")
+    g.step(1, "plain_graph")
+    g.step(3, "persistent")          # graphs taken again for the new plan, other parity first
+    g.step(1, "plain")
+    w12 = g.measure("work")
+    np.testing.assert_array_equal(gpu_fields(g), ref)
+    np.testing.assert_array_equal(w6, work[:6].sum(axis=0))
+    np.testing.assert_array_equal(w12, work[6:].sum(axis=0))
+    np.testing.assert_allclose(g.checksums(12), ck, rtol=1e-12, atol=1e-9)
+    assert np.all(g.visits() == 12)
+    g.close()
 
 
 def test_map_does_not_change_fields():
@@ -195,7 +224,8 @@ def test_ragged_fp64_bit_exact(shape):
     wl = mk(nx, ny, nz, px, py, hot=((nx // 3, ny // 2, 1, -1), (0, 0, 0, 0)), sigma=3.0,
             kmax=25, split="dirichlet" if px > 1 else "equal", steps=3, nslots=3)
     deep = (dict(tile_y=5, stage_rows=2), dict(tile_y=9, stage_rows=-4), dict(tile_x=3, stage_rows=-4),
-            dict(march=2), dict(march=4, tile_x=3, tile_y=2), dict(march=8, tile_x=7, tile_y=9))
+            dict(march=2), dict(march=4, tile_x=3, tile_y=2), dict(march=8, tile_x=7, tile_y=9),
+            dict(march=2, item_grid=1), dict(march=4, item_grid=1, tile_x=3, tile_y=2))
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     for tiles in (dict(), dict(tile_x=3, tile_y=2), dict(stage_rows=-1)) + (deep if nz % 4 == 0 else (dict(tile_y=5),)):
         for mode in (("persistent", "plain") if "march" in tiles else ("persistent",)):
@@ -219,7 +249,8 @@ def test_fp64_register_pipeline_at_its_workgroup_limit():
         g.close()
 
 
-@pytest.mark.parametrize("over", [dict(), dict(march=4), dict(march=2, tile_x=5, tile_y=3)])
+@pytest.mark.parametrize("over", [dict(), dict(march=4), dict(march=2, tile_x=5, tile_y=3),
+                                  dict(march=2, item_grid=1, tile_x=5, tile_y=3)])
 def test_multi_field_fp64_bit_exact(over):
     wl = mk(24, 20, 8, 3, 2, steps=3).replace(nfields=3)
     g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
@@ -529,7 +560,8 @@ def test_vertical_physics_fp64_bit_exact(nz):
     wl = mk(40, 36, nz, 4, 3, kmax=40, sigma=5.0, split="dirichlet", steps=3).replace(vertical=1)
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     for over in (dict(), dict(stage_rows=-1), dict(tile_x=5, tile_y=3)) + \
-            ((dict(stage_rows=-4, tile_x=4), dict(march=2), dict(march=4, tile_x=3, tile_y=4))
+            ((dict(stage_rows=-4, tile_x=4), dict(march=2), dict(march=4, tile_x=3, tile_y=4),
+              dict(march=4, item_grid=1, tile_x=3, tile_y=4))
              if nz % 4 == 0 else ()):
         g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
         np.testing.assert_array_equal(q, ref)
