@@ -72,37 +72,55 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_balanced(Grid, wl, steps, warmup, R, params, torch):
+def run_balanced(Grid, wl, steps, warmup, R, params, torch, overlap=2):
+    """The balanced path: windows of R steps; after each window except the last
+    (the rebalance points R, 2R, ... before the end) the window's loads are
+    snapshotted, the next window's first `overlap` steps are enqueued, and only
+    then does the host wait for the snapshot and remap, so that the balancer and
+    the plan build run while those steps run on the GPU; the new plan serves the
+    window's other steps.  The warm-up ends with a rebalance, so the timed steps
+    start from a measured plan.  Every kernel launch is timed with HIP events on
+    the library's stream (the snapshot and plan-upload kernels between them are
+    not)."""
     g = Grid(wl, graph_steps=R, **params)
     stream = g.stream
+    evs = []
 
-    def window(n, evs=None):
-        if evs is not None:
-            evs[0].record(stream)
+    def timed_steps(n, timed):
+        if n <= 0:
+            return
+        if timed:
+            e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            e[0].record(stream)
         g.step(n, MODE)
-        if evs is not None:
-            evs[1].record(stream)
-        loads = g.measure("work")            # synchronizes: the paper's measurement point
-        m, nmig, lam = g.rebalance(wl.strategy, wl.threshold)
-        return loads, nmig, lam
+        if timed:
+            e[1].record(stream)
+            evs.append(e)
 
-    done = 0
-    while done < warmup:                     # warm-up windows
-        n = min(R, warmup - done)
-        window(n)
-        done += n
+    def run(nsteps, timed):
+        wins = []
+        done = min(R, nsteps)
+        timed_steps(done, timed)
+        while done < nsteps:
+            n = min(R, nsteps - done)
+            g.measure_begin("work")          # the window's loads: the paper's measurement point
+            timed_steps(min(overlap, n), timed)   # next window's first steps, on the plan in force
+            loads = g.measure_end()          # waits for the snapshot only
+            m, nmig, lam = g.rebalance(wl.strategy, wl.threshold)
+            wins.append((loads, nmig, lam))
+            timed_steps(n - min(overlap, n), timed)
+            done += n
+        return wins
+
+    run(warmup, False)
+    if warmup > 0:
+        g.measure("work")
+        g.rebalance(wl.strategy, wl.threshold)
     g.measure("work")                        # fresh window and busy counters
+    st0 = g.stats()
     torch.cuda.synchronize()
-    # timing events are created before the timed region (creating one is a runtime call)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(-(-steps // R))]
-    wins = []
     t0 = time.perf_counter()
-    done = 0
-    while done < steps:
-        n = min(R, steps - done)
-        wins.append(window(n, evs[len(wins)]))
-        done += n
+    wins = run(steps, True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kernel_s = sum(e[0].elapsed_time(e[1]) for e in evs) / 1e3
@@ -112,7 +130,10 @@ def run_balanced(Grid, wl, steps, warmup, R, params, torch):
     g.measure("work")
     st = g.stats()
     g.close()
-    return dict(wall=wall, kernel_s=kernel_s, wins=wins, busy=busy, stats=st)
+    nw = max(len(wins), 1)
+    host = dict(balance_us_per_window=(st["host_balance_us"] - st0["host_balance_us"]) / nw,
+                plan_us_per_window=(st["host_plan_us"] - st0["host_plan_us"]) / nw)
+    return dict(wall=wall, kernel_s=kernel_s, wins=wins, busy=busy, stats=st, host=host)
 
 
 def run_plain(Grid, wl, steps, warmup, params, torch, mode="plain"):
@@ -184,7 +205,7 @@ def run_ablation(Grid, wl, steps, warmup, R, params, torch, balance_host):
     import numpy as np
 
     S = wl.nslots
-    p = {k: v for k, v in params.items() if k not in ("nqueues", "steal", "wg_per_queue")}
+    p = {k: v for k, v in params.items() if k not in ("nqueues", "steal", "wg_per_queue", "item_grid")}
     block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)],
                      dtype=np.int32)
     out = {}
@@ -240,6 +261,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ablation", action="store_true", help="skip the block-vs-balanced map leg")
     ap.add_argument("--ablation-steps", type=int, default=50)
+    ap.add_argument("--overlap-steps", type=int, default=2,
+                    help="steps enqueued after each window before the host waits for its loads")
     ap.add_argument("--no-tuned", action="store_true", help="library default launch shape")
     ap.add_argument("--set", action="append", default=[], help="launch override key=value")
     ap.add_argument("--calibration-copy", type=float, default=0.0, metavar="MIB",
@@ -272,7 +295,7 @@ def main(argv=None) -> int:
     params["precision"] = args.precision
     log(f"bench: {wl.name} steps={args.steps} warmup={args.warmup} R={R} S={S} params={params}")
 
-    bal = run_balanced(Grid, wl, args.steps, args.warmup, R, params, torch)
+    bal = run_balanced(Grid, wl, args.steps, args.warmup, R, params, torch, args.overlap_steps)
     log(f"balanced: {bal['wall'] * 1e3 / args.steps:.4f} ms/step, "
         f"kernel {bal['kernel_s'] * 1e6 / args.steps:.2f} us/step")
     plain = plain_graph = None
@@ -300,9 +323,10 @@ def main(argv=None) -> int:
 
     block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)])
     loads = [w for w, _, _ in bal["wins"]]
-    lam_bal = float(np.mean([lam[0] for _, _, lam in bal["wins"]]))   # map in force vs its window
-    lam_plain = float(np.mean([lam_of(w, block) for w in loads]))
-    lam_star = float(np.mean([max(1.0, S * w.max() / w.sum()) for w in loads]))
+    # map in force vs its window (None when the timed steps hold no rebalance point)
+    lam_bal = float(np.mean([lam[0] for _, _, lam in bal["wins"]])) if loads else None
+    lam_plain = float(np.mean([lam_of(w, block) for w in loads])) if loads else None
+    lam_star = float(np.mean([max(1.0, S * w.max() / w.sum()) for w in loads])) if loads else None
     busy = bal["busy"]
     lam_wg = float(busy.max() / busy.mean()) if busy.mean() > 0 else None
 
@@ -330,6 +354,7 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "chunks": wl.nchunks,
                    "slots": S, "rebalance_every": R, "strategy": wl.strategy,
+                   "overlap_steps": args.overlap_steps,
                    "launch": {k: v for k, v in params.items() if k != "precision"},
                    "workgroups": st["nwg"], "tiles": st["ntiles"], "items": st["nitems"]},
         "balanced_vs_plain": {
@@ -344,7 +369,8 @@ def main(argv=None) -> int:
             "lambda_wg": lam_wg,
             "queues": st["nqueues"],
             "map_inert": st["nqueues"] == 1,
-            "migrations_per_rebalance": float(np.mean([n for _, n, _ in bal["wins"]])),
+            "migrations_per_rebalance": float(np.mean([n for _, n, _ in bal["wins"]])) if bal["wins"] else None,
+            "host_us_per_window": bal["host"],
         },
         "ablation_map_only": ablation,
         "roofline": {
@@ -355,7 +381,7 @@ def main(argv=None) -> int:
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.workload, args.precision,
                                         {k: v for k, v in params.items() if k != "precision"}),
-            "kernel": "k_persistent",
+            "kernel": "k_items" if params.get("item_grid") else "k_persistent",
             "bytes_per_launch": bytes_per_step,
             "us_per_launch_events": kernel_step_s * 1e6,
         },

@@ -183,6 +183,9 @@ typedef struct {
     double clock_hz;         /* rate of the in-kernel wall clock              */
     double last_checksum;    /* FP64 sum of all cells after the last step     */
     int64_t measured_steps;  /* steps accumulated in the current load window  */
+    double host_balance_us;  /* host time of every rebalance's balancer, summed */
+    double host_plan_us;     /* host time of every plan (items, queue order,
+                                staging, the upload launch), summed           */
 } lb_stats_t;
 
 /* Fill *cfg with the defaults listed in lb_config. */
@@ -231,6 +234,17 @@ int lb_step(lb_ctx *ctx, int32_t nsteps, int32_t mode);
  * kept for lb_rebalance.  Errors: LB_E_INVAL (ctx NULL, unknown source),
  * LB_E_HIP (the synchronisation or the copy failed). */
 int lb_measure(lb_ctx *ctx, int32_t source, double *loads_out, int32_t reset);
+
+/* lb_measure in two halves, so that the host can enqueue more steps before it
+ * waits (Section V's measured window, collected without draining the GPU).
+ * lb_measure_begin enqueues the window's snapshot behind the steps enqueued so
+ * far (and, when reset != 0, starts a new window, counting the steps enqueued
+ * after it) and returns at once; lb_measure_end waits for that snapshot only
+ * (steps enqueued after it keep running) and returns it as lb_measure does.
+ * Errors: LB_E_STATE (begin while a snapshot is pending, end without one),
+ * LB_E_INVAL, LB_E_HIP. */
+int lb_measure_begin(lb_ctx *ctx, int32_t source, int32_t reset);
+int lb_measure_end(lb_ctx *ctx, double *loads_out);
 
 /* Compute a new chunk->slot map with strategy LB_GREEDY (Section VI,
  * Experiment A: heaviest chunk to the least loaded slot), LB_REFINE (move

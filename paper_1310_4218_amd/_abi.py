@@ -65,6 +65,7 @@ class LbStats(C.Structure):
         ("tile_x", C.c_int32), ("tile_y", C.c_int32),
         ("clock_hz", C.c_double), ("last_checksum", C.c_double),
         ("measured_steps", C.c_int64),
+        ("host_balance_us", C.c_double), ("host_plan_us", C.c_double),
     ]
 
 
@@ -76,6 +77,8 @@ SIGNATURES = {
                                C.POINTER(C.c_void_p)]),
     "lb_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "lb_measure": (C.c_int, [C.c_void_p, C.c_int32, DBLP, C.c_int32]),
+    "lb_measure_begin": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "lb_measure_end": (C.c_int, [C.c_void_p, DBLP]),
     "lb_rebalance": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, DBLP, I32P, I32P, DBLP]),
     "lb_set_map": (C.c_int, [C.c_void_p, I32P, DBLP]),
     "lb_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, DBLP]),

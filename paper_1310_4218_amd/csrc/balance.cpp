@@ -11,8 +11,10 @@
 //     chunk id order, limit = (W / S) * threshold.
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
 #include <functional>
 #include <queue>
+#include <set>
 #include <utility>
 #include <vector>
 
@@ -22,11 +24,46 @@ namespace lbgrid {
 
 namespace {
 
+// Chunks by load descending, equal loads in ascending ids.  Loads are
+// non-negative doubles, whose bit patterns order like their values, so a
+// stable least-significant-digit radix sort of the complemented bits (from id
+// order) gives exactly that order; bytes that are the same in every key need
+// no pass.
 std::vector<int32_t> heavy_first(const double* w, int32_t C) {
     std::vector<int32_t> ord(static_cast<size_t>(C));
     for (int32_t c = 0; c < C; ++c) ord[c] = c;
-    std::stable_sort(ord.begin(), ord.end(), [w](int32_t a, int32_t b) { return w[a] > w[b]; });
-    return ord;  // stable: equal loads keep ascending ids
+    if (C < 64) {
+        std::sort(ord.begin(), ord.end(),
+                  [w](int32_t a, int32_t b) { return w[a] > w[b] || (w[a] == w[b] && a < b); });
+        return ord;
+    }
+    std::vector<uint64_t> key(static_cast<size_t>(C));
+    for (int32_t c = 0; c < C; ++c) {
+        const double v = w[c] == 0.0 ? 0.0 : w[c];   // -0.0 orders as +0.0
+        uint64_t bits;
+        std::memcpy(&bits, &v, sizeof(bits));
+        key[c] = ~bits;
+    }
+    std::vector<int32_t> tmp(static_cast<size_t>(C));
+    int32_t count[256];
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        std::memset(count, 0, sizeof(count));
+        for (int32_t c = 0; c < C; ++c) ++count[(key[c] >> shift) & 0xff];
+        if (count[(key[0] >> shift) & 0xff] == C) continue;
+        int32_t run = 0;
+        for (int d = 0; d < 256; ++d) {
+            const int32_t x = count[d];
+            count[d] = run;
+            run += x;
+        }
+        for (int32_t i = 0; i < C; ++i) {
+            const int32_t c = ord[i];
+            tmp[count[(key[c] >> shift) & 0xff]++] = c;
+        }
+        ord.swap(tmp);
+    }
+    return ord;
 }
 
 // GreedyLB: heaviest chunk first onto the least loaded slot.  A binary heap of
@@ -65,13 +102,21 @@ void refine(const double* w, const int32_t* old_map, int32_t C, int32_t S, doubl
     std::vector<std::vector<int32_t>> on(static_cast<size_t>(S));
     for (int32_t c : heavy_first(w, C)) on[map[c]].push_back(c);
 
-    std::vector<char> given_up(static_cast<size_t>(S), 0);
-    for (;;) {
-        int32_t p = -1;
-        for (int32_t s = 0; s < S; ++s)
-            if (!given_up[s] && (p < 0 || L[s] > L[p])) p = s;
-        if (p < 0 || !(L[p] > limit)) break;
-        int32_t q = static_cast<int32_t>(std::min_element(L.begin(), L.end()) - L.begin());
+    // Slots ordered two ways, updated as loads change: `hi` holds the slots not
+    // given up, most loaded first (lowest index on ties), `lo` every slot, least
+    // loaded first (lowest index on ties); the same choices as linear scans.
+    auto more = [&L](int32_t a, int32_t b) { return L[a] > L[b] || (L[a] == L[b] && a < b); };
+    auto less = [&L](int32_t a, int32_t b) { return L[a] < L[b] || (L[a] == L[b] && a < b); };
+    std::set<int32_t, decltype(more)> hi(more);
+    std::set<int32_t, decltype(less)> lo(less);
+    for (int32_t s = 0; s < S; ++s) {
+        hi.insert(s);
+        lo.insert(s);
+    }
+    while (!hi.empty()) {
+        const int32_t p = *hi.begin();
+        if (!(L[p] > limit)) break;
+        const int32_t q = *lo.begin();
         // L[q] + w[c] is non-increasing along the heavy-first list: binary search
         // for the first chunk whose move keeps q at or under the limit.
         std::vector<int32_t>& lp = on[p];
@@ -79,14 +124,22 @@ void refine(const double* w, const int32_t* old_map, int32_t C, int32_t S, doubl
         auto it = std::partition_point(lp.begin(), lp.end(),
                                        [&](int32_t c) { return !(Lq + w[c] <= limit); });
         if (it == lp.end() || p == q) {
-            given_up[p] = 1;
+            hi.erase(p);   // given up
             continue;
         }
         int32_t c = *it;
         lp.erase(it);
         map[c] = q;
+        hi.erase(p);
+        lo.erase(p);
+        lo.erase(q);
+        const bool q_active = hi.erase(q) > 0;
         L[p] -= w[c];
         L[q] += w[c];
+        hi.insert(p);
+        lo.insert(p);
+        lo.insert(q);
+        if (q_active) hi.insert(q);
         std::vector<int32_t>& lq = on[q];
         auto pos = std::lower_bound(lq.begin(), lq.end(), c, [w](int32_t a, int32_t b) {
             return w[a] > w[b] || (w[a] == w[b] && a < b);

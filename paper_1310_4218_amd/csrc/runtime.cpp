@@ -10,6 +10,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -306,6 +307,7 @@ struct lb_ctx {
     std::vector<int32_t> tile_off;    // C + 1: tiles of chunk c
     std::vector<int32_t> row_base;    // per tile: its first row in the visit counters
     std::vector<int32_t> pos_rank;    // per tile: its rank by (first row, first column)
+    std::vector<int32_t> pos_order;   // tiles by that rank
     std::vector<ItemDesc> items;      // the installed plan, chunk order
     std::vector<int32_t> item_off;    // C + 1
     int64_t plan_version = 0;
@@ -325,6 +327,10 @@ struct lb_ctx {
     hipEvent_t upload_done = nullptr;
     hipEvent_t measured_ev = nullptr;   // end of the last measurement's copy
     bool upload_pending = false;
+    bool measure_pending = false;     // lb_measure_begin enqueued a snapshot not yet collected
+    int64_t pending_steps = 0;        // steps in that snapshot's window
+    double host_balance_us = 0.0;     // all rebalances: the balancer
+    double host_plan_us = 0.0;        // all plans: items, queue order, staging, upload launch
     hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
     hipGraphExec_t g_pers1 = nullptr; // one persistent step
     // one workgroup per item: graph_steps steps and one step, per parity of the
@@ -333,6 +339,7 @@ struct lb_ctx {
     hipGraphExec_t g_items1[2] = {nullptr, nullptr};
     int64_t items_graph_version[2] = {-1, -1};
     bool wstate_stale = false;        // only the shared per-parity step state is current
+    bool items_stale = false;         // the chunk-order item tables on the device are not the plan's
     hipGraphExec_t g_plain = nullptr; // one plain step
     std::string err;
 };
@@ -395,7 +402,11 @@ void build_tiles(lb_ctx* x) {
                    (static_cast<uint64_t>(x->tiles[4 * i + 0]) << 32) | static_cast<uint32_t>(i);
         std::sort(k.begin(), k.end());
         x->pos_rank.resize(static_cast<size_t>(p.ntiles));
-        for (int32_t r = 0; r < p.ntiles; ++r) x->pos_rank[k[r] & 0xffffffffu] = r;
+        x->pos_order.resize(static_cast<size_t>(p.ntiles));
+        for (int32_t r = 0; r < p.ntiles; ++r) {
+            x->pos_rank[k[r] & 0xffffffffu] = r;
+            x->pos_order[r] = static_cast<int32_t>(k[r] & 0xffffffffu);
+        }
     }
     x->row_base.resize(static_cast<size_t>(p.ntiles));
     int32_t r = 0;
@@ -428,6 +439,7 @@ std::vector<int32_t> build_cost_table(const lb_config& c, int32_t r2cut) {
 //    a tile one after another (first row first).
 int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     const Plan& p = x->plan;
+    const auto t_plan = std::chrono::steady_clock::now();
 
     // Cost of every tile: its measured work when the plan follows a measurement;
     // else its chunk's cost times its share of the chunk's area; without costs,
@@ -486,14 +498,30 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
         return (static_cast<uint64_t>(~bits & 0x7fffffffu) << 32) | static_cast<uint32_t>(t);
     };
     std::vector<uint64_t> order(static_cast<size_t>(p.ntiles));
-    {
+    if (x->cfg.queue_order >= 1) {
+        // the keys in sorted order without sorting the position keys: per queue,
+        // its hot tiles (sorted), then its other tiles as they come in position order
+        auto queue_of = [&](int32_t t) { return x->map[x->tiles[4 * t + 3]] % p.Q; };
+        std::vector<int32_t> hot_end(qoff.begin(), qoff.end() - 1), tail(static_cast<size_t>(p.Q));
+        for (int32_t t = 0; t < p.ntiles; ++t) {
+            const uint64_t key = key_of(t);
+            if (!(key >> 63)) order[hot_end[queue_of(t)]++] = key;
+        }
+        for (int32_t q = 0; q < p.Q; ++q) tail[q] = hot_end[q];
+        for (int32_t r = 0; r < p.ntiles; ++r) {
+            const int32_t t = x->pos_order[r];
+            const uint64_t key = key_of(t);
+            if (key >> 63) order[tail[queue_of(t)]++] = key;
+        }
+        for (int32_t q = 0; q < p.Q; ++q) sort_keys(order.data() + qoff[q], hot_end[q] - qoff[q]);
+    } else {
         std::vector<int32_t> fill(qoff.begin(), qoff.end() - 1);
         for (int32_t c = 0; c < p.C; ++c) {
             int32_t& at = fill[x->map[c] % p.Q];
             for (int32_t t = x->tile_off[c]; t < x->tile_off[c + 1]; ++t) order[at++] = key_of(t);
         }
+        for (int32_t q = 0; q < p.Q; ++q) sort_keys(order.data() + qoff[q], qoff[q + 1] - qoff[q]);
     }
-    for (int32_t q = 0; q < p.Q; ++q) sort_keys(order.data() + qoff[q], qoff[q + 1] - qoff[q]);
     auto tile_at = [&](int32_t i) { return static_cast<int32_t>(order[i] & 0xffffffffu); };
     // Tail: in every queue, the cheapest tiles whose pieces make up the final
     // round of its G workgroups (the last G items in this order) are cut
@@ -557,8 +585,15 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     int32_t* st_off = reinterpret_cast<int32_t*>(x->staging + p.st_off);
     int32_t* st_seg = reinterpret_cast<int32_t*>(x->staging + p.st_seg);
     int32_t* st_n = reinterpret_cast<int32_t*>(x->staging + p.st_n);
-    std::memcpy(st_items, x->items.data(), sizeof(ItemDesc) * n);
-    std::memcpy(st_off, x->item_off.data(), sizeof(int32_t) * x->item_off.size());
+    // A context whose balanced steps launch one workgroup per item reads the
+    // chunk-order tables only in plain steps: they go up on the first plain step
+    // after a change (upload_items), not with every plan.
+    const bool chunk_tables = !p.IG;
+    x->items_stale = p.IG;
+    if (chunk_tables) {
+        std::memcpy(st_items, x->items.data(), sizeof(ItemDesc) * n);
+        std::memcpy(st_off, x->item_off.data(), sizeof(int32_t) * x->item_off.size());
+    }
     int32_t k = 0;
     for (int32_t q = 0; q < p.Q; ++q) {
         st_seg[q] = k;
@@ -580,7 +615,7 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     // queues, else w mod and div Q
     const int per_xcd = a.xcd_queues ? p.Q / 8 : 1;
     int qh = 0, qr = 0;
-    for (int32_t w = 0; w < p.nwg; ++w) {
+    for (int32_t w = 0; w < (p.IG ? 0 : p.nwg); ++w) {   // (not read by a launch per item)
         int home, rank;
         if (a.xcd_queues) {
             home = (w & 7) + 8 * qh;
@@ -609,17 +644,44 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
                          reinterpret_cast<uint32_t*>(x->ws + off), static_cast<uint32_t>(bytes / 4)};
     };
     const GatherSeg segs[] = {
-        seg(p.st_items, p.off_items, sizeof(ItemDesc) * n),
         seg(p.st_queue, p.off_queue, sizeof(ItemDesc) * n),
-        seg(p.st_first, p.off_first, sizeof(ItemDesc) * 2 * p.nwg),
-        seg(p.st_off, p.off_itemoff, sizeof(int32_t) * (p.C + 1)),
         seg(p.st_seg, p.off_seg, sizeof(int32_t) * (p.Q + 1)),
         seg(p.st_n, p.off_ctrl + offsetof(Ctrl, nitems), sizeof(int32_t)),
+        seg(p.st_items, p.off_items, sizeof(ItemDesc) * n),
+        seg(p.st_off, p.off_itemoff, sizeof(int32_t) * (p.C + 1)),
+        seg(p.st_first, p.off_first, sizeof(ItemDesc) * 2 * p.nwg),
     };
-    LAUNCH_TRY(x, launch_gather(segs, static_cast<int>(sizeof(segs) / sizeof(segs[0])), x->stream));
+    const int nsegs = chunk_tables ? static_cast<int>(sizeof(segs) / sizeof(segs[0])) : 3;
+    LAUNCH_TRY(x, launch_gather(segs, nsegs, x->stream));
     HIP_TRY(x, hipEventRecord(x->upload_done, x->stream));
     x->upload_pending = true;
     ++x->plan_version;
+    x->host_plan_us += std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t_plan).count();
+    return LB_OK;
+}
+
+// The chunk-order item tables of the installed plan, which plain steps read;
+// deferred by upload_plan for contexts that launch one workgroup per item.
+int upload_items(lb_ctx* x) {
+    const Plan& p = x->plan;
+    if (x->upload_pending) {
+        HIP_TRY(x, hipEventSynchronize(x->upload_done));
+        x->upload_pending = false;
+    }
+    const int32_t n = static_cast<int32_t>(x->items.size());
+    std::memcpy(x->staging + p.st_items, x->items.data(), sizeof(ItemDesc) * n);
+    std::memcpy(x->staging + p.st_off, x->item_off.data(), sizeof(int32_t) * x->item_off.size());
+    const GatherSeg segs[] = {
+        GatherSeg{reinterpret_cast<const uint32_t*>(x->staging_dev + p.st_items),
+                  reinterpret_cast<uint32_t*>(x->ws + p.off_items),
+                  static_cast<uint32_t>(sizeof(ItemDesc) * n / 4)},
+        GatherSeg{reinterpret_cast<const uint32_t*>(x->staging_dev + p.st_off),
+                  reinterpret_cast<uint32_t*>(x->ws + p.off_itemoff), static_cast<uint32_t>(p.C + 1)},
+    };
+    LAUNCH_TRY(x, launch_gather(segs, 2, x->stream));
+    HIP_TRY(x, hipEventRecord(x->upload_done, x->stream));
+    x->upload_pending = true;
+    x->items_stale = false;
     return LB_OK;
 }
 
@@ -935,6 +997,8 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
         x->wstate_stale = false;
     }
     if (!own_state) x->wstate_stale = true;
+    if ((mode == LB_PLAIN || mode == LB_PLAIN_GRAPH) && x->items_stale && (rc = upload_items(x)) != LB_OK)
+        return rc;
     switch (mode) {
         case LB_PERSISTENT: {
             const int R = x->cfg.graph_steps;
@@ -1019,17 +1083,16 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
     return LB_OK;
 }
 
-int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
+int lb_measure_begin(lb_ctx* x, int32_t source, int32_t reset) {
     if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
     if (x->broken) return fail(&x->err, LB_E_STATE, "context unusable: an earlier step failed part-way");
     if (source != LB_LOAD_WORK && source != LB_LOAD_TIME) return fail(&x->err, LB_E_INVAL, "unknown load source");
+    if (x->measure_pending) return fail(&x->err, LB_E_STATE, "a measurement is pending: call lb_measure_end first");
     const Plan& p = x->plan;
     HIP_TRY(x, hipSetDevice(x->device));
     // one kernel moves the loads and tile work into pinned staging after the
     // window's last step and clears the counters (work, time, busy and tile
-    // counters are adjacent in the workspace); one synchronisation covers it
-    double* st = reinterpret_cast<double*>(x->staging + p.st_loads);
-    double* stt = reinterpret_cast<double*>(x->staging + p.st_tiles);
+    // counters are adjacent in the workspace); an event marks its end
     LAUNCH_TRY(x, launch_measure_out(
                       reinterpret_cast<double*>(x->ws + (source == LB_LOAD_WORK ? p.off_lw : p.off_lt)),
                       reinterpret_cast<double*>(x->ws + p.off_tw), p.C, p.ntiles,
@@ -1037,15 +1100,40 @@ int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
                       reinterpret_cast<double*>(const_cast<char*>(x->staging_dev) + p.st_tiles),
                       x->ws + p.off_lw, reset ? p.off_busy + sizeof(double) * p.nwg - p.off_lw : 0,
                       x->stream));
-    int rc = sync_spin(x, x->measured_ev);
-    if (rc != LB_OK) return rc;
-    x->measured.assign(st, st + p.C);
-    x->tile_measured.assign(stt, stt + p.ntiles);
-    x->tile_steps = x->window_steps;
-    x->have_measured = true;
-    if (loads_out) std::memcpy(loads_out, x->measured.data(), sizeof(double) * p.C);
+    HIP_TRY(x, hipEventRecord(x->measured_ev, x->stream));
+    x->measure_pending = true;
+    x->pending_steps = x->window_steps;
     if (reset) x->window_steps = 0;
     return LB_OK;
+}
+
+int lb_measure_end(lb_ctx* x, double* loads_out) {
+    if (!x) return fail(nullptr, LB_E_INVAL, "ctx is NULL");
+    if (!x->measure_pending) return fail(&x->err, LB_E_STATE, "no measurement begun");
+    const Plan& p = x->plan;
+    HIP_TRY(x, hipSetDevice(x->device));
+    if (forced_failure("sync")) return fail(&x->err, LB_E_HIP, "forced failure at sync (LBGRID_FAIL_AT)");
+    // poll the event: the measurement sits on the critical path between two
+    // windows, and polling returns sooner than a blocking wait on this system
+    hipError_t q;
+    while ((q = hipEventQuery(x->measured_ev)) == hipErrorNotReady) {
+    }
+    x->measure_pending = false;
+    if (q != hipSuccess) return fail(&x->err, LB_E_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    const double* st = reinterpret_cast<const double*>(x->staging + p.st_loads);
+    const double* stt = reinterpret_cast<const double*>(x->staging + p.st_tiles);
+    x->measured.assign(st, st + p.C);
+    x->tile_measured.assign(stt, stt + p.ntiles);
+    x->tile_steps = x->pending_steps;
+    x->have_measured = true;
+    if (loads_out) std::memcpy(loads_out, x->measured.data(), sizeof(double) * p.C);
+    return LB_OK;
+}
+
+int lb_measure(lb_ctx* x, int32_t source, double* loads_out, int32_t reset) {
+    int rc = lb_measure_begin(x, source, reset);
+    if (rc != LB_OK) return rc;
+    return lb_measure_end(x, loads_out);
 }
 
 int lb_balance_host(const double* loads, const int32_t* old_map, int32_t C, int32_t S,
@@ -1084,9 +1172,12 @@ int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* lo
     const Plan& p = x->plan;
     const double* w = loads;
     if (!w) {
+        if (x->measure_pending)
+            return fail(&x->err, LB_E_STATE, "a measurement is pending: call lb_measure_end first");
         if (!x->have_measured) return fail(&x->err, LB_E_STATE, "no measured loads: call lb_measure first or pass loads");
         w = x->measured.data();
     }
+    const auto t_bal = std::chrono::steady_clock::now();
     std::vector<int32_t> nm(static_cast<size_t>(p.C));
     int32_t mig = 0;
     if (strategy == LB_GREEDY_THEN_REFINESWAP)  // Experiment C: Greedy first, RefineSwap later
@@ -1096,6 +1187,8 @@ int lb_rebalance(lb_ctx* x, int32_t strategy, double threshold, const double* lo
         x->err = g_err;
         return rc;
     }
+    x->host_balance_us +=
+        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t_bal).count();
     const double before = imbalance(w, x->map.data(), p.C, p.S);
     const double after = imbalance(w, nm.data(), p.C, p.S);
     x->map = nm;
@@ -1163,6 +1256,8 @@ int lb_stats(lb_ctx* x, lb_stats_t* out) {
     out->ntiles = p.ntiles;
     out->nrows = p.nrows;
     out->nitems = static_cast<int32_t>(x->items.size());
+    out->host_balance_us = x->host_balance_us;
+    out->host_plan_us = x->host_plan_us;
     out->nslots = p.S;
     out->nqueues = p.Q;
     out->nwg = p.nwg;

@@ -111,6 +111,17 @@ class Grid:
         check(_abi.lib().lb_measure(h, _abi.SOURCES[source], self._loads_out, int(reset)), h)
         return np.frombuffer(self._loads_out, dtype=np.float64, count=self.nchunks).copy()
 
+    def measure_begin(self, source: str = "work", reset: bool = True) -> None:
+        """Enqueue the window's load snapshot without waiting (see measure_end)."""
+        h = self.handle
+        check(_abi.lib().lb_measure_begin(h, _abi.SOURCES[source], int(reset)), h)
+
+    def measure_end(self) -> np.ndarray:
+        """Wait for the snapshot of measure_begin only and return its loads."""
+        h = self.handle
+        check(_abi.lib().lb_measure_end(h, self._loads_out), h)
+        return np.frombuffer(self._loads_out, dtype=np.float64, count=self.nchunks).copy()
+
     def rebalance(self, strategy: str = "greedy", threshold: float = 1.05,
                   loads: Optional[np.ndarray] = None):
         """Returns (map, nmigrated, (lambda_before, lambda_after))."""

@@ -1,7 +1,7 @@
-"""HBM traffic of the persistent step kernel from two rocprofv3 counter runs.
+"""HBM traffic of the step kernel (k_items or k_persistent) from two rocprofv3 counter runs.
 
     rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- python3 bench.py --workload W \
-        --no-cpu --no-plain --steps S --warmup 10 --calibration-copy 512
+        --no-cpu --no-plain --no-ablation --steps S --warmup 10 --calibration-copy 512
     rocprofv3 --pmc WRITE_SIZE -d OUT/write -o run -- python3 bench.py ...same...
     python -m paper_1310_4218_amd.traffic --fetch OUT/fetch --write OUT/write --workload W \
         --copy-mib 512
@@ -130,7 +130,9 @@ def main(argv=None) -> int:
 
     fetch = read_counter(args.fetch, "FETCH_SIZE")
     write = read_counter(args.write, "WRITE_SIZE")
-    kf, kw = pick(fetch, ["k_persistent"]), pick(write, ["k_persistent"])
+    # the step kernel: one workgroup per item if the run launched it, else the persistent one
+    kname = "k_items" if pick(fetch, ["k_items"]) else "k_persistent"
+    kf, kw = pick(fetch, [kname]), pick(write, [kname])
     cf, cw = pick(fetch, ["copy"]), pick(write, ["copy"])
     if not kf or not kw or not cf or not cw:
         print("missing dispatches: persistent", len(kf), len(kw), "copy", len(cf), len(cw),
@@ -144,7 +146,7 @@ def main(argv=None) -> int:
     mean = lambda v: sum(v) / len(v)
     fetch_b = mean(kf) * 1024.0 * f_scale
     write_b = mean(kw) * 1024.0 * w_scale
-    out = dict(workload=args.workload, kernel="k_persistent",
+    out = dict(workload=args.workload, kernel=kname,
                dispatches=dict(fetch=len(kf), write=len(kw)),
                fetch_bytes_per_launch=fetch_b, write_bytes_per_launch=write_b,
                hbm_bytes_per_launch=fetch_b + write_b,

@@ -179,6 +179,36 @@ def test_item_grid_mixed_launch_forms_fp64():
     g.close()
 
 
+def test_measure_in_two_halves():
+    """lb_measure_begin snapshots the window behind the steps enqueued so far; steps
+    enqueued before lb_measure_end belong to the next window; the rebalance waits for the
+    snapshot to be collected."""
+    from paper_1310_4218_amd._abi import LbError, LB_E_STATE
+    wl = mk(40, 36, 12, 4, 3, hot=((5, 4, 1, 2),), split="dirichlet", steps=6, nslots=5)
+    ref, work, _, _ = oracle.run(wl, nsteps=6)
+    g = Grid(wl, precision="fp64", march=2, item_grid=1)
+    with pytest.raises(LbError) as e:
+        g.measure_end()
+    assert e.value.code == LB_E_STATE
+    g.step(3, "persistent_eager")
+    g.measure_begin("work")
+    with pytest.raises(LbError) as e:
+        g.measure_begin("work")
+    assert e.value.code == LB_E_STATE
+    g.step(2, "persistent_eager")            # the next window's first steps
+    with pytest.raises(LbError) as e:
+        g.rebalance("greedy")
+    assert e.value.code == LB_E_STATE
+    w3 = g.measure_end()
+    g.rebalance("greedy")
+    g.step(1, "persistent_eager")
+    w6 = g.measure("work")
+    np.testing.assert_array_equal(w3, work[:3].sum(axis=0))
+    np.testing.assert_array_equal(w6, work[3:].sum(axis=0))
+    np.testing.assert_array_equal(gpu_fields(g), ref)
+    g.close()
+
+
 def test_map_does_not_change_fields():
     wl = mk(48, 40, 8, 6, 5, split="dirichlet", steps=4, nslots=7)
     _, base, _ = run_gpu(wl, 4, "plain")
