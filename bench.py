@@ -198,10 +198,11 @@ def cpu_baseline(wl, budget_s):
 
 
 def run_ablation(Grid, wl, steps, warmup, R, params, torch, balance_host):
-    """The balancer's own effect: one queue per slot, no stealing, the same kernel and
-    items, the static block map against the balancer's map.  Every window both legs
-    measure their loads and re-install their map with those costs (lb_set_map), the
-    balanced leg after remapping with the workload's strategy from the map in force."""
+    """The balancer's own effect: one queue per slot, no stealing, the persistent kernel
+    with the same items, the static block map against the balancer's map (and against
+    GreedyLB at every rebalance point when the workload's strategy is another one).
+    Every window each leg measures its loads and re-installs its map with those costs
+    (lb_set_map), the balanced legs after remapping from the map in force."""
     import numpy as np
 
     S = wl.nslots
@@ -209,7 +210,8 @@ def run_ablation(Grid, wl, steps, warmup, R, params, torch, balance_host):
     block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)],
                      dtype=np.int32)
     out = {}
-    for leg in ("block", "balanced"):
+    legs = ("block", "balanced") + (("greedy",) if wl.strategy != "greedy" else ())
+    for leg in legs:
         g = Grid(wl, graph_steps=R, nqueues=S, steal=0, wg_per_queue=0, **p)
         m = block.copy()
         first = True
@@ -231,8 +233,8 @@ def run_ablation(Grid, wl, steps, warmup, R, params, torch, balance_host):
                 L = np.bincount(m, weights=w, minlength=S)
                 lam_in_force.append(float(L.max() / (w.sum() / S)))
                 lam_star.append(float(max(1.0, S * w.max() / w.sum())))
-            if leg == "balanced":
-                strat = wl.strategy
+            if leg != "block":
+                strat = wl.strategy if leg == "balanced" else "greedy"
                 if strat == "greedy_then_refineswap":
                     strat = "greedy" if first else "refineswap"
                 m, _ = balance_host(w, S, strat, None if (first and strat == "greedy") else m,

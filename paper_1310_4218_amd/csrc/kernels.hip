@@ -126,16 +126,18 @@ __device__ __forceinline__ double vstep(double eps, double q, double b) {
 }
 
 // k upward sweeps over a column whose nz levels are spread over NQ consecutive
-// lanes (V levels per lane, NQ a power of two <= 64), as a systolic wavefront:
-// at time step tau lane j applies sweep tau - j to its levels, taking the
-// level below from lane j - 1's result of the previous time step.  Level 0 is
-// the fixed bottom boundary.  k + NQ - 1 time steps instead of k * nz.
+// lanes of one wave (V levels per lane), as a systolic wavefront: at time step
+// tau lane j applies sweep tau - j to its levels, taking the level below from
+// lane j - 1's result of the previous time step.  Level 0 is the fixed bottom
+// boundary.  k + NQ - 1 time steps instead of k * nz.
 template <typename T, int V>
 __device__ __forceinline__ void physics_vertical(T eps, int k, int tzq, int NQ, T (&q)[V]) {
     T top = q[V - 1];
+    const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
+    const int from = tzq == 0 ? lane : lane - 1;    // the lane holding the levels below
     const int steps = k > 0 ? k + NQ - 1 : 0;
     for (int tau = 0; tau < steps; ++tau) {
-        const T below = __shfl_up(top, 1, NQ);
+        const T below = __shfl(top, from, kWave);
         const int sweep = tau - tzq;
         if (sweep >= 0 && sweep < k) {
 #pragma unroll
@@ -586,15 +588,30 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
     const int nz = a.nz, nx = a.nx, ny = a.ny;
     const int NQ = nz / V;
     const int TX = a.tile_x;
-    const int BS = a.block;                   // (TX + 2) * NQ == blockDim.x
-    const int tcol = threadIdx.x / NQ;
-    const int tzq = threadIdx.x - tcol * NQ;
+    const int BS = a.block;                   // == blockDim.x
+    // Thread -> (column tcol, lane tzq of the column).  Dense: consecutive NQ
+    // threads per column, (TX + 2) * NQ threads.  With col_per_wave > 0 (the
+    // vertical physics when NQ does not divide 64) every wave holds
+    // col_per_wave whole columns in its first lanes and leaves the rest idle,
+    // so that a column's lanes never straddle two waves.
+    int tcol, tzq;
+    bool lane_used = true;
+    if (a.col_per_wave > 0) {
+        const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
+        const int cw = lane / NQ;
+        tcol = (static_cast<int>(threadIdx.x) >> 6) * a.col_per_wave + cw;
+        tzq = lane - cw * NQ;
+        lane_used = cw < a.col_per_wave;
+    } else {
+        tcol = threadIdx.x / NQ;
+        tzq = threadIdx.x - tcol * NQ;
+    }
     const int zoff = tzq * V;
     const int x0 = d.x0, y0 = d.y0;
     const int w = d.wh & 0xffff;
     const int h = d.wh >> 16;
-    const bool streams = tcol < w + 2;        // this thread loads grid column x0 - 1 + tcol
-    const bool active = tcol >= 1 && tcol <= w;
+    const bool streams = lane_used && tcol < w + 2;   // this thread loads grid column x0 - 1 + tcol
+    const bool active = lane_used && tcol >= 1 && tcol <= w;
     int gx = x0 - 1 + tcol;
     gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
     const uint32_t rowbytes = static_cast<uint32_t>(nx) * static_cast<uint32_t>(nz) * sizeof(T);

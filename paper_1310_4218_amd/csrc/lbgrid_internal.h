@@ -93,6 +93,8 @@ struct DevArgs {
                                // copies exceed the 256 MB last-level cache)
     uint32_t field_bytes;      // bytes of one field (< 4 GiB with the march pipeline)
     int32_t vertical;          // 1: column physics with the vertical dependency
+    int32_t col_per_wave;      // > 0: the march puts this many whole columns in each wave
+                               // (vertical physics with nz / V not dividing 64); 0: dense
     int32_t r2cut;
     int32_t kmin;
     int32_t alpha;

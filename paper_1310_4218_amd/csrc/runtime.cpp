@@ -39,6 +39,7 @@ int fail(std::string* where, int code, const std::string& msg) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+
 // Everything lb_query / lb_grid_init derive from a configuration.
 struct Plan {
     int32_t nx = 0, ny = 0, nz = 0, nfields = 1, px = 0, py = 0, C = 0, S = 0, Q = 0, G = 0, nwg = 0;
@@ -48,6 +49,7 @@ struct Plan {
     int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
     int32_t M = 0;          // rows in flight of the column march; 0 = another pipeline
     bool IG = false;        // balanced steps launch one workgroup per item
+    int32_t CPW = 0;        // march: whole columns per wave (vertical physics, NQ not dividing 64)
     int32_t B = 0;          // rows per direct global->LDS batch; 0 = register pipeline
     int32_t ring = 4;       // LDS ring rows
     int32_t r2cut = 0;
@@ -179,9 +181,14 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (!strictly_increasing(p.ys, p.ny)) return bad("ysplit must rise strictly from 0 to ny");
 
     const int NQ = p.nz / p.vec;
-    if (c->physics == LB_PHYS_VERTICAL && (NQ > 64 || 64 % NQ != 0))
+    // The vertical physics passes levels up a column's lanes inside one wave:
+    // with NQ dividing 64 every layout keeps columns whole in a wave; otherwise
+    // only the march lays out whole columns per wave (64 / NQ per wave).
+    if (c->physics == LB_PHYS_VERTICAL && (NQ > 64 || (64 % NQ != 0 && c->march == 0)))
         return fail(err, LB_E_UNSUPPORTED,
-                    "vertical physics needs nz / V to divide 64 (V = 4, 2 or 1 by divisibility of nz)");
+                    "vertical physics needs nz / V <= 64 lanes per column, and the column-march "
+                    "pipeline (march > 0) unless nz / V divides 64 (V = 4, 2 or 1 by divisibility of nz)");
+    p.CPW = (c->physics == LB_PHYS_VERTICAL && c->march > 0 && 64 % NQ != 0) ? 64 / NQ : 0;
     // pipeline: the column march (M rows in flight), direct global->LDS batches of B
     // rows (V = 4 only) or the register path
     p.M = c->march;
@@ -205,7 +212,10 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
                sizeof(int32_t) * static_cast<size_t>(tx) * p.TY * (p.B > 0 ? 2 : 1);
     };
     // threads per workgroup: TX columns (the march adds the two halo columns) of NQ threads
-    auto threads_for = [&](int tx) { return (p.M > 0 ? tx + 2 : tx) * NQ; };
+    auto threads_for = [&](int tx) {
+        if (p.CPW > 0) return (tx + 2 + p.CPW - 1) / p.CPW * 64;   // whole columns per wave
+        return (p.M > 0 ? tx + 2 : tx) * NQ;
+    };
     const int most = p.M > 0 ? (p.prec == LB_FP64 ? kMaxBlockDeep : kMaxBlock)
                              : (p.B == 0 && (p.RD >= 4 || p.prec == LB_FP64)) ? kMaxBlockDeep : kMaxBlock;
     if (c->tile_x > 0) {
@@ -727,21 +737,6 @@ int sync(lb_ctx* x) {
     return LB_OK;
 }
 
-// Wait for everything enqueued on the stream so far by polling an event
-// recorded behind it.  The measurement sits on the critical path between two
-// windows; polling returns about 10 us sooner per window than
-// hipStreamSynchronize on this system.
-int sync_spin(lb_ctx* x, hipEvent_t ev) {
-    HIP_TRY(x, hipSetDevice(x->device));
-    if (forced_failure("sync")) return fail(&x->err, LB_E_HIP, "forced failure at sync (LBGRID_FAIL_AT)");
-    HIP_TRY(x, hipEventRecord(ev, x->stream));
-    hipError_t q;
-    while ((q = hipEventQuery(ev)) == hipErrorNotReady) {
-    }
-    if (q != hipSuccess) return fail(&x->err, LB_E_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
-    return LB_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -903,6 +898,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.stream_store = 2 * P.field_bytes > (size_t{256} << 20) ? 1 : 0;
     a.field_bytes = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(P.ncells) * P.elem, 0xFFFFFFFFull));
     a.vertical = cfg->physics == LB_PHYS_VERTICAL ? 1 : 0;
+    a.col_per_wave = P.CPW;
     if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
         int ncu = 0;
         if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device)) != hipSuccess)

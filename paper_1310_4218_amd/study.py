@@ -16,7 +16,9 @@ For each source the chunks are mapped with GreedyLB, and the map is judged
   (b) by the measured time of persistent steps run with that map and with
       stealing off, so that the map alone decides the balance.
 Also reported: Spearman rank correlation of each time source with the work
-loads.  Prints one JSON line per window.
+loads.  Prints one JSON line per window; with --out, writes them all as one JSON
+record (the workload, slots, and per window the rank correlations and, per
+source, the map's imbalance and timed step).
 """
 from __future__ import annotations
 
@@ -41,7 +43,9 @@ def lam(w, m, S) -> float:
     return float(L.max() / (w.sum() / S))
 
 
-def run(wl, windows=3, R=None, steps_timed=10, log=print):
+def run(wl, windows=3, R=None, steps_timed=10, log=print, keep_loads=False):
+    """One result per window (see the module docstring); with keep_loads the three
+    load vectors and the three maps are kept in it as well (not in the JSON lines)."""
     import torch
 
     from ._abi import balance_host
@@ -90,6 +94,9 @@ def run(wl, windows=3, R=None, steps_timed=10, log=print):
             g.close()
             res["maps"][name] = dict(lambda_work=lam(w, m, S), us_per_step=us)
         log(json.dumps(res))
+        if keep_loads:
+            res["loads"] = {"work": w, "time/plain": t_plain, "time/persist": t_pers}
+            res["map_arrays"] = maps
         out.append(res)
         t += R
     return out
@@ -100,13 +107,19 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="moving")
     ap.add_argument("--windows", type=int, default=3)
     ap.add_argument("--slots", type=int, default=None, help="override S")
+    ap.add_argument("--out", default=None, help="write the record to this JSON file")
     args = ap.parse_args(argv)
     from . import workloads as W
 
     wl = W.get(args.workload)
     if args.slots:
         wl = wl.replace(nslots=args.slots)
-    run(wl, args.windows, log=lambda s: print(s, flush=True))
+    res = run(wl, args.windows, log=lambda s: print(s, flush=True))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(dict(workload=wl.name, slots=wl.nslots, chunks=wl.nchunks,
+                           command="python -m paper_1310_4218_amd.study " + " ".join(argv or sys.argv[1:]),
+                           windows=res), f, indent=1)
     return 0
 
 

@@ -163,6 +163,17 @@ def large() -> Workload:
                nslots=256, rebalance_every=10, strategy="refine", threshold=1.05)
 
 
+def fields(nf: int) -> Workload:
+    """The paper's per-step volume: 1024x1024x40 with nf fields (50 in Experiments B and C,
+    100 in Table I and Experiment A), 16 chunks as 1 x 16 bands along y (the 1D
+    decomposition of Fig. 5), 4 slots (P = 4), one wide hotspot (sigma 256, k in 1..3, so
+    about twice the physics inside it) moving along y by 16 cells/step, 40 steps, Greedy
+    on the first rebalance and RefineSwap after (Experiment C) every 10 steps."""
+    return _mk(f"fields{nf}-1024x1024x40-c16", 1024, 1024, 40, 1, 16, [(512, 0, 0, 16)], 256.0, 1, 3,
+               40, seed=1006, nslots=4, rebalance_every=10, strategy="greedy_then_refineswap",
+               nfields=nf)
+
+
 PRESETS = {
     "small": small,
     "moving": moving,
@@ -172,6 +183,8 @@ PRESETS = {
     "sweep1024": lambda: sweep(1024),
     "precision": precision,
     "large": large,
+    "fields50": lambda: fields(50),
+    "fields100": lambda: fields(100),
 }
 
 
