@@ -309,6 +309,24 @@ int lb_checksums(lb_ctx *ctx, double *out, int32_t n, int32_t *got);
 int lb_balance_host(const double *loads, const int32_t *old_map, int32_t C, int32_t S,
                     int32_t strategy, double threshold, int32_t *map_out, int32_t *nmigrated);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the FP64 checksum of
+ * lb_fields (the same two-pass, fixed-order sum, so the same bits) of a field
+ * the caller owns, without a context.  Its partial sums live in a fixed
+ * 8 KiB device array of the library (1024 doubles per GPU, held until the
+ * process ends), whose address is resolved at lb_grid_init or at this call's
+ * first use on a device; the call itself allocates nothing and does not
+ * synchronize.  field: ncells values (float for LB_FP32 and LB_FP32_KAHAN,
+ * double for LB_FP64) in device memory; sum_out: one double the device can
+ * write (device memory or mapped pinned host memory), written when the work
+ * enqueued on hip_stream (NULL: the null stream) of the current device
+ * completes.  Calls that overlap on one GPU share the array and race: order
+ * them on one stream.  Errors: LB_E_INVAL (NULL pointers, unknown precision,
+ * ncells < 0 or > LB_NOALLOC_MAX_CELLS), LB_E_HIP (launch failure). */
+#define LB_NOALLOC_MAX_CELLS ((int64_t)1 << 40)
+int lb_field_sum_noalloc(const void *field, int32_t precision, int64_t ncells, double *sum_out,
+                         void *hip_stream);
+
 /* Release the context (synchronizes its stream first).  NULL is a no-op. */
 void lb_destroy(lb_ctx *ctx);
 

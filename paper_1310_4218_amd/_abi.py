@@ -78,6 +78,7 @@ SIGNATURES = {
     "lb_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "lb_measure": (C.c_int, [C.c_void_p, C.c_int32, DBLP, C.c_int32]),
     "lb_measure_begin": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "lb_field_sum_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p]),
     "lb_measure_end": (C.c_int, [C.c_void_p, DBLP]),
     "lb_rebalance": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, DBLP, I32P, I32P, DBLP]),
     "lb_set_map": (C.c_int, [C.c_void_p, I32P, DBLP]),

@@ -32,7 +32,9 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
+#include "lbgrid.h"
 #include "lbgrid_internal.h"
 
 namespace lbgrid {
@@ -1521,3 +1523,63 @@ int launch_field_sum(const void* q, int prec, int64_t n, double* partial, double
 }
 
 }  // namespace lbgrid
+
+// ---- the checksum for callers that cannot allocate ----------------------------------
+// The two-pass FP64 field sum of lb_fields (k_sum1 over kSumBlocks blocks, then
+// k_sum2) with its partials in this file-scope array instead of a context's
+// workspace.  Each GPU the library runs on holds its own copy until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress gives
+// for the current device (the array's name is a host-side stand-in).
+static __device__ __align__(256) double scratch[lbgrid::kSumBlocks];
+
+namespace lbgrid {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int prepare_static_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return static_cast<int>(hipErrorInvalidDevice);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return static_cast<int>(hipSuccess);
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return static_cast<int>(e);
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return static_cast<int>(e);
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return static_cast<int>(e);
+    g_scratch_dev[device] = static_cast<double*>(p);
+    return static_cast<int>(hipSuccess);
+}
+
+}  // namespace lbgrid
+
+extern "C" int lb_field_sum_noalloc(const void* field, int32_t precision, int64_t ncells, double* sum_out,
+                                    void* hip_stream) {
+    using namespace lbgrid;
+    if (!sum_out) return report_error(LB_E_INVAL, "sum_out is NULL");
+    if (!field && ncells > 0) return report_error(LB_E_INVAL, "field is NULL");
+    if (precision != LB_FP32 && precision != LB_FP32_KAHAN && precision != LB_FP64)
+        return report_error(LB_E_INVAL, "unknown precision");
+    if (ncells < 0 || ncells > LB_NOALLOC_MAX_CELLS)
+        return report_error(LB_E_INVAL, "ncells must be in [0, LB_NOALLOC_MAX_CELLS]");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return report_error(LB_E_HIP, hipGetErrorString(e));
+    if ((e = static_cast<hipError_t>(prepare_static_scratch(dev))) != hipSuccess)
+        return report_error(LB_E_HIP, hipGetErrorString(e));
+    double* part = g_scratch_dev[dev];
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (precision == LB_FP64)
+        hipLaunchKernelGGL(k_sum1<double>, dim3(kSumBlocks), dim3(256), 0, s, static_cast<const double*>(field),
+                           ncells, part);
+    else
+        hipLaunchKernelGGL(k_sum1<float>, dim3(kSumBlocks), dim3(256), 0, s, static_cast<const float*>(field),
+                           ncells, part);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, part, kSumBlocks, sum_out);
+    if ((e = hipGetLastError()) != hipSuccess) return report_error(LB_E_HIP, hipGetErrorString(e));
+    return LB_OK;
+}

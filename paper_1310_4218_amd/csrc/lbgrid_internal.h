@@ -139,6 +139,12 @@ int  launch_field_sum(const void* q, int prec, int64_t n, double* partial, doubl
 int  launch_reset_control(const DevArgs& a, void* stream);
 int  persistent_occupancy(const DevArgs& a, int prec, int vec, int block, size_t lds);  // per CU
 
+// The allocation-free checksum entry point's scratch (kernels.hip): resolve the
+// device address of `device`'s copy (with that device current); 0 or a hipError_t.
+int  prepare_static_scratch(int device);
+// Record msg as the calling thread's last error and return code (runtime.cpp).
+int  report_error(int code, const char* msg);
+
 // Host balancer (balance.cpp).  Return 0 on success, -1 on bad arguments.
 enum Strategy { kGreedy = 0, kRefine = 1, kRefineSwap = 2 };
 int balance(const double* w, const int32_t* old_map, int32_t C, int32_t S, int strategy,

@@ -39,6 +39,12 @@ int fail(std::string* where, int code, const std::string& msg) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+}  // namespace
+
+// The thread's last error, for entry points defined with the kernels.
+int lbgrid::report_error(int code, const char* msg) { return fail(nullptr, code, msg); }
+
+namespace {
 
 // Everything lb_query / lb_grid_init derive from a configuration.
 struct Plan {
@@ -861,6 +867,10 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     }
     build_tiles(x);
     const std::vector<int32_t> ktab = build_cost_table(*cfg, P.r2cut);
+    // resolve this device's copy of the allocation-free entry point's scratch now,
+    // at set-up, rather than on that entry point's first call
+    if ((e = static_cast<hipError_t>(prepare_static_scratch(x->device))) != hipSuccess)
+        return hip_bail(e, "hipGetSymbolAddress(scratch)");
 
     DevArgs& a = x->args;
     a.field0 = x->field[0];
