@@ -112,7 +112,13 @@ def run_balanced(Grid, wl, steps, warmup, R, params, torch, overlap=2):
             done += n
         return wins
 
-    run(warmup, False)
+    # the first step runs the unmeasured initial plan; remap after it so that the rest
+    # of the warm-up (and a profile of the whole run) runs measured plans
+    if warmup > 1:
+        g.step(1, MODE)
+        g.measure("work")
+        g.rebalance(wl.strategy, wl.threshold)
+    run(warmup - 1 if warmup > 1 else warmup, False)
     if warmup > 0:
         g.measure("work")
         g.rebalance(wl.strategy, wl.threshold)
@@ -329,8 +335,10 @@ def main(argv=None) -> int:
     lam_bal = float(np.mean([lam[0] for _, _, lam in bal["wins"]])) if loads else None
     lam_plain = float(np.mean([lam_of(w, block) for w in loads])) if loads else None
     lam_star = float(np.mean([max(1.0, S * w.max() / w.sum()) for w in loads])) if loads else None
+    # per persistent workgroup, or per compute unit that ran items (one workgroup per item)
     busy = bal["busy"]
-    lam_wg = float(busy.max() / busy.mean()) if busy.mean() > 0 else None
+    busy = busy[busy > 0] if params.get("item_grid") else busy
+    lam_wg = float(busy.max() / busy.mean()) if busy.size and busy.mean() > 0 else None
 
     elem = 8 if args.precision == "fp64" else 4
     bytes_per_step = 2 * elem * cells
@@ -369,6 +377,8 @@ def main(argv=None) -> int:
             "lambda_plain": lam_plain,
             "lambda_star": lam_star,
             "lambda_wg": lam_wg,
+            "lambda_wg_over": "compute units" if params.get("item_grid") else "workgroups",
+            "busy_units": int(busy.size),
             "queues": st["nqueues"],
             "map_inert": st["nqueues"] == 1,
             "migrations_per_rebalance": float(np.mean([n for _, n, _ in bal["wins"]])) if bal["wins"] else None,

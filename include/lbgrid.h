@@ -146,11 +146,14 @@ typedef struct {
                                 overrides stage_rows.  0 = off (default)      */
     int32_t queue_order;     /* order of the items of a queue: 0 = longest
                                 first (cost per item descending); 1 = the hot
-                                items (cost per item above twice the queue's
-                                mean) longest first, then all others by their
+                                items (cost per item above hot_cut percent of
+                                the mean) longest first, then all others by their
                                 position (first row, then first column), so
                                 that workgroups running at the same time read
                                 neighbouring rows (default 0)                 */
+    int32_t hot_cut;         /* queue_order 1: an item is hot when its cost
+                                exceeds hot_cut percent of the mean cost per
+                                item (200)                                    */
     int32_t item_grid;       /* 1: a balanced step (LB_PERSISTENT,
                                 LB_PERSISTENT_EAGER) launches one workgroup
                                 per item, in queue order, and the hardware
@@ -186,6 +189,11 @@ typedef struct {
     double host_balance_us;  /* host time of every rebalance's balancer, summed */
     double host_plan_us;     /* host time of every plan (items, queue order,
                                 staging, the upload launch), summed           */
+    int32_t busy_slots;      /* entries lb_wg_busy returns: nwg (persistent
+                                workgroups), or 2048 per-compute-unit slots
+                                when balanced steps launch one workgroup per
+                                item (keyed by XCD and CU id; unused ones 0)  */
+    int32_t pad0;
 } lb_stats_t;
 
 /* Fill *cfg with the defaults listed in lb_config. */

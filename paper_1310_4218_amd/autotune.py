@@ -31,6 +31,7 @@ SPACE = {
     "item_grid": [0, 1],          # 1: one workgroup per item (needs march > 0)
     "march": [0, 2, 4, 8],        # > 0: column-march pipeline, rows in flight
     "queue_order": [0, 1],        # 1: hot items longest first, the rest by position
+    "hot_cut": [200, 120, 150, 300, 500],   # queue_order 1: hot above this % of the mean
     "tile_x": [8, 16, 32, 64],
     "tile_y": [2, 4, 8, 12, 16, 24, 32],
     "nqueues": [1, 8, 32, 256],

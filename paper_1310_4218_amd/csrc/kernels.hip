@@ -1159,7 +1159,15 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items(DevArgs 
     const ItemDesc d = uni(a.queue[blockIdx.x]);
     const uint64_t t_start = wall_clock64();
     const ItemOut o = process_item_march<T, V, KAHAN, D>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
-    record_item(a, partials, d, o, static_cast<double>(wall_clock64() - t_start));
+    const double ticks = static_cast<double>(wall_clock64() - t_start);
+    record_item(a, partials, d, o, ticks);
+    if (threadIdx.x == 0) {
+        // busy time per compute unit: the hardware's XCD id and the CU/array/engine
+        // bits 8..15 of its HW_ID register name the unit this workgroup ran on
+        const unsigned hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);      // HW_ID, 32 bits
+        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20);     // XCC_ID, 4 bits
+        unsafeAtomicAdd(&a.wg_busy[((xcc & 7u) << 8) | ((hw >> 8) & 0xffu)], ticks);
+    }
 }
 
 template <typename T, int V, int KAHAN, int PIPE>

@@ -15,6 +15,9 @@ constexpr int kRingRows = 4;        // LDS row ring of the tile kernel
 constexpr int kMaxBlock = 1024;
 constexpr int kMaxBlockDeep = 512;  // workgroup limit of the 4- and 8-row register pipelines
 constexpr size_t kMaxLds = 160 * 1024;  // gfx950: 160 KiB of LDS per CU
+// Busy-time slots of a launch of one workgroup per item: one per compute unit,
+// keyed by XCD (3 bits) and the unit's shader-engine/array/CU id (8 bits).
+constexpr int kCuSlots = 2048;
 
 // Device control block (first bytes of the workspace).
 struct Ctrl {
@@ -73,7 +76,8 @@ struct DevArgs {
     double* partials;          // 2 x part_stride, by step parity: per item, the sum of its
                                // outputs in that step
     double* hist;              // kHistLen per-step sums
-    double* wg_busy;           // nwg
+    double* wg_busy;           // nwg (persistent: per workgroup), or kCuSlots (one workgroup
+                               // per item: per compute unit)
     uint64_t* wg_timeline;     // 4 per workgroup, last persistent launch: start, first item,
                                // end of last item, exit (wall-clock ticks)
     int32_t* visits;           // per tile row: times it was computed

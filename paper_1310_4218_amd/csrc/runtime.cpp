@@ -138,6 +138,10 @@ int64_t cost_table_cut(double sigma, int32_t kmin, int32_t kmax) {
     return static_cast<int64_t>(std::ceil(2.0 * sigma * sigma * std::log(static_cast<double>(span)))) + 1;
 }
 
+// Busy-time counters a launch fills: one per workgroup of the persistent
+// launch, or one per compute unit with one workgroup per item.
+int32_t busy_slots(const Plan& p) { return p.IG ? kCuSlots : p.nwg; }
+
 int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (!c) return fail(err, LB_E_INVAL, "config is NULL");
     auto bad = [&](const char* what) { return fail(err, LB_E_INVAL, std::string("invalid config: ") + what); };
@@ -167,6 +171,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->march != 0 && c->march != 2 && c->march != 4 && c->march != 8)
         return bad("march must be 0 (off), 2, 4 or 8 rows in flight");
     if (c->queue_order != 0 && c->queue_order != 1) return bad("queue_order must be 0 or 1");
+    if (c->hot_cut < 0) return bad("hot_cut must be >= 0");
     if (c->item_grid != 0 && c->item_grid != 1) return bad("item_grid must be 0 or 1");
     if (c->item_grid == 1 && c->march == 0) return bad("item_grid needs the column-march pipeline (march > 0)");
 
@@ -282,7 +287,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_lw = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_lt = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_tw = take(sizeof(double) * static_cast<size_t>(p.ntiles));
-    p.off_busy = take(sizeof(double) * static_cast<size_t>(p.nwg_cap));
+    p.off_busy = take(sizeof(double) * static_cast<size_t>(std::max(p.nwg_cap, kCuSlots)));
     p.off_part = take(sizeof(double) * 2 * static_cast<size_t>(p.nrows));
     p.off_hist = take(sizeof(double) * kHistLen);
     p.off_tl = take(sizeof(uint64_t) * 4 * static_cast<size_t>(p.nwg_cap));
@@ -493,15 +498,15 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
     // The sort key is one integer: the complemented bits of the cost per piece
     // as a float (non-negative floats order like their bit patterns), then the
     // tile index; plain integer sorting keeps a plan of ~10^4 tiles cheap.
-    // With queue_order 1 only the hot tiles (cost per piece above twice the
-    // mean over all pieces) are keyed by cost; every other tile sorts after
+    // With queue_order 1 only the hot tiles (cost per piece above hot_cut
+    // percent of the mean over all pieces) are keyed by cost; every other tile sorts after
     // them by its position rank (first row, then first column).  Keys: cost
     // keys have the top bit clear, position keys set.
     double hot_cut = 0.0;
     if (x->cfg.queue_order >= 1) {
         int64_t npieces = 0;
         for (int32_t t = 0; t < p.ntiles; ++t) npieces += pieces[t];
-        hot_cut = npieces > 0 ? 2.0 * W / static_cast<double>(npieces) : 0.0;
+        hot_cut = npieces > 0 ? (x->cfg.hot_cut / 100.0) * W / static_cast<double>(npieces) : 0.0;
     }
     auto key_of = [&](int32_t t) -> uint64_t {
         const double pp = tcost[t] / pieces[t];
@@ -781,6 +786,7 @@ void lb_config_default(lb_config* c) {
     c->item_alpha = -1;
     c->march = 0;
     c->queue_order = 0;
+    c->hot_cut = 200;
     c->item_grid = 0;
 }
 
@@ -1104,7 +1110,7 @@ int lb_measure_begin(lb_ctx* x, int32_t source, int32_t reset) {
                       reinterpret_cast<double*>(x->ws + p.off_tw), p.C, p.ntiles,
                       reinterpret_cast<double*>(const_cast<char*>(x->staging_dev) + p.st_loads),
                       reinterpret_cast<double*>(const_cast<char*>(x->staging_dev) + p.st_tiles),
-                      x->ws + p.off_lw, reset ? p.off_busy + sizeof(double) * p.nwg - p.off_lw : 0,
+                      x->ws + p.off_lw, reset ? p.off_busy + sizeof(double) * busy_slots(p) - p.off_lw : 0,
                       x->stream));
     HIP_TRY(x, hipEventRecord(x->measured_ev, x->stream));
     x->measure_pending = true;
@@ -1263,6 +1269,7 @@ int lb_stats(lb_ctx* x, lb_stats_t* out) {
     out->nrows = p.nrows;
     out->nitems = static_cast<int32_t>(x->items.size());
     out->host_balance_us = x->host_balance_us;
+    out->busy_slots = busy_slots(x->plan);
     out->host_plan_us = x->host_plan_us;
     out->nslots = p.S;
     out->nqueues = p.Q;
@@ -1281,10 +1288,11 @@ int lb_stats(lb_ctx* x, lb_stats_t* out) {
 
 int lb_wg_busy(lb_ctx* x, double* out, int32_t n) {
     if (!x || !out) return fail(x ? &x->err : nullptr, LB_E_INVAL, "ctx and out are required");
-    if (n < x->plan.nwg) return fail(&x->err, LB_E_NOMEM, "out too small for nwg entries");
+    const int32_t slots = busy_slots(x->plan);
+    if (n < slots) return fail(&x->err, LB_E_NOMEM, "out too small for the busy slots (lb_stats busy_slots)");
     int rc = sync(x);
     if (rc != LB_OK) return rc;
-    HIP_TRY(x, hipMemcpy(out, x->ws + x->plan.off_busy, sizeof(double) * x->plan.nwg, hipMemcpyDeviceToHost));
+    HIP_TRY(x, hipMemcpy(out, x->ws + x->plan.off_busy, sizeof(double) * slots, hipMemcpyDeviceToHost));
     return LB_OK;
 }
 

@@ -159,8 +159,11 @@ class Grid:
         return {k: getattr(s, k) for k, _ in _abi.LbStats._fields_}
 
     def wg_busy(self) -> np.ndarray:
-        out = np.empty(self.nwg, dtype=np.float64)
-        check(_abi.lib().lb_wg_busy(self.handle, ptr(out, C.c_double), self.nwg), self.handle)
+        """Busy ticks per persistent workgroup, or per compute unit (unused slots 0) when
+        balanced steps launch one workgroup per item."""
+        n = self.stats()["busy_slots"]
+        out = np.empty(n, dtype=np.float64)
+        check(_abi.lib().lb_wg_busy(self.handle, ptr(out, C.c_double), n), self.handle)
         return out
 
     def wg_timeline(self) -> np.ndarray:

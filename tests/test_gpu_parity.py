@@ -398,6 +398,23 @@ def test_time_loads_and_busy_counters():
     assert np.all(g.measure("work") == 0)
 
 
+def test_busy_per_compute_unit_with_one_workgroup_per_item():
+    """With one workgroup per item the busy ticks are kept per compute unit: their sum is
+    the chunks' time loads, at most 2048 slots are used, several units took part, and a
+    measurement with reset clears them."""
+    wl = W.moving()
+    g = Grid(wl, march=4, item_grid=1, tile_x=8, tile_y=8)
+    g.step(3, "persistent_eager")
+    t = g.measure("time", reset=False)
+    busy = g.wg_busy()
+    assert busy.size == g.stats()["busy_slots"] == 2048
+    assert busy.sum() == pytest.approx(t.sum(), rel=1e-9)
+    assert (busy > 0).sum() >= 8
+    g.measure("work", reset=True)
+    assert np.all(g.wg_busy() == 0)
+    g.close()
+
+
 def test_failed_launch_keeps_the_step_count(monkeypatch):
     """A launch refused part-way through lb_step (forced from the host): the steps fully
     enqueued before it count, the context keeps working from there, and its fields
