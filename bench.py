@@ -265,6 +265,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="large")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_kahan", "fp64"])
+    ap.add_argument("--vertical", action="store_true",
+                    help="column physics with the vertical dependency (Figs. 1 and 4)")
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
@@ -298,6 +300,8 @@ def main(argv=None) -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     wl = W.get(args.workload)
+    if args.vertical:
+        wl = wl.replace(vertical=1)
     R = wl.rebalance_every or 10
     S = wl.nslots
     params = {} if args.no_tuned else tuned_params(args.workload, args.precision)
@@ -374,6 +378,7 @@ def main(argv=None) -> int:
         "dtype": {"fp32": "f32", "fp32_kahan": "f32", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "chunks": wl.nchunks,
+                   "physics": "vertical" if args.vertical else "pointwise",
                    "slots": S, "rebalance_every": R, "strategy": wl.strategy,
                    "overlap_steps": args.overlap_steps,
                    "launch": {k: v for k, v in params.items() if k != "precision"},

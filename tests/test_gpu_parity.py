@@ -721,6 +721,28 @@ def test_vertical_physics_fp64_bit_exact(nz):
         g.close()
 
 
+@pytest.mark.parametrize("name", ["precision", "large"])
+def test_vertical_physics_full_size_fp64_windows(name):
+    """The vertical column physics at full size in the benchmark's launch configuration
+    (the 2048x2048x80 grid has 20 lanes per column, laid out as whole columns per wave):
+    after 6 steps with a rebalance, FP64 sampled windows equal the windowed oracle's and
+    the loads equal the oracle's."""
+    wl = W.get(name).replace(vertical=1)
+    T = 6
+    g = Grid(wl, **_launch(name, "fp64"))
+    g.step(3)
+    np.testing.assert_array_equal(g.measure("work"), _oracle_loads(wl, 0, 3))
+    g.rebalance(wl.strategy, wl.threshold)
+    g.step(T - 3)
+    q = g.field(device="cuda")
+    for ox, oy in _windows(wl, T):
+        q0 = oracle.init_window(wl, ox - T, oy - T, 16 + 2 * T, 16 + 2 * T)
+        ref = oracle.run_window(wl, q0, ox - T, oy - T, T)[T:T + 16, T:T + 16]
+        np.testing.assert_array_equal(_gpu_window(q, ox, oy, 16), ref)
+    assert np.all(g.visits() == T)
+    g.close()
+
+
 def test_vertical_physics_fp32_and_launch_forms():
     wl = W.small().replace(vertical=1)
     ref, _, _, _ = oracle.run(wl)
