@@ -78,6 +78,8 @@ def test_query_rejects_bad_config(lib, field, value, msg):
     (dict(stage_rows=-1, precision=2, tile_x=80), "FP64"),
     (dict(march=3), "march must be"), (dict(march=2, nz=6), "march needs nz divisible by 4"),
     (dict(march=4, precision=2, tile_x=70), "FP64 march"), (dict(march=8, tile_x=200), "1024 threads"),
+    (dict(item_grid=1), "item_grid needs the column-march"), (dict(item_grid=2, march=2), "item_grid must be"),
+    (dict(queue_order=3), "queue_order must be"), (dict(hot_cut=-1), "hot_cut"),
 ])
 def test_query_rejects_bad_pipeline(lib, over, msg):
     """Register pipeline depths are 2, 4 or 8 rows; the deep ones need V = 4 and
@@ -90,6 +92,28 @@ def test_query_rejects_bad_pipeline(lib, over, msg):
     b = _abi.LbBuffers()
     assert lib.lb_query(C.byref(cfg), C.byref(b)) == _abi.LB_E_INVAL
     assert msg in lib.lb_last_error(None).decode()
+
+
+def test_vertical_layouts(lib):
+    """Vertical physics passes levels up a column's lanes inside one wave: columns of lanes
+    that do not divide 64 (80 levels: 20 lanes) need the march, which lays out whole columns
+    per wave; more than 64 lanes per column are never possible."""
+    from paper_1310_4218_amd._abi import LbError
+    wl = W.small().replace(nz=80, vertical=1)
+    with pytest.raises(LbError) as e:
+        _abi.query(_abi.config_from_workload(wl)[0])
+    assert e.value.code == _abi.LB_E_UNSUPPORTED
+    _abi.query(_abi.config_from_workload(wl, march=2)[0])
+    _abi.query(_abi.config_from_workload(wl, march=4, item_grid=1, tile_x=14)[0])
+    with pytest.raises(LbError) as e:
+        _abi.query(_abi.config_from_workload(W.small().replace(nz=260, vertical=1), march=2)[0])
+    assert e.value.code == _abi.LB_E_UNSUPPORTED
+
+
+def test_measure_halves_need_a_context(lib):
+    assert lib.lb_measure_begin(None, 0, 1) == _abi.LB_E_INVAL
+    assert lib.lb_measure_end(None, None) == _abi.LB_E_INVAL
+    assert lib.lb_field_sum_noalloc(None, 0, 10, None, None) == _abi.LB_E_INVAL
 
 
 def test_query_accepts_pipeline_depths(lib):
