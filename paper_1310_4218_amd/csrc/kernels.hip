@@ -740,6 +740,7 @@ __device__ __forceinline__ StepInfo step_info(const WgState& w) {
 __device__ __forceinline__ WgState next_state(const DevArgs& a, const WgState& w) {
     WgState n;
     n.step = w.step + 1;
+    n.cur = w.cur ^ 1;
 #pragma unroll
     for (int h = 0; h < kMaxHot; ++h) {
         int x = w.hx[h] + a.hvx[h], y = w.hy[h] + a.hvy[h];
@@ -815,6 +816,13 @@ __device__ void settle_partials(const DevArgs& a, int p, double* red, int bs) {
         a.hist[(ps - 1) % kHistLen] = total;
         a.ctrl->pend_step[p] = 0;
     }
+}
+
+// Sum every pending partials buffer other than those in `mine` (bit b: buffer
+// b), which the calling launch writes.  Run by one whole workgroup.
+__device__ void settle_others(const DevArgs& a, unsigned mine, double* red, int bs) {
+    for (int b = 0; b < kStepSlots; ++b)
+        if (!((mine >> b) & 1u)) settle_partials(a, b, red, bs);
 }
 
 // ---- claiming work ----------------------------------------------------------------
@@ -920,12 +928,13 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_persistent(DevArgs a) {
     const int wg = blockIdx.x;
     const WgState ws = a.wstate[wg];            // equal in every workgroup of the launch
     const uint64_t step = ws.step;
-    const int par = static_cast<int>(step & 1);
+    const int par = static_cast<int>(step & 1);  // claim-counter set
+    const int b = static_cast<int>(step & 3);    // partials buffer and state slot
     const StepInfo si = step_info(ws);
-    const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
-    T* dst = static_cast<T*>(par ? a.field0 : a.field1);
+    const T* src = static_cast<const T*>(ws.cur ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(ws.cur ? a.field0 : a.field1);
     int* heads = a.heads + par * a.nqueues;
-    double* partials = a.partials + static_cast<int64_t>(par) * a.part_stride;
+    double* partials = a.partials + static_cast<int64_t>(b) * a.part_stride;
     const int home = home_queue(a, wg);
     const int hbeg = a.seg[home];
     const int hn = a.seg[home + 1] - hbeg;
@@ -941,12 +950,12 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_persistent(DevArgs a) {
         int* other = a.heads + (par ^ 1) * a.nqueues;
         for (int q = threadIdx.x; q < a.nqueues; q += a.block) other[q] = a.head0;
         if (threadIdx.x == 0) {
-            a.ctrl->pend_n[par] = a.ctrl->nitems;
-            a.ctrl->pend_step[par] = step + 1;
-            a.pstate[par ^ 1] = next_state(a, ws);
+            a.ctrl->pend_n[b] = a.ctrl->nitems;
+            a.ctrl->pend_step[b] = step + 1;
+            a.pstate[(b + 1) & 3] = next_state(a, ws);
         }
     }
-    if (wg == a.nwg - 1) settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
+    if (wg == a.nwg - 1) settle_others(a, 1u << b, red, a.block);   // earlier steps' sums
     __syncthreads();
     Carry carry{0, 0, 0};
     bool drained = false;    // (thread 0) the home queue has nothing left to claim
@@ -1037,7 +1046,9 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
     const int wg = blockIdx.x;
     const WgState ws = a.wstate[wg];            // equal in every workgroup of the launch
     const uint64_t step = ws.step;
-    const int par = uni(static_cast<int>(step & 1));
+    const int par = uni(static_cast<int>(step & 1));   // claim-counter set
+    const int b = uni(static_cast<int>(step & 3));     // partials buffer and state slot
+    const int cur = uni(ws.cur);
     StepInfo si;
     si.step = step;
 #pragma unroll
@@ -1045,10 +1056,10 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
         si.hcx[h] = uni(ws.hx[h]);
         si.hcy[h] = uni(ws.hy[h]);
     }
-    const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
-    T* dst = static_cast<T*>(par ? a.field0 : a.field1);
+    const T* src = static_cast<const T*>(cur ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(cur ? a.field0 : a.field1);
     int* heads = a.heads + par * a.nqueues;
-    double* partials = a.partials + static_cast<int64_t>(par) * a.part_stride;
+    double* partials = a.partials + static_cast<int64_t>(b) * a.part_stride;
     const int home = uni(home_queue(a, wg));
     const int hbeg = uni(a.seg[home]);
     const int hn = uni(a.seg[home + 1]) - hbeg;
@@ -1061,12 +1072,12 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
         int* other = a.heads + (par ^ 1) * a.nqueues;
         for (int q = threadIdx.x; q < a.nqueues; q += a.block) other[q] = a.head0;
         if (threadIdx.x == 0) {
-            a.ctrl->pend_n[par] = a.ctrl->nitems;
-            a.ctrl->pend_step[par] = step + 1;
-            a.pstate[par ^ 1] = next_state(a, ws);
+            a.ctrl->pend_n[b] = a.ctrl->nitems;
+            a.ctrl->pend_step[b] = step + 1;
+            a.pstate[(b + 1) & 3] = next_state(a, ws);
         }
     }
-    if (wg == a.nwg - 1) settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
+    if (wg == a.nwg - 1) settle_others(a, 1u << b, red, a.block);   // earlier steps' sums
     __syncthreads();                             // every thread has read its step state
     if (threadIdx.x == 0) a.wstate[wg] = next_state(a, ws);
     double busy = 0.0;
@@ -1126,16 +1137,17 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
 // workgroup as soon as a previous one leaves the CU.  This keeps every CU full
 // of short-lived workgroups whose loads cover neighbouring rows, the pattern a
 // streaming kernel reads HBM fastest with, and needs no claims.  The step
-// state is the shared copy of the step's parity (par, from the host); workgroup
-// 0 writes the next step's copy, resets the other claim-counter set, records
-// this step's pending checksum and sums the previous step's.
+// state is the shared copy in the step's slot (its number mod 4, from the
+// host); workgroup 0 writes the next step's copy, resets the claim-counter set
+// of the next step, records this step's pending checksum and sums the earlier
+// steps'.
 template <typename T, int V, int KAHAN, int D>
-__global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items(DevArgs a, int par) {
+__global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items(DevArgs a, int slot) {
     extern __shared__ __align__(32) unsigned char smem[];
     T* lds = reinterpret_cast<T*>(smem);
     __shared__ double red[kRedLen];
 
-    const WgState ws = a.pstate[par];
+    const WgState ws = a.pstate[slot];
     StepInfo si;
     si.step = ws.step;
 #pragma unroll
@@ -1143,17 +1155,18 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items(DevArgs 
         si.hcx[h] = uni(ws.hx[h]);
         si.hcy[h] = uni(ws.hy[h]);
     }
-    const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
-    T* dst = static_cast<T*>(par ? a.field0 : a.field1);
-    double* partials = a.partials + static_cast<int64_t>(par) * a.part_stride;
+    const int cur = uni(ws.cur);
+    const T* src = static_cast<const T*>(cur ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(cur ? a.field0 : a.field1);
+    double* partials = a.partials + static_cast<int64_t>(slot) * a.part_stride;
     if (blockIdx.x == 0) {
-        settle_partials(a, par ^ 1, red, a.block);   // the previous step's sum
-        int* other = a.heads + (par ^ 1) * a.nqueues;
+        settle_others(a, 1u << slot, red, a.block);   // earlier steps' sums
+        int* other = a.heads + static_cast<int>((ws.step + 1) & 1) * a.nqueues;
         for (int q = threadIdx.x; q < a.nqueues; q += a.block) other[q] = a.head0;
         if (threadIdx.x == 0) {
-            a.ctrl->pend_n[par] = a.ctrl->nitems;
-            a.ctrl->pend_step[par] = ws.step + 1;
-            a.pstate[par ^ 1] = next_state(a, ws);
+            a.ctrl->pend_n[slot] = a.ctrl->nitems;
+            a.ctrl->pend_step[slot] = ws.step + 1;
+            a.pstate[(slot + 1) & 3] = next_state(a, ws);
         }
     }
     const ItemDesc d = uni(a.queue[blockIdx.x]);
@@ -1178,10 +1191,10 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_plain(DevArgs a, int chu
 
     const WgState ws = a.wstate[0];
     const uint64_t step = ws.step;
-    const int par = static_cast<int>(step & 1);
+    const int b = static_cast<int>(step & 3);
     const StepInfo si = step_info(ws);
-    const T* src = static_cast<const T*>(par ? a.field1 : a.field0);
-    T* dst = static_cast<T*>(par ? a.field0 : a.field1);
+    const T* src = static_cast<const T*>(ws.cur ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(ws.cur ? a.field0 : a.field1);
     const int item = a.item_off[chunk] + blockIdx.x;
     if (item >= a.item_off[chunk + 1]) return;  // grid sized for a larger plan
     const ItemDesc d = a.items[item];
@@ -1195,7 +1208,7 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_plain(DevArgs a, int chu
     else
         o = process_item<T, V, KAHAN, PIPE>(a, d, no_item(), none, unused, src, dst, si.hcx, si.hcy, lds,
                                             red, NoHook{});
-    record_item(a, a.partials + static_cast<int64_t>(par) * a.part_stride, d, o,
+    record_item(a, a.partials + static_cast<int64_t>(b) * a.part_stride, d, o,
                 static_cast<double>(wall_clock64() - t_start));
 }
 
@@ -1206,26 +1219,26 @@ __global__ __launch_bounds__(kSumThreads) void k_finish(DevArgs a) {
     __shared__ double red[kRedLen];
     const WgState ws = a.wstate[0];
     const uint64_t step = ws.step;
-    const int par = static_cast<int>(step & 1);
-    settle_partials(a, par ^ 1, red, kSumThreads);
-    const double total = sum_partials(a.partials + static_cast<int64_t>(par) * a.part_stride,
+    const int b = static_cast<int>(step & 3);
+    settle_others(a, 1u << b, red, kSumThreads);
+    const double total = sum_partials(a.partials + static_cast<int64_t>(b) * a.part_stride,
                                       static_cast<int>(a.ctrl->nitems), red, kSumThreads);
     if (threadIdx.x == 0) {
         a.hist[step % kHistLen] = total;
-        a.ctrl->pend_step[par] = 0;
+        a.ctrl->pend_step[b] = 0;
     }
     for (int q = threadIdx.x; q < 2 * a.nqueues; q += kSumThreads) a.heads[q] = a.head0;
     __syncthreads();                  // every thread has read wstate[0]
     const WgState nx = next_state(a, ws);
     for (int w = threadIdx.x; w < a.nwg; w += kSumThreads) a.wstate[w] = nx;
-    if (threadIdx.x == 0) a.pstate[par ^ 1] = nx;
+    if (threadIdx.x == 0) a.pstate[(b + 1) & 3] = nx;
 }
 
-// Every workgroup's own copy of the step state from the shared copy of parity
-// par (after steps launched one workgroup per item, which keep only the shared
+// Every workgroup's own copy of the step state from the shared copy in slot
+// (after steps launched one workgroup per item, which keep only the shared
 // copies, and before a form that reads its own copy).
-__global__ __launch_bounds__(256) void k_seed_state(DevArgs a, int par) {
-    const WgState s = a.pstate[par];
+__global__ __launch_bounds__(256) void k_seed_state(DevArgs a, int slot) {
+    const WgState s = a.pstate[slot];
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < a.nwg; w += gridDim.x * blockDim.x)
         a.wstate[w] = s;
 }
@@ -1233,8 +1246,7 @@ __global__ __launch_bounds__(256) void k_seed_state(DevArgs a, int par) {
 // Sums the checksum of any persistent step still pending (one workgroup).
 __global__ __launch_bounds__(kSumThreads) void k_flush(DevArgs a) {
     __shared__ double red[kRedLen];
-    settle_partials(a, 0, red, kSumThreads);
-    settle_partials(a, 1, red, kSumThreads);
+    settle_others(a, 0u, red, kSumThreads);
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
@@ -1263,16 +1275,16 @@ __global__ void k_reset_control(DevArgs a) {
     for (int q = threadIdx.x; q < 2 * a.nqueues; q += blockDim.x) a.heads[q] = a.head0;
     WgState first;
     first.step = 0;
+    first.cur = 0;
 #pragma unroll
     for (int h = 0; h < kMaxHot; ++h) {
         first.hx[h] = a.hx_first[h];
         first.hy[h] = a.hy_first[h];
     }
     for (int w = threadIdx.x; w < a.nwg; w += blockDim.x) a.wstate[w] = first;
-    if (threadIdx.x < 2) a.pstate[threadIdx.x] = first;
-    if (threadIdx.x == 0) {
-        a.ctrl->pend_step[0] = 0;
-        a.ctrl->pend_step[1] = 0;
+    if (threadIdx.x < kStepSlots) {
+        a.pstate[threadIdx.x] = first;
+        a.ctrl->pend_step[threadIdx.x] = 0;
     }
 }
 
@@ -1439,18 +1451,18 @@ int launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitem
     return static_cast<int>(hipGetLastError());
 }
 
-int launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int par,
+int launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
                  void* stream) {
     if (vec != 4 || a.march <= 0 || nitems <= 0) return static_cast<int>(hipErrorInvalidValue);
     hipLaunchKernelGGL(pick_items(prec, pipe_of(a)), dim3(nitems), dim3(block), lds,
-                       static_cast<hipStream_t>(stream), a, par);
+                       static_cast<hipStream_t>(stream), a, slot);
     return static_cast<int>(hipGetLastError());
 }
 
-int launch_seed_state(const DevArgs& a, int par, void* stream) {
+int launch_seed_state(const DevArgs& a, int slot, void* stream) {
     const int blocks = (a.nwg + 255) / 256;
     hipLaunchKernelGGL(k_seed_state, dim3(blocks > 0 ? blocks : 1), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), a, par);
+                       static_cast<hipStream_t>(stream), a, slot);
     return static_cast<int>(hipGetLastError());
 }
 

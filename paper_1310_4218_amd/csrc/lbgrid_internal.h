@@ -19,16 +19,21 @@ constexpr size_t kMaxLds = 160 * 1024;  // gfx950: 160 KiB of LDS per CU
 // keyed by XCD (3 bits) and the unit's shader-engine/array/CU id (8 bits).
 constexpr int kCuSlots = 2048;
 
+// Checksum partial buffers and shared step-state copies are kept per step
+// mod 4: a launch writes those of its own step(s) (one, or two when it fuses
+// two steps) and never those of the launch before it.
+constexpr int kStepSlots = 4;
+
 // Device control block (first bytes of the workspace).
 struct Ctrl {
     uint32_t nitems;        // work items of the installed plan
     uint32_t pad0;
-    // The checksum partials of a persistent step are summed during the next
-    // step (or by k_flush): pend_step[p] = 1 + the step whose partials buffer p
-    // holds, 0 once they are summed; pend_n[p] = the items that wrote it.
-    uint64_t pend_step[2];
-    uint32_t pend_n[2];
-    uint64_t pad1[4];
+    // The checksum partials of a step are summed during a later launch (or by
+    // k_flush): pend_step[b] = 1 + the step whose partials buffer b holds, 0
+    // once they are summed; pend_n[b] = the items that wrote it.
+    uint64_t pend_step[kStepSlots];
+    uint32_t pend_n[kStepSlots];
+    uint64_t pad1[2];
 };
 
 // What each workgroup of the persistent launch carries from one step to the
@@ -38,6 +43,7 @@ struct Ctrl {
 struct alignas(64) WgState {
     uint64_t step;
     int32_t hx[kMaxHot], hy[kMaxHot];
+    int32_t cur;            // field copy (0 or 1) holding the values this step reads
 };
 
 // One work item: a range of rows of one tile, self-contained so that a claim
@@ -66,15 +72,15 @@ struct DevArgs {
     int32_t* heads;            // 2 x Q claim counters, one set per step parity; a step finds
                                // its set at head0 and resets the other set for the next step
     WgState* wstate;           // nwg: step and hotspot centres, kept by each workgroup
-    WgState* pstate;           // 2, by step parity: the state of a step whose launch form
-                               // reads one shared copy (one workgroup per item); every form
-                               // writes the next step's copy
+    WgState* pstate;           // kStepSlots, by step mod 4: the state of a step whose launch
+                               // form reads one shared copy (one workgroup per item); every
+                               // form writes the copy of the step after its own
     Ctrl* ctrl;
     double* loads_work;        // C
     double* loads_time;        // C
     double* tile_work;         // ntiles: work units of each tile (rebuilds items from it)
-    double* partials;          // 2 x part_stride, by step parity: per item, the sum of its
-                               // outputs in that step
+    double* partials;          // kStepSlots x part_stride, by step mod 4: per item, the sum
+                               // of its outputs in that step
     double* hist;              // kHistLen per-step sums
     double* wg_busy;           // nwg (persistent: per workgroup), or kCuSlots (one workgroup
                                // per item: per compute unit)
@@ -124,11 +130,12 @@ int  launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, 
 int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitems_chunk,
                         int block, size_t lds, void* stream);
 // One workgroup per item of the installed plan (nitems of them, in queue order);
-// par is the parity of the step (steps enqueued so far, mod 2).
-int  launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int par,
+// slot is the step's number mod 4 (steps enqueued so far).
+int  launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
                   void* stream);
-// Copy the shared state of a step of parity par into every workgroup's own copy.
-int  launch_seed_state(const DevArgs& a, int par, void* stream);
+// Copy the shared state of the step in slot (its number mod 4) into every
+// workgroup's own copy.
+int  launch_seed_state(const DevArgs& a, int slot, void* stream);
 int  launch_finish(const DevArgs& a, void* stream);
 int  launch_flush(const DevArgs& a, void* stream);
 int  launch_gather(const GatherSeg* segs, int n, void* stream);   // n <= kMaxGather

@@ -288,7 +288,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_lt = take(sizeof(double) * static_cast<size_t>(p.C));
     p.off_tw = take(sizeof(double) * static_cast<size_t>(p.ntiles));
     p.off_busy = take(sizeof(double) * static_cast<size_t>(std::max(p.nwg_cap, kCuSlots)));
-    p.off_part = take(sizeof(double) * 2 * static_cast<size_t>(p.nrows));
+    p.off_part = take(sizeof(double) * kStepSlots * static_cast<size_t>(p.nrows));
     p.off_hist = take(sizeof(double) * kHistLen);
     p.off_tl = take(sizeof(uint64_t) * 4 * static_cast<size_t>(p.nwg_cap));
     p.off_visits = take(sizeof(int32_t) * static_cast<size_t>(p.nrows));
@@ -354,11 +354,12 @@ struct lb_ctx {
     double host_plan_us = 0.0;        // all plans: items, queue order, staging, upload launch
     hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
     hipGraphExec_t g_pers1 = nullptr; // one persistent step
-    // one workgroup per item: graph_steps steps and one step, per parity of the
-    // first step (the parity is a launch argument), for the plan they were taken on
-    hipGraphExec_t g_items[2] = {nullptr, nullptr};
-    hipGraphExec_t g_items1[2] = {nullptr, nullptr};
-    int64_t items_graph_version[2] = {-1, -1};
+    // one workgroup per item: graph_steps steps and one step, per slot (number mod 4)
+    // of the first step (the slot is a launch argument), for the plan they were taken on
+    hipGraphExec_t g_items[kStepSlots] = {};
+    hipGraphExec_t g_items1[kStepSlots] = {};
+    int64_t items_graph_version[kStepSlots] = {-1, -1, -1, -1};
+    int cur = 0;                      // field copy holding the current step's values
     bool wstate_stale = false;        // only the shared per-parity step state is current
     bool items_stale = false;         // the chunk-order item tables on the device are not the plan's
     hipGraphExec_t g_plain = nullptr; // one plain step
@@ -706,22 +707,22 @@ int upload_items(lb_ctx* x) {
     return LB_OK;
 }
 
-// Launch of one balanced step (either form); par is the step's parity.
-int launch_balanced(lb_ctx* x, int par, hipStream_t s) {
+// Launch of one balanced step (either form); slot is the step's number mod 4.
+int launch_balanced(lb_ctx* x, int slot, hipStream_t s) {
     const Plan& p = x->plan;
     if (p.IG)
-        return launch_items(x->args, p.prec, p.vec, static_cast<int>(x->items.size()), p.block, p.lds, par, s);
+        return launch_items(x->args, p.prec, p.vec, static_cast<int>(x->items.size()), p.block, p.lds, slot, s);
     return launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, s);
 }
 
-int capture(lb_ctx* x, int mode, int nsteps, hipGraphExec_t* out, int par0 = 0) {
+int capture(lb_ctx* x, int mode, int nsteps, hipGraphExec_t* out, int slot0 = 0) {
     const Plan& p = x->plan;
     hipGraph_t g = nullptr;
     HIP_TRY(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
     int rc = 0;
     for (int i = 0; i < nsteps && rc == 0; ++i) {
         if (mode == LB_PERSISTENT) {
-            rc = launch_balanced(x, (par0 + i) & 1, x->cap);
+            rc = launch_balanced(x, (slot0 + i) & 3, x->cap);
         } else {
             for (int32_t c = 0; c < p.C && rc == 0; ++c)
                 rc = launch_plain_chunk(x->args, p.prec, p.vec, c, x->item_off[c + 1] - x->item_off[c],
@@ -990,9 +991,11 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
     const int fail_at = forced_launch_failure();
     int launches = 0;
     auto forced = [&]() { return fail_at > 0 && ++launches == fail_at; };
+    // every launch moves the field to the other copy (a launch of one step at a time)
     auto done = [&](int n) {
         x->steps += n;
         x->window_steps += n;
+        x->cur ^= (n & 1);
     };
     auto launch_failed = [&](const char* what, int e, bool partial) {
         if (partial) x->broken = true;
@@ -1005,7 +1008,7 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
     // refreshed after steps launched one workgroup per item.
     const bool own_state = !(p.IG && (mode == LB_PERSISTENT || mode == LB_PERSISTENT_EAGER));
     if (own_state && x->wstate_stale) {
-        LAUNCH_TRY(x, launch_seed_state(x->args, static_cast<int>(x->steps & 1), x->stream));
+        LAUNCH_TRY(x, launch_seed_state(x->args, static_cast<int>(x->steps & 3), x->stream));
         x->wstate_stale = false;
     }
     if (!own_state) x->wstate_stale = true;
@@ -1015,8 +1018,8 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
         case LB_PERSISTENT: {
             const int R = x->cfg.graph_steps;
             if (p.IG) {
-                // graphs per parity of their first step, retaken when the plan changes
-                for (int k = 0; k < 2; ++k)
+                // graphs per slot of their first step, retaken when the plan changes
+                for (int k = 0; k < kStepSlots; ++k)
                     if (x->items_graph_version[k] != x->plan_version) {
                         if (x->g_items[k]) HIP_TRY(x, hipGraphExecDestroy(x->g_items[k]));
                         if (x->g_items1[k]) HIP_TRY(x, hipGraphExecDestroy(x->g_items1[k]));
@@ -1024,19 +1027,19 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
                         x->items_graph_version[k] = x->plan_version;
                     }
                 for (int i = 0; i < nsteps / R; ++i) {
-                    const int par = static_cast<int>(x->steps & 1);
-                    if (!x->g_items[par] && (rc = capture(x, LB_PERSISTENT, R, &x->g_items[par], par)) != LB_OK)
+                    const int sl = static_cast<int>(x->steps & 3);
+                    if (!x->g_items[sl] && (rc = capture(x, LB_PERSISTENT, R, &x->g_items[sl], sl)) != LB_OK)
                         return rc;
                     if (forced()) return launch_failed("hipGraphLaunch", 0, false);
-                    if (int e = hipGraphLaunch(x->g_items[par], x->stream)) return launch_failed("hipGraphLaunch", e, false);
+                    if (int e = hipGraphLaunch(x->g_items[sl], x->stream)) return launch_failed("hipGraphLaunch", e, false);
                     done(R);
                 }
                 for (int i = 0; i < nsteps % R; ++i) {
-                    const int par = static_cast<int>(x->steps & 1);
-                    if (!x->g_items1[par] && (rc = capture(x, LB_PERSISTENT, 1, &x->g_items1[par], par)) != LB_OK)
+                    const int sl = static_cast<int>(x->steps & 3);
+                    if (!x->g_items1[sl] && (rc = capture(x, LB_PERSISTENT, 1, &x->g_items1[sl], sl)) != LB_OK)
                         return rc;
                     if (forced()) return launch_failed("hipGraphLaunch", 0, false);
-                    if (int e = hipGraphLaunch(x->g_items1[par], x->stream)) return launch_failed("hipGraphLaunch", e, false);
+                    if (int e = hipGraphLaunch(x->g_items1[sl], x->stream)) return launch_failed("hipGraphLaunch", e, false);
                     done(1);
                 }
                 break;
@@ -1058,7 +1061,7 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
         case LB_PERSISTENT_EAGER:
             for (int i = 0; i < nsteps; ++i) {
                 if (forced()) return launch_failed("launch_balanced", 0, false);
-                if (int e = launch_balanced(x, static_cast<int>(x->steps & 1), x->stream))
+                if (int e = launch_balanced(x, static_cast<int>(x->steps & 3), x->stream))
                     return launch_failed("launch_balanced", e, false);
                 done(1);
             }
@@ -1241,7 +1244,7 @@ int lb_fields(lb_ctx* x, int32_t field, void* dst, size_t dst_bytes, double* che
     const size_t bytes = static_cast<size_t>(p.ncells) * p.elem;
     if (dst && dst_bytes < bytes) return fail(&x->err, LB_E_NOMEM, "dst too small");
     HIP_TRY(x, hipSetDevice(x->device));
-    const char* cur = static_cast<const char*>(x->field[x->steps & 1]) + static_cast<size_t>(field) * bytes;
+    const char* cur = static_cast<const char*>(x->field[x->cur]) + static_cast<size_t>(field) * bytes;
     if (checksum_out) {
         double* part = reinterpret_cast<double*>(x->ws + p.off_sum);
         LAUNCH_TRY(x, launch_field_sum(cur, p.prec, p.ncells, part, part + kSumBlocks, x->stream));
@@ -1347,7 +1350,7 @@ void lb_destroy(lb_ctx* x) {
     if (x->stream || x->cap) (void)hipStreamSynchronize(x->stream);
     if (x->g_pers) (void)hipGraphExecDestroy(x->g_pers);
     if (x->g_pers1) (void)hipGraphExecDestroy(x->g_pers1);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kStepSlots; ++k) {
         if (x->g_items[k]) (void)hipGraphExecDestroy(x->g_items[k]);
         if (x->g_items1[k]) (void)hipGraphExecDestroy(x->g_items1[k]);
     }
