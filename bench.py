@@ -97,7 +97,7 @@ def run_balanced(Grid, wl, steps, warmup, R, params, torch, overlap=2):
         g.step(n, MODE)
         if timed:
             e[1].record(stream)
-            evs.append(e)
+            evs.append(e + (n,))
 
     def run(nsteps, timed):
         wins = []
@@ -132,6 +132,10 @@ def run_balanced(Grid, wl, steps, warmup, R, params, torch, overlap=2):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kernel_s = sum(e[0].elapsed_time(e[1]) for e in evs) / 1e3
+    # launches of the step kernel in the timed region: two steps per launch when fused,
+    # an odd count ending on a single step
+    fused = params.get("fuse_steps") == 2
+    launches = sum(n // 2 + n % 2 if fused else n for _, _, n in evs)
     # workgroup busy time of the persistent kernel over one more window
     g.step(R, MODE)
     busy = g.wg_busy()
@@ -141,7 +145,7 @@ def run_balanced(Grid, wl, steps, warmup, R, params, torch, overlap=2):
     nw = max(len(wins), 1)
     host = dict(balance_us_per_window=(st["host_balance_us"] - st0["host_balance_us"]) / nw,
                 plan_us_per_window=(st["host_plan_us"] - st0["host_plan_us"]) / nw)
-    return dict(wall=wall, kernel_s=kernel_s, wins=wins, busy=busy, stats=st, host=host)
+    return dict(wall=wall, kernel_s=kernel_s, launches=launches, wins=wins, busy=busy, stats=st, host=host)
 
 
 def run_plain(Grid, wl, steps, warmup, params, torch, mode="plain"):
@@ -214,7 +218,7 @@ def run_ablation(Grid, wl, steps, warmup, R, params, torch, balance_host):
     import numpy as np
 
     S = wl.nslots
-    p = {k: v for k, v in params.items() if k not in ("nqueues", "steal", "wg_per_queue", "item_grid")}
+    p = {k: v for k, v in params.items() if k not in ("nqueues", "steal", "wg_per_queue", "item_grid", "fuse_steps")}
     block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)],
                      dtype=np.int32)
     out = {}
@@ -355,12 +359,16 @@ def main(argv=None) -> int:
     lam_wg = float(busy.max() / busy.mean()) if busy.size and busy.mean() > 0 else None
 
     elem = 8 if args.precision == "fp64" else 4
-    bytes_per_step = 2 * elem * cells
+    # a launch reads every cell once and writes it once, whether it takes one step or
+    # two (fused); launches of two steps do half the traffic per step
+    bytes_per_launch = 2 * elem * cells
     # both field copies larger than the 256 MB Infinity Cache: every step streams from HBM;
     # smaller grids stay cache-resident and are bound by latency and fixed costs instead
-    hbm_resident = bytes_per_step > 256 * 2 ** 20
-    kernel_step_s = bal["kernel_s"] / args.steps
-    achieved = bytes_per_step / kernel_step_s / 1e9
+    hbm_resident = bytes_per_launch > 256 * 2 ** 20
+    kernel_launch_s = bal["kernel_s"] / bal["launches"]
+    achieved = bytes_per_launch / kernel_launch_s / 1e9
+    kname = ("k_items2" if params.get("fuse_steps") == 2 else "k_items") if params.get("item_grid") \
+        else "k_persistent"
     st = bal["stats"]
 
     out = {
@@ -409,9 +417,10 @@ def main(argv=None) -> int:
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.workload, args.precision,
                                         {k: v for k, v in params.items() if k != "precision"}),
-            "kernel": "k_items" if params.get("item_grid") else "k_persistent",
-            "bytes_per_launch": bytes_per_step,
-            "us_per_launch_events": kernel_step_s * 1e6,
+            "kernel": kname,
+            "bytes_per_launch": bytes_per_launch,
+            "steps_per_launch": args.steps / bal["launches"],
+            "us_per_launch_events": kernel_launch_s * 1e6,
         },
     }
     if args.calibration_copy > 0:

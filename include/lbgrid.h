@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 3
+#define LB_ABI_VERSION 4
 #define LB_MAX_HOT 4
 #define LB_NBUF 3
 
@@ -160,6 +160,16 @@ typedef struct {
                                 dispatcher schedules them instead of claims on
                                 the queues; needs march > 0.  0 = persistent
                                 workgroups claiming from the queues (default) */
+    int32_t fuse_steps;      /* item_grid 1 only: 2 = a balanced launch takes
+                                two steps at once (temporal blocking): each
+                                item reads its cells and a two-cell halo of
+                                step s once, computes step s + 1 on the item
+                                and a one-cell ring around it, and writes
+                                step s + 2, with the same bits as two single
+                                steps; an odd step count ends on a single
+                                step.  (tile_x + 4) * nz / 4 threads per
+                                workgroup, at most 512 in FP64.  0 or 1 = one
+                                step per launch (default)                     */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;
@@ -193,7 +203,8 @@ typedef struct {
                                 workgroups), or 2048 per-compute-unit slots
                                 when balanced steps launch one workgroup per
                                 item (keyed by XCD and CU id; unused ones 0)  */
-    int32_t pad0;
+    int32_t block2;          /* threads per workgroup of a two-step launch
+                                (fuse_steps 2), else 0                        */
 } lb_stats_t;
 
 /* Fill *cfg with the defaults listed in lb_config. */

@@ -220,6 +220,36 @@ __device__ void block_sum2(double& a, double& b, double* red, int bs) {
     __syncthreads();
 }
 
+// Three block-wide sums (valid in thread 0); red must hold 3 * kMaxBlock / 64
+// doubles of LDS.
+__device__ void block_sum3(double& a, double& b, double& c, double* red, int bs) {
+    constexpr int kW = kMaxBlock / kWave;
+    const int wave = threadIdx.x / kWave;
+    const int nwaves = (bs + kWave - 1) / kWave;
+    const int active = min(kWave, bs - wave * kWave);
+    a = wave_sum(a, active);
+    b = wave_sum(b, active);
+    c = wave_sum(c, active);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[wave] = a;
+        red[kW + wave] = b;
+        red[2 * kW + wave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0, sc = 0.0;
+        for (int w = 0; w < nwaves; ++w) {
+            sa += red[w];
+            sb += red[kW + w];
+            sc += red[2 * kW + w];
+        }
+        a = sa;
+        b = sb;
+        c = sc;
+    }
+    __syncthreads();
+}
+
 // ---- one work item ----------------------------------------------------------------
 constexpr int kPipeDma = 1;   // pipeline template value of the direct global->LDS path
 
@@ -236,6 +266,13 @@ struct ItemOut {
     double checksum;  // sum of the item's outputs over all fields (valid in thread 0)
     double work;      // work units of the item (valid in thread 0)
     int chunk;
+};
+
+// Result of an item that advances its cells by two steps in one pass.
+struct ItemOut2 {
+    double checksum1;  // sum of the item's outputs of the first step (thread 0)
+    double checksum2;  // ... of the second step
+    double work;       // work units of both steps (thread 0)
 };
 
 struct NoHook {
@@ -574,6 +611,61 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, const Vec<T, V>& 
     }
 }
 
+// One cell group of the march: the 7-point update of this thread's V levels
+// of the current row (x and z neighbours from the row in LDS at Lc, y
+// neighbours ym and yp), then the column physics with k iterations.
+template <typename T, int V, int KAHAN>
+__device__ __forceinline__ void cell_update(const DevArgs& a, const T* Lc, const Vec<T, V>& c,
+                                            const Vec<T, V>& ym, const Vec<T, V>& yp, int tzq, int NQ,
+                                            int nz, int k, T cc, T cn, T eps, T (&q)[V]) {
+    const Vec<T, V> xm = ld<T, V>(Lc - nz);
+    const Vec<T, V> xp = ld<T, V>(Lc + nz);
+    const T below = Lc[-1];   // the column's level zoff - 1 when tzq > 0
+    const T above = Lc[V];    // ... zoff + V when tzq < NQ - 1
+    const T zlo = (tzq == 0) ? c.v[0] : below;
+    const T zhi = (tzq == NQ - 1) ? c.v[V - 1] : above;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const T zm = (v == 0) ? zlo : c.v[v - 1];
+        const T zp = (v == V - 1) ? zhi : c.v[v + 1];
+        T sum = xm.v[v] + xp.v[v];
+        sum = sum + ym.v[v];
+        sum = sum + yp.v[v];
+        sum = sum + zm;
+        sum = sum + zp;
+        q[v] = combine(cc, cn, c.v[v], sum);
+    }
+    if (a.vertical)
+        physics_vertical<T, V>(eps, k, tzq, NQ, q);
+    else
+        physics_vec<KAHAN, T, V>(eps, k, q);
+}
+
+// Thread -> (column tcol, lane tzq of the column) of a march workgroup.
+// Dense: consecutive NQ threads per column.  With col_per_wave > 0 (the
+// vertical physics when NQ does not divide 64) every wave holds col_per_wave
+// whole columns in its first lanes and leaves the rest idle, so that a
+// column's lanes never straddle two waves.  Returns whether the lane is used.
+__device__ __forceinline__ bool march_lane(const DevArgs& a, int NQ, int& tcol, int& tzq) {
+    if (a.col_per_wave > 0) {
+        const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
+        const int cw = lane / NQ;
+        tcol = (static_cast<int>(threadIdx.x) >> 6) * a.col_per_wave + cw;
+        tzq = lane - cw * NQ;
+        return cw < a.col_per_wave;
+    }
+    tcol = threadIdx.x / NQ;
+    tzq = threadIdx.x - tcol * NQ;
+    return true;
+}
+
+// v mod n in [0, n) for v within a few multiples of n of the range
+__device__ __forceinline__ int wrap_near(int v, int n) {
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
 // One item with the column-march pipeline.  The workgroup has (TX+2)*NQ
 // threads: thread column tcol (0..TX+1) streams grid column x0 - 1 + tcol of
 // the item's rows -1 .. h (the item's own w columns and one halo column on
@@ -590,24 +682,9 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
     const int nz = a.nz, nx = a.nx, ny = a.ny;
     const int NQ = nz / V;
     const int TX = a.tile_x;
-    const int BS = a.block;                   // == blockDim.x
-    // Thread -> (column tcol, lane tzq of the column).  Dense: consecutive NQ
-    // threads per column, (TX + 2) * NQ threads.  With col_per_wave > 0 (the
-    // vertical physics when NQ does not divide 64) every wave holds
-    // col_per_wave whole columns in its first lanes and leaves the rest idle,
-    // so that a column's lanes never straddle two waves.
+    const int BS = a.block;                   // == blockDim.x (at least (TX + 2) columns)
     int tcol, tzq;
-    bool lane_used = true;
-    if (a.col_per_wave > 0) {
-        const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
-        const int cw = lane / NQ;
-        tcol = (static_cast<int>(threadIdx.x) >> 6) * a.col_per_wave + cw;
-        tzq = lane - cw * NQ;
-        lane_used = cw < a.col_per_wave;
-    } else {
-        tcol = threadIdx.x / NQ;
-        tzq = threadIdx.x - tcol * NQ;
-    }
+    const bool lane_used = march_lane(a, NQ, tcol, tzq);
     const int zoff = tzq * V;
     const int x0 = d.x0, y0 = d.y0;
     const int w = d.wh & 0xffff;
@@ -662,30 +739,10 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
                     Vec<T, V> o;
                     uint32_t so = kOutOfRange;
                     if (active) {
-                        const T* Lc = L + tcol * nz + zoff;
-                        const Vec<T, V> xm = ld<T, V>(Lc - nz);
-                        const Vec<T, V> xp = ld<T, V>(Lc + nz);
-                        const T below = Lc[-1];   // the column's level zoff - 1 when tzq > 0
-                        const T above = Lc[V];    // ... zoff + V when tzq < NQ - 1
-                        const T zlo = (tzq == 0) ? c.v[0] : below;
-                        const T zhi = (tzq == NQ - 1) ? c.v[V - 1] : above;
                         const int k = kbuf[r * TX + tcol - 1];
                         T q[V];
-#pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            const T zm = (v == 0) ? zlo : c.v[v - 1];
-                            const T zp = (v == V - 1) ? zhi : c.v[v + 1];
-                            T sum = xm.v[v] + xp.v[v];
-                            sum = sum + ym.v[v];
-                            sum = sum + yp.v[v];
-                            sum = sum + zm;
-                            sum = sum + zp;
-                            q[v] = combine(cc, cn, c.v[v], sum);
-                        }
-                        if (a.vertical)
-                            physics_vertical<T, V>(eps, k, tzq, NQ, q);
-                        else
-                            physics_vec<KAHAN, T, V>(eps, k, q);
+                        cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, k, cc, cn,
+                                                 eps, q);
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             o.v[v] = q[v];
@@ -716,6 +773,147 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
     o.checksum = chk;
     o.work = work;
     o.chunk = d.chunk;
+    return o;
+}
+
+// Two steps of one item in one pass (temporal blocking): the values of step
+// s + 2 on the item's w x h columns from those of step s, with the field read
+// once and written once for both steps.  The workgroup has (TX + 4) * NQ
+// threads (or whole columns per wave, as in the one-step march): thread
+// column tcol streams grid column x0 - 2 + tcol, rows -2 .. h + 1 of the item.
+// Threads 1 .. w + 2 compute step s + 1 on the columns -1 .. w and rows
+// -1 .. h (the item and the ring of cells around it that the item's next
+// update reads); threads 2 .. w + 1 compute step s + 2 on the item's own cells
+// one row behind.  Each update is the same arithmetic as in the one-step
+// march, so the fused steps give the same bits as two launches of one step.
+// The ring's step s + 1 values are computed again by the neighbouring items;
+// only the item's own cells count in the checksum and the work of each step.
+// Both rows of a step go through LDS (step s values for step s + 1, step s + 1
+// values for step s + 2), double-buffered, with one barrier per row.  hc1 are
+// the hotspot centres of step s, hc2 those of step s + 1.
+template <typename T, int V, int KAHAN, int D>
+__device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, const T* __restrict__ src,
+                                        T* __restrict__ dst, const int* hc1x, const int* hc1y,
+                                        const int* hc2x, const int* hc2y, T* lds, double* red) {
+    const int nz = a.nz, nx = a.nx, ny = a.ny;
+    const int NQ = nz / V;
+    const int TX = a.tile_x;
+    const int BS = a.block2;                  // == blockDim.x (at least (TX + 4) columns)
+    int tcol, tzq;
+    const bool lane_used = march_lane(a, NQ, tcol, tzq);
+    const int zoff = tzq * V;
+    const int x0 = d.x0, y0 = d.y0;
+    const int w = d.wh & 0xffff;
+    const int h = d.wh >> 16;
+    const bool streams = lane_used && tcol < w + 4;                // loads grid column x0 - 2 + tcol
+    const bool act1 = lane_used && tcol >= 1 && tcol <= w + 2;      // step s + 1 on column tcol - 2
+    const bool act2 = lane_used && tcol >= 2 && tcol <= w + 1;      // step s + 2 on column tcol - 2
+    const int gx = streams ? wrap_near(x0 - 2 + tcol, nx) : 0;
+    const uint32_t rowbytes = static_cast<uint32_t>(nx) * static_cast<uint32_t>(nz) * sizeof(T);
+    const uint32_t colbytes = (static_cast<uint32_t>(gx) * nz + zoff) * sizeof(T);
+    const T cc = static_cast<T>(a.cc), cn = static_cast<T>(a.cn), eps = static_cast<T>(a.eps);
+    const int RL = (TX + 4) * nz;             // LDS row (elements); buffers: 2 of step s, 2 of s + 1
+    const int K1 = TX + 2;                    // row stride of the step s + 1 trip counts
+    int* kb1 = reinterpret_cast<int*>(lds + 4 * RL);
+    int* kb2 = kb1 + K1 * (a.tile_y + 2);
+    // byte offset of row i (-2 .. h + 1) of this thread's column; out of range for
+    // threads without a column and past the last row the item reads
+    auto row_off = [&](int i) -> uint32_t {
+        if (!streams || i > h + 1) return kOutOfRange;
+        return colbytes + static_cast<uint32_t>(wrap_near(y0 + i, ny)) * rowbytes;
+    };
+    for (int i = threadIdx.x; i < (w + 2) * (h + 2); i += BS) {
+        const int r = i / (w + 2), cx = i - r * (w + 2);
+        kb1[r * K1 + cx] = column_k(a, hc1x, hc1y, wrap_near(x0 - 1 + cx, nx), wrap_near(y0 - 1 + r, ny));
+    }
+    for (int i = threadIdx.x; i < w * h; i += BS) {
+        const int r = i / w, cx = i - r * w;
+        kb2[r * TX + cx] = column_k(a, hc2x, hc2y, x0 + cx, y0 + r);
+    }
+    const bool own1 = tcol >= 2 && tcol <= w + 1;   // an item column (step s + 1 counts it)
+    double chk1 = 0.0, chk2 = 0.0;
+    int ksum = 0, krows = 0;                  // trip counts and rows of this thread's column (field 0)
+    int par = 0;                              // LDS buffers of the next row
+    const int n_it = h + 2;                   // iteration n computes step s + 1 on row n - 1
+    for (int f = 0; f < a.nfields; ++f) {
+        const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+        const rsrc_t out = field_rsrc(dst + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+        Vec<T, V> ym = bload<T, V>(in, row_off(-2));   // step s rows i - 1, i, then i + 1 ..
+        Vec<T, V> c = bload<T, V>(in, row_off(-1));
+        Vec<T, V> R[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) R[j] = bload<T, V>(in, row_off(j));
+        Vec<T, V> s1m{}, s1c{};               // step s + 1 rows i - 2 and i - 1
+        for (int n0 = 0; n0 < n_it; n0 += D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int n = n0 + j;
+                if (n < n_it) {
+                    const int i = n - 1;
+                    T* LA = lds + par * RL;           // step s, row i
+                    T* LB = lds + (2 + par) * RL;     // step s + 1, row i - 1
+                    par ^= 1;
+                    if (streams) st<T, V>(LA + tcol * nz + zoff, c);
+                    if (act1) st<T, V>(LB + tcol * nz + zoff, s1c);
+                    __syncthreads();
+                    const Vec<T, V> yp = R[j];
+                    R[j] = bload<T, V>(in, row_off(n + D));
+                    Vec<T, V> s1n{};
+                    if (act1) {
+                        const int k = kb1[n * K1 + tcol - 1];
+                        T q[V];
+                        cell_update<T, V, KAHAN>(a, LA + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, k, cc, cn,
+                                                 eps, q);
+                        const bool own = own1 && i >= 0 && i < h;
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            s1n.v[v] = q[v];
+                            if (own) chk1 += static_cast<double>(q[v]);
+                        }
+                        if (own && f == 0 && tzq == 0) {
+                            ksum += k;
+                            ++krows;
+                        }
+                    }
+                    if (i >= 1) {                     // step s + 2 on row i - 1
+                        Vec<T, V> o;
+                        uint32_t so = kOutOfRange;
+                        if (act2) {
+                            const int k = kb2[(i - 1) * TX + tcol - 2];
+                            T q[V];
+                            cell_update<T, V, KAHAN>(a, LB + tcol * nz + zoff, s1c, s1m, s1n, tzq, NQ, nz, k,
+                                                     cc, cn, eps, q);
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                o.v[v] = q[v];
+                                chk2 += static_cast<double>(q[v]);
+                            }
+                            if (f == 0 && tzq == 0) {
+                                ksum += k;
+                                ++krows;
+                            }
+                            so = colbytes + static_cast<uint32_t>(y0 + i - 1) * rowbytes;
+                        }
+                        if (a.stream_store)
+                            bstore<T, V, 2>(out, so, o);
+                        else
+                            bstore<T, V, 0>(out, so, o);
+                    }
+                    ym = c;
+                    c = yp;
+                    s1m = s1c;
+                    s1c = s1n;
+                }
+            }
+        }
+    }
+    double work = static_cast<double>(nz) * static_cast<double>(a.nfields) *
+                  (static_cast<double>(a.alpha) * static_cast<double>(krows) + static_cast<double>(ksum));
+    block_sum3(chk1, chk2, work, red, BS);
+    ItemOut2 o;
+    o.checksum1 = chk1;
+    o.checksum2 = chk2;
+    o.work = work;
     return o;
 }
 
@@ -1131,6 +1329,15 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
     }
 }
 
+// Busy time per compute unit of a launch of one workgroup per item: the
+// hardware's XCD id and the CU/array/engine bits 8..15 of its HW_ID register
+// name the unit this workgroup ran on.
+__device__ __forceinline__ void add_cu_busy(const DevArgs& a, double ticks) {
+    const unsigned hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);      // HW_ID, 32 bits
+    const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20);     // XCC_ID, 4 bits
+    unsafeAtomicAdd(&a.wg_busy[((xcc & 7u) << 8) | ((hw >> 8) & 0xffu)], ticks);
+}
+
 // One launch per step with one workgroup per item: workgroup b runs item b of
 // the queue order (all queues in turn; with one queue, the global longest-first
 // or hot-first-then-by-position order), and the hardware dispatcher starts each
@@ -1174,13 +1381,62 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items(DevArgs 
     const ItemOut o = process_item_march<T, V, KAHAN, D>(a, d, src, dst, si.hcx, si.hcy, lds, red, NoHook{});
     const double ticks = static_cast<double>(wall_clock64() - t_start);
     record_item(a, partials, d, o, ticks);
-    if (threadIdx.x == 0) {
-        // busy time per compute unit: the hardware's XCD id and the CU/array/engine
-        // bits 8..15 of its HW_ID register name the unit this workgroup ran on
-        const unsigned hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);      // HW_ID, 32 bits
-        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20);     // XCC_ID, 4 bits
-        unsafeAtomicAdd(&a.wg_busy[((xcc & 7u) << 8) | ((hw >> 8) & 0xffu)], ticks);
+    if (threadIdx.x == 0) add_cu_busy(a, ticks);
+}
+
+// Two steps per launch, one workgroup per item (the launch form above with
+// the fused two-step item body).  Step s's shared state is in slot; the
+// state of step s + 1 follows from it.  The launch writes the checksum
+// partials of steps s and s + 1 (buffers slot and slot + 1 mod 4), sums the
+// other buffers, and leaves the state of step s + 2 in slot + 2 mod 4: two
+// steps later, and the field copy flipped once (one launch, one write).
+template <typename T, int V, int KAHAN, int D>
+__global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items2(DevArgs a, int slot) {
+    extern __shared__ __align__(32) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    __shared__ double red[kRedLen];
+
+    const WgState ws = a.pstate[slot];
+    const WgState ws1 = next_state(a, ws);
+    int h1x[kMaxHot], h1y[kMaxHot], h2x[kMaxHot], h2y[kMaxHot];
+#pragma unroll
+    for (int h = 0; h < kMaxHot; ++h) {
+        h1x[h] = uni(ws.hx[h]);
+        h1y[h] = uni(ws.hy[h]);
+        h2x[h] = uni(ws1.hx[h]);
+        h2y[h] = uni(ws1.hy[h]);
     }
+    const int cur = uni(ws.cur);
+    const T* src = static_cast<const T*>(cur ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(cur ? a.field0 : a.field1);
+    const int slot1 = (slot + 1) & 3;
+    if (blockIdx.x == 0) {
+        settle_others(a, (1u << slot) | (1u << slot1), red, a.block2);   // earlier steps' sums
+        for (int q = threadIdx.x; q < 2 * a.nqueues; q += a.block2) a.heads[q] = a.head0;
+        if (threadIdx.x == 0) {
+            a.ctrl->pend_n[slot] = a.ctrl->nitems;
+            a.ctrl->pend_n[slot1] = a.ctrl->nitems;
+            a.ctrl->pend_step[slot] = ws.step + 1;
+            a.ctrl->pend_step[slot1] = ws.step + 2;
+            WgState n2 = next_state(a, ws1);
+            n2.cur = ws.cur ^ 1;
+            a.pstate[(slot + 2) & 3] = n2;
+        }
+    }
+    const ItemDesc d = uni(a.queue[blockIdx.x]);
+    const uint64_t t_start = wall_clock64();
+    const ItemOut2 o = process_item_march2<T, V, KAHAN, D>(a, d, src, dst, h1x, h1y, h2x, h2y, lds, red);
+    const double ticks = static_cast<double>(wall_clock64() - t_start);
+    if (threadIdx.x == 0) {
+        a.partials[static_cast<int64_t>(slot) * a.part_stride + d.id] = o.checksum1;
+        a.partials[static_cast<int64_t>(slot1) * a.part_stride + d.id] = o.checksum2;
+        unsafeAtomicAdd(&a.loads_work[d.chunk], o.work);
+        unsafeAtomicAdd(&a.loads_time[d.chunk], ticks);
+        unsafeAtomicAdd(&a.tile_work[d.tile], o.work);
+        add_cu_busy(a, ticks);
+    }
+    for (int r = threadIdx.x; r < (d.wh >> 16); r += a.block2)   // one visit per row and step
+        __hip_atomic_fetch_add(&a.visits[d.vbase + r], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T, int V, int KAHAN, int PIPE>
@@ -1408,6 +1664,19 @@ ItemsFn pick_items(int prec, int pipe) {
     if (prec == 1) return items_for<float, 1>(pipe);
     return items_for<float, 0>(pipe);
 }
+template <typename T, int KAHAN>
+ItemsFn items2_for(int pipe) {
+    switch (pipe) {
+        case kPipeMarch + 4: return k_items2<T, 4, KAHAN, 4>;
+        case kPipeMarch + 8: return k_items2<T, 4, KAHAN, 8>;
+        default: return k_items2<T, 4, KAHAN, 2>;
+    }
+}
+ItemsFn pick_items2(int prec, int pipe) {
+    if (prec == 2) return items2_for<double, 0>(pipe);
+    if (prec == 1) return items2_for<float, 1>(pipe);
+    return items2_for<float, 0>(pipe);
+}
 
 PersistentFn pick_persistent(int prec, int vec, int pipe) {
     if (prec == 2) return persistent_for<double, 0>(vec, pipe);
@@ -1455,6 +1724,15 @@ int launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, siz
                  void* stream) {
     if (vec != 4 || a.march <= 0 || nitems <= 0) return static_cast<int>(hipErrorInvalidValue);
     hipLaunchKernelGGL(pick_items(prec, pipe_of(a)), dim3(nitems), dim3(block), lds,
+                       static_cast<hipStream_t>(stream), a, slot);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_items2(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
+                  void* stream) {
+    if (vec != 4 || a.march <= 0 || nitems <= 0 || block != a.block2)
+        return static_cast<int>(hipErrorInvalidValue);
+    hipLaunchKernelGGL(pick_items2(prec, pipe_of(a)), dim3(nitems), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a, slot);
     return static_cast<int>(hipGetLastError());
 }

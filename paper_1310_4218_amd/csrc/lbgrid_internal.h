@@ -95,6 +95,7 @@ struct DevArgs {
     int32_t tile_x;            // TX
     int32_t tile_y;            // TY (the trip-count buffers hold TX * TY entries)
     int32_t block;             // threads per workgroup = TX * nz / V (== blockDim.x)
+    int32_t block2;            // threads per workgroup of the two-step item launch
     int32_t stage_rows;        // > 0: rows per direct global->LDS batch (V = 4 only); 0: registers
     int32_t reg_depth;         // register pipeline: rows in flight (2, 4 or 8; 2 unless V = 4)
     int32_t march;             // > 0: column-march pipeline with this many rows in flight (2, 4, 8)
@@ -133,6 +134,10 @@ int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nite
 // slot is the step's number mod 4 (steps enqueued so far).
 int  launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
                   void* stream);
+// The same with two steps per launch (temporal blocking): slot is the number mod 4
+// of the first of them, block the threads of a two-step workgroup (a.block2).
+int  launch_items2(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
+                   void* stream);
 // Copy the shared state of the step in slot (its number mod 4) into every
 // workgroup's own copy.
 int  launch_seed_state(const DevArgs& a, int slot, void* stream);

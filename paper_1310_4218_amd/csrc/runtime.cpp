@@ -55,6 +55,9 @@ struct Plan {
     int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
     int32_t M = 0;          // rows in flight of the column march; 0 = another pipeline
     bool IG = false;        // balanced steps launch one workgroup per item
+    int32_t F = 1;          // steps per launch of one workgroup per item (1, or 2 fused)
+    int32_t block2 = 0;     // threads per workgroup of the two-step item launch
+    size_t lds2 = 0;        // its LDS bytes
     int32_t CPW = 0;        // march: whole columns per wave (vertical physics, NQ not dividing 64)
     int32_t B = 0;          // rows per direct global->LDS batch; 0 = register pipeline
     int32_t ring = 4;       // LDS ring rows
@@ -174,6 +177,8 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->hot_cut < 0) return bad("hot_cut must be >= 0");
     if (c->item_grid != 0 && c->item_grid != 1) return bad("item_grid must be 0 or 1");
     if (c->item_grid == 1 && c->march == 0) return bad("item_grid needs the column-march pipeline (march > 0)");
+    if (c->fuse_steps < 0 || c->fuse_steps > 2) return bad("fuse_steps must be 0, 1 or 2");
+    if (c->fuse_steps == 2 && c->item_grid != 1) return bad("fuse_steps 2 needs item_grid 1");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
     p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
@@ -204,6 +209,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     // rows (V = 4 only) or the register path
     p.M = c->march;
     p.IG = c->item_grid == 1;
+    p.F = c->fuse_steps == 2 ? 2 : 1;
     if (p.M > 0) {
         if (p.vec != 4) return bad("march needs nz divisible by 4");
         if (static_cast<uint64_t>(p.ncells) * p.elem > 0xFFFFFE00ull)
@@ -227,13 +233,25 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         if (p.CPW > 0) return (tx + 2 + p.CPW - 1) / p.CPW * 64;   // whole columns per wave
         return (p.M > 0 ? tx + 2 : tx) * NQ;
     };
+    // the two-step item launch: two halo columns on either side, four LDS rows
+    // (two of each step) and the trip counts of both steps
+    auto threads2_for = [&](int tx) {
+        if (p.CPW > 0) return (tx + 4 + p.CPW - 1) / p.CPW * 64;
+        return (tx + 4) * NQ;
+    };
+    auto lds2_for = [&](int tx) {
+        return size_t{4} * (tx + 4) * col_bytes +
+               sizeof(int32_t) * (static_cast<size_t>(tx + 2) * (p.TY + 2) + static_cast<size_t>(tx) * p.TY);
+    };
     const int most = p.M > 0 ? (p.prec == LB_FP64 ? kMaxBlockDeep : kMaxBlock)
                              : (p.B == 0 && (p.RD >= 4 || p.prec == LB_FP64)) ? kMaxBlockDeep : kMaxBlock;
     if (c->tile_x > 0) {
         p.TX = c->tile_x;
     } else {
         p.TX = p.M > 0 ? 32 : 16;
-        while (p.TX > 1 && (threads_for(p.TX) > most || lds_for(p.TX) > 64 * 1024)) --p.TX;
+        while (p.TX > 1 && (threads_for(p.TX) > most || lds_for(p.TX) > 64 * 1024 ||
+                            (p.F == 2 && (threads2_for(p.TX) > most || lds2_for(p.TX) > 64 * 1024))))
+            --p.TX;
     }
     if (p.TX > 1024 || p.TY > 256) return bad("tile sizes must be at most 1024 x 256");
     p.block = threads_for(p.TX);
@@ -246,6 +264,14 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         return bad("FP64 with the register pipeline needs tile_x * nz / V <= 512 threads");
     p.lds = lds_for(p.TX);
     if (p.lds > kMaxLds) return bad("tile too large: the LDS row ring and trip counts exceed 160 KiB");
+    if (p.F == 2) {
+        p.block2 = threads2_for(p.TX);
+        p.lds2 = lds2_for(p.TX);
+        if (p.block2 > most)
+            return bad(p.prec == LB_FP64 ? "fuse_steps 2 in FP64 needs (tile_x + 4) * nz / 4 <= 512 threads"
+                                         : "fuse_steps 2 needs (tile_x + 4) * nz / 4 <= 1024 threads");
+        if (p.lds2 > kMaxLds) return bad("tile too large for fuse_steps 2: its LDS rows and trip counts exceed 160 KiB");
+    }
 
     // tiles of every chunk, chunks in id order, tiles in raster order; every tile
     // row can become an item of its own
@@ -295,7 +321,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     p.off_sum = take(sizeof(double) * (kSumBlocks + 1));
     p.off_first = take(sizeof(ItemDesc) * 2 * static_cast<size_t>(p.nwg_cap));
     p.off_wstate = take(sizeof(WgState) * static_cast<size_t>(p.nwg_cap));
-    p.off_pstate = take(sizeof(WgState) * 2);
+    p.off_pstate = take(sizeof(WgState) * kStepSlots);
     p.ws_bytes = o;
     // pinned staging: measured loads, then the plan tables of an upload
     size_t h = 0;
@@ -707,11 +733,21 @@ int upload_items(lb_ctx* x) {
     return LB_OK;
 }
 
-// Launch of one balanced step (either form); slot is the step's number mod 4.
-int launch_balanced(lb_ctx* x, int slot, hipStream_t s) {
+// Steps a balanced launch takes when `left` steps remain: two when the plan
+// fuses steps and at least two remain, else one.
+int launch_span(const Plan& p, int left) { return p.F == 2 && left >= 2 ? 2 : 1; }
+
+// Field copies written by n balanced steps launched in spans of launch_span.
+int launches_for(const Plan& p, int n) { return p.F == 2 ? n / 2 + n % 2 : n; }
+
+// One balanced launch of n (= launch_span) steps, in the plan's form; slot is the
+// number mod 4 of its first step.
+int launch_balanced(lb_ctx* x, int slot, int n, hipStream_t s) {
     const Plan& p = x->plan;
-    if (p.IG)
-        return launch_items(x->args, p.prec, p.vec, static_cast<int>(x->items.size()), p.block, p.lds, slot, s);
+    const int nitems = static_cast<int>(x->items.size());
+    if (p.IG && n == 2) return launch_items2(x->args, p.prec, p.vec, nitems, p.block2, p.lds2, slot, s);
+    if (n != 1) return static_cast<int>(hipErrorInvalidValue);
+    if (p.IG) return launch_items(x->args, p.prec, p.vec, nitems, p.block, p.lds, slot, s);
     return launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, s);
 }
 
@@ -720,10 +756,13 @@ int capture(lb_ctx* x, int mode, int nsteps, hipGraphExec_t* out, int slot0 = 0)
     hipGraph_t g = nullptr;
     HIP_TRY(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
     int rc = 0;
-    for (int i = 0; i < nsteps && rc == 0; ++i) {
+    for (int i = 0; i < nsteps && rc == 0;) {
         if (mode == LB_PERSISTENT) {
-            rc = launch_balanced(x, (slot0 + i) & 3, x->cap);
+            const int n = launch_span(p, nsteps - i);
+            rc = launch_balanced(x, (slot0 + i) & 3, n, x->cap);
+            i += n;
         } else {
+            ++i;
             for (int32_t c = 0; c < p.C && rc == 0; ++c)
                 rc = launch_plain_chunk(x->args, p.prec, p.vec, c, x->item_off[c + 1] - x->item_off[c],
                                         p.block, p.lds, x->cap);
@@ -789,6 +828,7 @@ void lb_config_default(lb_config* c) {
     c->queue_order = 0;
     c->hot_cut = 200;
     c->item_grid = 0;
+    c->fuse_steps = 0;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
@@ -906,6 +946,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.tile_x = P.TX;
     a.tile_y = P.TY;
     a.block = P.block;
+    a.block2 = P.block2;
     a.stage_rows = P.B;
     a.reg_depth = P.RD;
     a.march = P.M;
@@ -991,11 +1032,12 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
     const int fail_at = forced_launch_failure();
     int launches = 0;
     auto forced = [&]() { return fail_at > 0 && ++launches == fail_at; };
-    // every launch moves the field to the other copy (a launch of one step at a time)
-    auto done = [&](int n) {
+    // every launch moves the field to the other copy: n steps take n launches,
+    // or launches_for(n) when balanced launches fuse steps
+    auto done = [&](int n, bool balanced) {
         x->steps += n;
         x->window_steps += n;
-        x->cur ^= (n & 1);
+        x->cur ^= ((balanced ? launches_for(p, n) : n) & 1);
     };
     auto launch_failed = [&](const char* what, int e, bool partial) {
         if (partial) x->broken = true;
@@ -1032,15 +1074,22 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
                         return rc;
                     if (forced()) return launch_failed("hipGraphLaunch", 0, false);
                     if (int e = hipGraphLaunch(x->g_items[sl], x->stream)) return launch_failed("hipGraphLaunch", e, false);
-                    done(R);
+                    done(R, true);
                 }
-                for (int i = 0; i < nsteps % R; ++i) {
+                for (int i = 0; i < nsteps % R;) {
                     const int sl = static_cast<int>(x->steps & 3);
-                    if (!x->g_items1[sl] && (rc = capture(x, LB_PERSISTENT, 1, &x->g_items1[sl], sl)) != LB_OK)
-                        return rc;
-                    if (forced()) return launch_failed("hipGraphLaunch", 0, false);
-                    if (int e = hipGraphLaunch(x->g_items1[sl], x->stream)) return launch_failed("hipGraphLaunch", e, false);
-                    done(1);
+                    const int n = launch_span(p, nsteps % R - i);
+                    if (n == 2) {   // a pair of the remainder: one launch, not worth a graph
+                        if (forced()) return launch_failed("launch_balanced", 0, false);
+                        if (int e = launch_balanced(x, sl, 2, x->stream)) return launch_failed("launch_balanced", e, false);
+                    } else {
+                        if (!x->g_items1[sl] && (rc = capture(x, LB_PERSISTENT, 1, &x->g_items1[sl], sl)) != LB_OK)
+                            return rc;
+                        if (forced()) return launch_failed("hipGraphLaunch", 0, false);
+                        if (int e = hipGraphLaunch(x->g_items1[sl], x->stream)) return launch_failed("hipGraphLaunch", e, false);
+                    }
+                    done(n, true);
+                    i += n;
                 }
                 break;
             }
@@ -1049,21 +1098,23 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
             for (int i = 0; i < nsteps / R; ++i) {
                 if (forced()) return launch_failed("hipGraphLaunch", 0, false);
                 if (int e = hipGraphLaunch(x->g_pers, x->stream)) return launch_failed("hipGraphLaunch", e, false);
-                done(R);
+                done(R, true);
             }
             for (int i = 0; i < nsteps % R; ++i) {
                 if (forced()) return launch_failed("hipGraphLaunch", 0, false);
                 if (int e = hipGraphLaunch(x->g_pers1, x->stream)) return launch_failed("hipGraphLaunch", e, false);
-                done(1);
+                done(1, true);
             }
             break;
         }
         case LB_PERSISTENT_EAGER:
-            for (int i = 0; i < nsteps; ++i) {
+            for (int i = 0; i < nsteps;) {
+                const int n = launch_span(p, nsteps - i);
                 if (forced()) return launch_failed("launch_balanced", 0, false);
-                if (int e = launch_balanced(x, static_cast<int>(x->steps & 3), x->stream))
+                if (int e = launch_balanced(x, static_cast<int>(x->steps & 3), n, x->stream))
                     return launch_failed("launch_balanced", e, false);
-                done(1);
+                done(n, true);
+                i += n;
             }
             break;
         case LB_PLAIN_GRAPH:
@@ -1078,7 +1129,7 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
             for (int i = 0; i < nsteps; ++i) {
                 if (forced()) return launch_failed("hipGraphLaunch", 0, false);
                 if (int e = hipGraphLaunch(x->g_plain, x->stream)) return launch_failed("hipGraphLaunch", e, false);
-                done(1);
+                done(1, false);
             }
             break;
         default:  // LB_PLAIN: C launches and a finisher per step
@@ -1092,7 +1143,7 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
                                           : launch_finish(x->args, x->stream);
                     if (e) return launch_failed(c < p.C ? "launch_plain_chunk" : "launch_finish", e, partial);
                 }
-                done(1);
+                done(1, false);
             }
     }
     return LB_OK;
@@ -1278,6 +1329,7 @@ int lb_stats(lb_ctx* x, lb_stats_t* out) {
     out->nqueues = p.Q;
     out->nwg = p.nwg;
     out->block = p.block;
+    out->block2 = p.block2;
     out->tile_x = p.TX;
     out->tile_y = p.TY;
     out->clock_hz = x->clock_hz;

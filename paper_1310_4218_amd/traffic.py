@@ -1,4 +1,4 @@
-"""HBM traffic of the step kernel (k_items or k_persistent) from two rocprofv3 counter runs.
+"""HBM traffic of the step kernel (k_items2, k_items or k_persistent) from two rocprofv3 counter runs.
 
     rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o run -- python3 bench.py --workload W \
         --no-cpu --no-plain --no-ablation --steps S --warmup 10 --calibration-copy 512
@@ -130,9 +130,10 @@ def main(argv=None) -> int:
 
     fetch = read_counter(args.fetch, "FETCH_SIZE")
     write = read_counter(args.write, "WRITE_SIZE")
-    # the step kernel: one workgroup per item if the run launched it, else the persistent one
-    kname = "k_items" if pick(fetch, ["k_items"]) else "k_persistent"
-    kf, kw = pick(fetch, [kname]), pick(write, [kname])
+    # the step kernel: one workgroup per item, two steps or one per launch, if the run
+    # launched it, else the persistent one
+    kname = next((k for k in ("k_items2", "k_items") if pick(fetch, [k + "<"])), "k_persistent")
+    kf, kw = pick(fetch, [kname + "<"]), pick(write, [kname + "<"])
     cf, cw = pick(fetch, ["copy"]), pick(write, ["copy"])
     if not kf or not kw or not cf or not cw:
         print("missing dispatches: persistent", len(kf), len(kw), "copy", len(cf), len(cw),

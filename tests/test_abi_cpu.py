@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_struct_layout_and_version(lib):
-    assert lib.lb_abi_version() == 3
+    assert lib.lb_abi_version() == 4
     assert lib.lb_config_bytes() == C.sizeof(_abi.LbConfig)
     assert lib.lb_stats_bytes() == C.sizeof(_abi.LbStats)
 
@@ -80,12 +80,16 @@ def test_query_rejects_bad_config(lib, field, value, msg):
     (dict(march=4, precision=2, tile_x=70), "FP64 march"), (dict(march=8, tile_x=200), "1024 threads"),
     (dict(item_grid=1), "item_grid needs the column-march"), (dict(item_grid=2, march=2), "item_grid must be"),
     (dict(queue_order=3), "queue_order must be"), (dict(hot_cut=-1), "hot_cut"),
+    (dict(fuse_steps=3), "fuse_steps must be"), (dict(fuse_steps=2, march=2), "fuse_steps 2 needs item_grid"),
+    (dict(fuse_steps=2, march=2, item_grid=1, precision=2, tile_x=61), "fuse_steps 2 in FP64"),
+    (dict(fuse_steps=2, march=2, item_grid=1, tile_x=125), "fuse_steps 2 needs (tile_x + 4)"),
 ])
 def test_query_rejects_bad_pipeline(lib, over, msg):
     """Register pipeline depths are 2, 4 or 8 rows; the deep ones need V = 4 and
     workgroups of at most 512 threads, and depth 8 is FP32 only.  The column march
     takes 2, 4 or 8 rows in flight, needs V = 4 and (tile_x + 2) * nz / 4 threads, at
-    most 512 in FP64."""
+    most 512 in FP64; two steps per launch need item_grid 1 and (tile_x + 4) * nz / 4
+    threads.  (64x64x32: tile_x 61 and 125 fit one step per launch but not two.)"""
     cfg, keep = _abi.config_from_workload(W.small())
     for k, v in over.items():
         setattr(cfg, k, v)
@@ -105,6 +109,7 @@ def test_vertical_layouts(lib):
     assert e.value.code == _abi.LB_E_UNSUPPORTED
     _abi.query(_abi.config_from_workload(wl, march=2)[0])
     _abi.query(_abi.config_from_workload(wl, march=4, item_grid=1, tile_x=14)[0])
+    _abi.query(_abi.config_from_workload(wl, march=4, item_grid=1, fuse_steps=2, tile_x=14)[0])
     with pytest.raises(LbError) as e:
         _abi.query(_abi.config_from_workload(W.small().replace(nz=260, vertical=1), march=2)[0])
     assert e.value.code == _abi.LB_E_UNSUPPORTED

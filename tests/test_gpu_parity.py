@@ -141,6 +141,8 @@ def test_launch_forms_bit_identical():
     dict(march=2, item_grid=1), dict(march=4, item_grid=1, tile_x=5, tile_y=3),
     dict(march=8, item_grid=1, tile_y=11, queue_order=1), dict(march=4, item_grid=1, nslots=16, nqueues=16),
     dict(march=2, queue_order=1, tile_x=4, tile_y=3),
+    dict(march=4, item_grid=1, fuse_steps=2), dict(march=2, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3),
+    dict(march=8, item_grid=1, fuse_steps=2, tile_y=11, queue_order=1),
 ])
 def test_schedule_invariance(over):
     wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=3)
@@ -177,6 +179,71 @@ def test_item_grid_mixed_launch_forms_fp64():
     np.testing.assert_allclose(g.checksums(12), ck, rtol=1e-12, atol=1e-9)
     assert np.all(g.visits() == 12)
     g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_steps_mixed_launch_forms(precision):
+    """Two steps per launch: each item reads its cells and a two-cell halo once,
+    computes the first step on a one-cell ring around it as well, and writes the second
+    step.  Runs of fused launches, single steps (odd counts, odd graph lengths), every
+    other launch form and a rebalance, in one context: FP64 fields equal the oracle's bit
+    for bit and FP32 fields equal those of one step per launch; loads equal the oracle's,
+    per-step checksums agree with it, and every tile row is computed once per step."""
+    wl = mk(40, 36, 12, 4, 3, hot=((5, 4, 1, 2),), split="dirichlet", steps=16, nslots=5)
+    ref, work, ck, _ = oracle.run(wl, nsteps=16)
+    prog = [(2, "persistent_eager"), (1, "plain"), (4, "persistent"), ("measure", 7), ("rebalance", 0),
+            (3, "persistent_eager"), (1, "plain_graph"), (5, "persistent"), ("measure", 16)]
+
+    def run(**over):
+        g = Grid(wl, precision=precision, march=4, item_grid=1, graph_steps=3, tile_x=6, tile_y=5, **over)
+        loads = []
+        for n, mode in prog:
+            if n == "measure":
+                loads.append(g.measure("work"))
+            elif n == "rebalance":
+                g.rebalance("greedy")
+            else:
+                g.step(n, mode)
+        return g, loads
+
+    g, loads = run(fuse_steps=2)
+    np.testing.assert_array_equal(loads[0], work[:7].sum(axis=0))
+    np.testing.assert_array_equal(loads[1], work[7:].sum(axis=0))
+    assert np.all(g.visits() == 16)
+    q = gpu_fields(g)
+    if precision == "fp64":
+        np.testing.assert_array_equal(q, ref)
+        np.testing.assert_allclose(g.checksums(16), ck, rtol=1e-12, atol=1e-9)
+    else:
+        # the same FP32 values, summed in FP64 in another order: equal to rounding of the sums
+        one, _ = run()
+        np.testing.assert_array_equal(q, gpu_fields(one))
+        np.testing.assert_allclose(g.checksums(16), one.checksums(16), rtol=1e-12, atol=1e-9)
+        assert rel_err(q, ref) <= TOL
+        np.testing.assert_allclose(g.checksums(16), ck, rtol=TOL)
+        one.close()
+    g.close()
+
+
+def test_fused_steps_wide_tiles_and_small_grids_fp64():
+    """The fused launch where its halo wraps around a small grid more than once (a two-
+    cell halo on a grid narrower than a tile plus four columns, or shorter than three
+    rows), and with the widest tile an FP64 workgroup allows ((28 + 4) x 64 / 4 = 512
+    threads)."""
+    for shape, over in (((5, 3, 8, 1, 1), dict(tile_x=8, tile_y=4)), ((2, 7, 4, 2, 1), dict(tile_x=1, tile_y=2)),
+                        ((3, 1, 12, 1, 1), dict()), ((70, 40, 64, 2, 2), dict(tile_x=28, tile_y=9))):
+        nx, ny, nz, px, py = shape
+        say("fused", shape, over)
+        wl = mk(nx, ny, nz, px, py, hot=((nx // 2, ny // 2, 1, 1),), sigma=2.0, kmax=20, steps=5, nslots=2)
+        ref, work, _, _ = oracle.run(wl, nsteps=5)
+        g = Grid(wl, precision="fp64", march=2, item_grid=1, fuse_steps=2, **over)
+        if nz == 64:
+            assert g.stats()["block2"] == (over["tile_x"] + 4) * 16 == 512
+        g.step(5, "persistent_eager")
+        np.testing.assert_array_equal(gpu_fields(g), ref)
+        np.testing.assert_array_equal(g.measure("work"), work.sum(axis=0))
+        assert np.all(g.visits() == 5)
+        g.close()
 
 
 def test_measure_in_two_halves():
@@ -255,7 +322,8 @@ def test_ragged_fp64_bit_exact(shape):
             kmax=25, split="dirichlet" if px > 1 else "equal", steps=3, nslots=3)
     deep = (dict(tile_y=5, stage_rows=2), dict(tile_y=9, stage_rows=-4), dict(tile_x=3, stage_rows=-4),
             dict(march=2), dict(march=4, tile_x=3, tile_y=2), dict(march=8, tile_x=7, tile_y=9),
-            dict(march=2, item_grid=1), dict(march=4, item_grid=1, tile_x=3, tile_y=2))
+            dict(march=2, item_grid=1), dict(march=4, item_grid=1, tile_x=3, tile_y=2),
+            dict(march=2, item_grid=1, fuse_steps=2), dict(march=4, item_grid=1, fuse_steps=2, tile_x=3, tile_y=2))
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     for tiles in (dict(), dict(tile_x=3, tile_y=2), dict(stage_rows=-1)) + (deep if nz % 4 == 0 else (dict(tile_y=5),)):
         for mode in (("persistent", "plain") if "march" in tiles else ("persistent",)):
@@ -280,7 +348,8 @@ def test_fp64_register_pipeline_at_its_workgroup_limit():
 
 
 @pytest.mark.parametrize("over", [dict(), dict(march=4), dict(march=2, tile_x=5, tile_y=3),
-                                  dict(march=2, item_grid=1, tile_x=5, tile_y=3)])
+                                  dict(march=2, item_grid=1, tile_x=5, tile_y=3),
+                                  dict(march=2, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3)])
 def test_multi_field_fp64_bit_exact(over):
     wl = mk(24, 20, 8, 3, 2, steps=3).replace(nfields=3)
     g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
@@ -664,7 +733,8 @@ def test_study_load_sources():
 # ------------------------------------------------------------------ many fields (the paper's volume)
 @pytest.mark.parametrize("over", [dict(march=4, item_grid=1, tile_x=8, tile_y=24),
                                   dict(march=2, item_grid=1, tile_x=5, tile_y=7, queue_order=1),
-                                  dict(march=8, tile_x=6, tile_y=5), dict(stage_rows=-1)])
+                                  dict(march=8, tile_x=6, tile_y=5), dict(stage_rows=-1),
+                                  dict(march=4, item_grid=1, fuse_steps=2, tile_x=8, tile_y=24)])
 def test_many_fields_fp64_bit_exact(over):
     """Twelve fields sharing one cost field, in the launch shapes the multi-field benchmark
     uses: FP64 fields bit-identical to the oracle's, loads (counting every field) identical."""
@@ -713,7 +783,8 @@ def test_vertical_physics_fp64_bit_exact(nz):
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     for over in (dict(), dict(stage_rows=-1), dict(tile_x=5, tile_y=3)) + \
             ((dict(stage_rows=-4, tile_x=4), dict(march=2), dict(march=4, tile_x=3, tile_y=4),
-              dict(march=4, item_grid=1, tile_x=3, tile_y=4))
+              dict(march=4, item_grid=1, tile_x=3, tile_y=4),
+              dict(march=4, item_grid=1, fuse_steps=2, tile_x=3, tile_y=4))
              if nz % 4 == 0 else ()):
         g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
         np.testing.assert_array_equal(q, ref)
@@ -771,7 +842,9 @@ def test_vertical_physics_whole_columns_per_wave_fp64(nz):
     wl = mk(40, 36, nz, 4, 3, kmax=40, sigma=5.0, split="dirichlet", steps=3).replace(vertical=1)
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     for over in (dict(march=2), dict(march=4, tile_x=3, tile_y=4), dict(march=8, tile_x=7, tile_y=9),
-                 dict(march=4, item_grid=1, tile_x=5, tile_y=3), dict(march=2, item_grid=1)):
+                 dict(march=4, item_grid=1, tile_x=5, tile_y=3), dict(march=2, item_grid=1),
+                 dict(march=4, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3),
+                 dict(march=2, item_grid=1, fuse_steps=2)):
         for mode in ("persistent", "plain"):
             g, q, w = run_gpu(wl, 3, mode, precision="fp64", **over)
             np.testing.assert_array_equal(q, ref)
