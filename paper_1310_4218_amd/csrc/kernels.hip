@@ -641,22 +641,39 @@ __device__ __forceinline__ void cell_update(const DevArgs& a, const T* Lc, const
         physics_vec<KAHAN, T, V>(eps, k, q);
 }
 
-// Thread -> (column tcol, lane tzq of the column) of a march workgroup.
-// Dense: consecutive NQ threads per column.  With col_per_wave > 0 (the
-// vertical physics when NQ does not divide 64) every wave holds col_per_wave
-// whole columns in its first lanes and leaves the rest idle, so that a
-// column's lanes never straddle two waves.  Returns whether the lane is used.
-__device__ __forceinline__ bool march_lane(const DevArgs& a, int NQ, int& tcol, int& tzq) {
+// Thread -> (column tcol, lane tzq of the column) of a march workgroup whose
+// thread columns 0 .. TX + 2 HALO - 1 stream grid columns x0 - HALO + tcol.
+// Threads are grouped in column slots: dense, NQ consecutive threads per slot;
+// with col_per_wave > 0 (the vertical physics when NQ does not divide 64)
+// every wave holds col_per_wave whole slots in its first lanes and leaves the
+// rest idle, so that a column's lanes never straddle two waves.  Slots 0 ..
+// TX - 1 hold the item's own columns, the slots after them the halo columns,
+// innermost first, alternating left and right.  The item's columns thus fill
+// whole waves, and a wave that holds only halo columns skips the arithmetic
+// of the cells it does not compute (a wave issues its vector instructions for
+// all of its lanes, idle or not).  Returns whether the lane is used.
+template <int HALO>
+__device__ __forceinline__ bool march_lane(const DevArgs& a, int NQ, int TX, int& tcol, int& tzq) {
+    int slot;
+    bool used = true;
     if (a.col_per_wave > 0) {
         const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
         const int cw = lane / NQ;
-        tcol = (static_cast<int>(threadIdx.x) >> 6) * a.col_per_wave + cw;
+        slot = (static_cast<int>(threadIdx.x) >> 6) * a.col_per_wave + cw;
         tzq = lane - cw * NQ;
-        return cw < a.col_per_wave;
+        used = cw < a.col_per_wave;
+    } else {
+        slot = threadIdx.x / NQ;
+        tzq = threadIdx.x - slot * NQ;
     }
-    tcol = threadIdx.x / NQ;
-    tzq = threadIdx.x - tcol * NQ;
-    return true;
+    const int h = slot - TX;                  // halo slot: ring h / 2, left when even
+    if (h < 0)
+        tcol = slot + HALO;
+    else if (h < 2 * HALO)
+        tcol = (h & 1) ? TX + HALO + (h >> 1) : HALO - 1 - (h >> 1);
+    else
+        tcol = slot + 2 * HALO;               // past every column: streams nothing
+    return used;
 }
 
 // v mod n in [0, n) for v within a few multiples of n of the range
@@ -684,7 +701,7 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
     const int TX = a.tile_x;
     const int BS = a.block;                   // == blockDim.x (at least (TX + 2) columns)
     int tcol, tzq;
-    const bool lane_used = march_lane(a, NQ, tcol, tzq);
+    const bool lane_used = march_lane<1>(a, NQ, TX, tcol, tzq);
     const int zoff = tzq * V;
     const int x0 = d.x0, y0 = d.y0;
     const int w = d.wh & 0xffff;
@@ -800,7 +817,7 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
     const int TX = a.tile_x;
     const int BS = a.block2;                  // == blockDim.x (at least (TX + 4) columns)
     int tcol, tzq;
-    const bool lane_used = march_lane(a, NQ, tcol, tzq);
+    const bool lane_used = march_lane<2>(a, NQ, TX, tcol, tzq);
     const int zoff = tzq * V;
     const int x0 = d.x0, y0 = d.y0;
     const int w = d.wh & 0xffff;
