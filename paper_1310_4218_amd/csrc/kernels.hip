@@ -722,10 +722,17 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
         gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
         return (streams && i <= h) ? colbytes + static_cast<uint32_t>(gy) * rowbytes : kOutOfRange;
     };
+    int flat = 1;                             // every trip count this thread looked up is kmin
     for (int i = threadIdx.x; i < w * h; i += BS) {
         const int r = i / w, cx = i - r * w;
-        kbuf[r * TX + cx] = column_k(a, hcx, hcy, x0 + cx, y0 + r);
+        const int k = column_k(a, hcx, hcy, x0 + cx, y0 + r);
+        kbuf[r * TX + cx] = k;
+        flat &= k == a.kmin;
     }
+    // all of the item's trip counts kmin: the physics loop runs on a scalar count
+    // (the reduction also orders the table stores before their reads)
+    const bool uniform = __builtin_amdgcn_readfirstlane(__syncthreads_and(flat)) != 0;
+    const int ku = a.kmin;
     double chk = 0.0;
     int ksum = 0, krows = 0;                  // trip counts and rows of this thread's column (field 0)
     int lpar = 0;                             // LDS buffer of the next row
@@ -756,10 +763,17 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
                     Vec<T, V> o;
                     uint32_t so = kOutOfRange;
                     if (active) {
-                        const int k = kbuf[r * TX + tcol - 1];
+                        int k;
                         T q[V];
-                        cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, k, cc, cn,
-                                                 eps, q);
+                        if (uniform) {
+                            k = ku;
+                            cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, ku, cc, cn,
+                                                     eps, q);
+                        } else {
+                            k = kbuf[r * TX + tcol - 1];
+                            cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, k, cc, cn,
+                                                     eps, q);
+                        }
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             o.v[v] = q[v];
@@ -839,14 +853,24 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
         if (!streams || i > h + 1) return kOutOfRange;
         return colbytes + static_cast<uint32_t>(wrap_near(y0 + i, ny)) * rowbytes;
     };
+    int flat = 1;                             // every trip count this thread looked up is kmin
     for (int i = threadIdx.x; i < (w + 2) * (h + 2); i += BS) {
         const int r = i / (w + 2), cx = i - r * (w + 2);
-        kb1[r * K1 + cx] = column_k(a, hc1x, hc1y, wrap_near(x0 - 1 + cx, nx), wrap_near(y0 - 1 + r, ny));
+        const int k = column_k(a, hc1x, hc1y, wrap_near(x0 - 1 + cx, nx), wrap_near(y0 - 1 + r, ny));
+        kb1[r * K1 + cx] = k;
+        flat &= k == a.kmin;
     }
     for (int i = threadIdx.x; i < w * h; i += BS) {
         const int r = i / w, cx = i - r * w;
-        kb2[r * TX + cx] = column_k(a, hc2x, hc2y, x0 + cx, y0 + r);
+        const int k = column_k(a, hc2x, hc2y, x0 + cx, y0 + r);
+        kb2[r * TX + cx] = k;
+        flat &= k == a.kmin;
     }
+    // When every trip count of the item (both steps, ring included) is kmin, the
+    // physics takes kmin as a workgroup-uniform scalar: a loop without per-lane
+    // control.  (The reduction also orders the table stores before their reads.)
+    const bool uniform = __builtin_amdgcn_readfirstlane(__syncthreads_and(flat)) != 0;
+    const int ku = a.kmin;
     const bool own1 = tcol >= 2 && tcol <= w + 1;   // an item column (step s + 1 counts it)
     double chk1 = 0.0, chk2 = 0.0;
     int ksum = 0, krows = 0;                  // trip counts and rows of this thread's column (field 0)
@@ -877,10 +901,17 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
                     R[j] = bload<T, V>(in, row_off(n + D));
                     Vec<T, V> s1n{};
                     if (act1) {
-                        const int k = kb1[n * K1 + tcol - 1];
+                        int k;
                         T q[V];
-                        cell_update<T, V, KAHAN>(a, LA + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, k, cc, cn,
-                                                 eps, q);
+                        if (uniform) {
+                            k = ku;
+                            cell_update<T, V, KAHAN>(a, LA + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, ku, cc, cn,
+                                                     eps, q);
+                        } else {
+                            k = kb1[n * K1 + tcol - 1];
+                            cell_update<T, V, KAHAN>(a, LA + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, k, cc, cn,
+                                                     eps, q);
+                        }
                         const bool own = own1 && i >= 0 && i < h;
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
@@ -896,10 +927,17 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
                         Vec<T, V> o;
                         uint32_t so = kOutOfRange;
                         if (act2) {
-                            const int k = kb2[(i - 1) * TX + tcol - 2];
+                            int k;
                             T q[V];
-                            cell_update<T, V, KAHAN>(a, LB + tcol * nz + zoff, s1c, s1m, s1n, tzq, NQ, nz, k,
-                                                     cc, cn, eps, q);
+                            if (uniform) {
+                                k = ku;
+                                cell_update<T, V, KAHAN>(a, LB + tcol * nz + zoff, s1c, s1m, s1n, tzq, NQ, nz, ku,
+                                                         cc, cn, eps, q);
+                            } else {
+                                k = kb2[(i - 1) * TX + tcol - 2];
+                                cell_update<T, V, KAHAN>(a, LB + tcol * nz + zoff, s1c, s1m, s1n, tzq, NQ, nz, k,
+                                                         cc, cn, eps, q);
+                            }
 #pragma unroll
                             for (int v = 0; v < V; ++v) {
                                 o.v[v] = q[v];
