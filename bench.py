@@ -46,6 +46,9 @@ if ROOT not in sys.path:
 from paper_1310_4218_amd.traffic import kernel_source_hash  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# MI355X FP32 vector peak (256 CUs x 64 lanes x 2 FMA flops x 2 (packed) x 2.4 GHz)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 METRIC = "grid point-updates/s and max/avg chunk-load ratio, balanced vs plain, 1 MI355X"
 # Steps of a window are launched one by one (LB_PERSISTENT_EAGER): after each
 # rebalance the first step then starts as soon as its launch is queued, where
@@ -367,9 +370,37 @@ def main(argv=None) -> int:
     hbm_resident = bytes_per_launch > 256 * 2 ** 20
     kernel_launch_s = bal["kernel_s"] / bal["launches"]
     achieved = bytes_per_launch / kernel_launch_s / 1e9
-    kname = ("k_items2" if params.get("fuse_steps") == 2 else "k_items") if params.get("item_grid") \
-        else "k_persistent"
+    fused = params.get("fuse_steps") == 2
+    kname = ("k_items2" if fused else "k_items") if params.get("item_grid") else "k_persistent"
+    steps_per_launch = args.steps / bal["launches"]
+    # Algorithmic floating-point operations of one step: 9 per point update for the
+    # stencil and its combination (6 additions, cc*c + cn*sum) and 5 per iteration of the
+    # column physics (q*q*q, the difference, the scaling by eps, the sum).  The trip
+    # counts summed over the grid follow from the measured work loads of the timed
+    # windows (work = nz * nfields * (alpha * columns + sum of trip counts), R steps each).
+    cols = wl.nx * wl.ny
+    ksum_step = (float(np.mean([w.sum() for w in loads])) / (wl.nz * wl.nfields) - wl.alpha_work * cols * R) / R \
+        if loads else None
+    flops_step = 9.0 * cells + 5.0 * wl.nz * wl.nfields * ksum_step if ksum_step is not None else None
+    flops_launch = flops_step * steps_per_launch if flops_step is not None else None
+    tflops = flops_launch / kernel_launch_s / 1e12 if flops_launch is not None else None
+    alu_peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     st = bal["stats"]
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": measured_traffic(args.workload, args.precision,
+                                       {k: v for k, v in params.items() if k != "precision"}),
+           "bytes_per_launch": bytes_per_launch}
+    alu = {"achieved": tflops, "peak": alu_peak, "unit": "TFLOP/s",
+           "frac": tflops / alu_peak if tflops is not None else None, "flops_per_launch": flops_launch}
+    # The two-step launch reads and writes each cell once for two steps and
+    # computes the first step on a ring around each item as well: it is bound by
+    # vector-instruction issue (hardware counters), not by memory.  One step per
+    # launch streams the field at about the device's copy rate.
+    if fused and hbm_resident:
+        roof = dict(bound="alu", **alu, traffic=hbm["traffic"], hbm=hbm)
+    else:
+        roof = dict(bound="hbm" if hbm_resident else "latency", **hbm, alu=alu)
+    roof.update(kernel=kname, steps_per_launch=steps_per_launch, us_per_launch_events=kernel_launch_s * 1e6)
 
     out = {
         "metric": METRIC,
@@ -409,19 +440,7 @@ def main(argv=None) -> int:
             "host_us_per_window": bal["host"],
         },
         "ablation_map_only": ablation,
-        "roofline": {
-            "bound": "hbm" if hbm_resident else "latency",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, args.precision,
-                                        {k: v for k, v in params.items() if k != "precision"}),
-            "kernel": kname,
-            "bytes_per_launch": bytes_per_launch,
-            "steps_per_launch": args.steps / bal["launches"],
-            "us_per_launch_events": kernel_launch_s * 1e6,
-        },
+        "roofline": roof,
     }
     if args.calibration_copy > 0:
         n = int(args.calibration_copy * 2 ** 20)

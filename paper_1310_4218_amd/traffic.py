@@ -132,7 +132,8 @@ def main(argv=None) -> int:
     write = read_counter(args.write, "WRITE_SIZE")
     # the step kernel: one workgroup per item, two steps or one per launch, if the run
     # launched it, else the persistent one
-    kname = next((k for k in ("k_items2", "k_items") if pick(fetch, [k + "<"])), "k_persistent")
+    kname = next((k for k in ("k_items2", "k_items", "k_persistent_march", "k_persistent")
+                  if pick(fetch, [k + "<"])), "k_persistent")
     kf, kw = pick(fetch, [kname + "<"]), pick(write, [kname + "<"])
     cf, cw = pick(fetch, ["copy"]), pick(write, ["copy"])
     if not kf or not kw or not cf or not cw:
