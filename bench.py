@@ -46,8 +46,10 @@ if ROOT not in sys.path:
 from paper_1310_4218_amd.traffic import kernel_source_hash  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# MI355X FP32 vector peak (256 CUs x 64 lanes x 2 FMA flops x 2 (packed) x 2.4 GHz)
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Vector ALU peaks of the MI355X: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6
+# TFLOP/s in FP32 and in FP64.  The FP32 figure of 157.3 needs packed FP32 (two FMAs per
+# lane and instruction), which this build disables (-packed-fp32-ops off).
+FP32_VECTOR_PEAK_TFLOPS = 78.6
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 METRIC = "grid point-updates/s and max/avg chunk-load ratio, balanced vs plain, 1 MI355X"
 # Steps of a window are launched one by one (LB_PERSISTENT_EAGER): after each
@@ -373,15 +375,15 @@ def main(argv=None) -> int:
     fused = params.get("fuse_steps") == 2
     kname = ("k_items2" if fused else "k_items") if params.get("item_grid") else "k_persistent"
     steps_per_launch = args.steps / bal["launches"]
-    # Algorithmic floating-point operations of one step: 9 per point update for the
-    # stencil and its combination (6 additions, cc*c + cn*sum) and 5 per iteration of the
+    # Algorithmic floating-point operations of one step: 8 per point update for the
+    # stencil and its combination (5 additions of the six neighbours, cc*c + cn*sum) and 5 per iteration of the
     # column physics (q*q*q, the difference, the scaling by eps, the sum).  The trip
     # counts summed over the grid follow from the measured work loads of the timed
     # windows (work = nz * nfields * (alpha * columns + sum of trip counts), R steps each).
     cols = wl.nx * wl.ny
     ksum_step = (float(np.mean([w.sum() for w in loads])) / (wl.nz * wl.nfields) - wl.alpha_work * cols * R) / R \
         if loads else None
-    flops_step = 9.0 * cells + 5.0 * wl.nz * wl.nfields * ksum_step if ksum_step is not None else None
+    flops_step = 8.0 * cells + 5.0 * wl.nz * wl.nfields * ksum_step if ksum_step is not None else None
     flops_launch = flops_step * steps_per_launch if flops_step is not None else None
     tflops = flops_launch / kernel_launch_s / 1e12 if flops_launch is not None else None
     alu_peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
