@@ -722,19 +722,24 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
         gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
         return (streams && i <= h) ? colbytes + static_cast<uint32_t>(gy) * rowbytes : kOutOfRange;
     };
+    // trip counts of the item's columns, looked up once per item; the item's work
+    // (k of every column, and the number of columns, each nz * nfields times) is
+    // summed here as well
     int flat = 1;                             // every trip count this thread looked up is kmin
+    int ksum = 0, kcols = 0;
     for (int i = threadIdx.x; i < w * h; i += BS) {
         const int r = i / w, cx = i - r * w;
         const int k = column_k(a, hcx, hcy, x0 + cx, y0 + r);
         kbuf[r * TX + cx] = k;
         flat &= k == a.kmin;
+        ksum += k;
+        ++kcols;
     }
     // all of the item's trip counts kmin: the physics loop runs on a scalar count
     // (the reduction also orders the table stores before their reads)
     const bool uniform = __builtin_amdgcn_readfirstlane(__syncthreads_and(flat)) != 0;
     const int ku = a.kmin;
     double chk = 0.0;
-    int ksum = 0, krows = 0;                  // trip counts and rows of this thread's column (field 0)
     int lpar = 0;                             // LDS buffer of the next row
     for (int f = 0; f < a.nfields; ++f) {
         const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
@@ -763,25 +768,17 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
                     Vec<T, V> o;
                     uint32_t so = kOutOfRange;
                     if (active) {
-                        int k;
                         T q[V];
-                        if (uniform) {
-                            k = ku;
+                        if (uniform)
                             cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, ku, cc, cn,
                                                      eps, q);
-                        } else {
-                            k = kbuf[r * TX + tcol - 1];
-                            cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, k, cc, cn,
-                                                     eps, q);
-                        }
+                        else
+                            cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz,
+                                                     kbuf[r * TX + tcol - 1], cc, cn, eps, q);
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             o.v[v] = q[v];
                             chk += static_cast<double>(q[v]);
-                        }
-                        if (f == 0 && tzq == 0) {
-                            ksum += k;
-                            ++krows;
                         }
                         int gy = y0 + r;
                         gy = gy >= ny ? gy - ny : gy;
@@ -798,7 +795,7 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
         }
     }
     double work = static_cast<double>(nz) * static_cast<double>(a.nfields) *
-                  (static_cast<double>(a.alpha) * static_cast<double>(krows) + static_cast<double>(ksum));
+                  (static_cast<double>(a.alpha) * static_cast<double>(kcols) + static_cast<double>(ksum));
     block_sum2(chk, work, red, BS);
     ItemOut o;
     o.checksum = chk;
@@ -853,28 +850,38 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
         if (!streams || i > h + 1) return kOutOfRange;
         return colbytes + static_cast<uint32_t>(wrap_near(y0 + i, ny)) * rowbytes;
     };
+    // Trip counts of both steps, looked up once per item.  The item's work (its own
+    // columns in both steps) is summed here as well: k of every own column, and
+    // the number of own columns, each taken nz * nfields times.
     int flat = 1;                             // every trip count this thread looked up is kmin
+    int ksum = 0, kcols = 0;
     for (int i = threadIdx.x; i < (w + 2) * (h + 2); i += BS) {
         const int r = i / (w + 2), cx = i - r * (w + 2);
         const int k = column_k(a, hc1x, hc1y, wrap_near(x0 - 1 + cx, nx), wrap_near(y0 - 1 + r, ny));
         kb1[r * K1 + cx] = k;
         flat &= k == a.kmin;
+        if (r >= 1 && r <= h && cx >= 1 && cx <= w) {
+            ksum += k;
+            ++kcols;
+        }
     }
     for (int i = threadIdx.x; i < w * h; i += BS) {
         const int r = i / w, cx = i - r * w;
         const int k = column_k(a, hc2x, hc2y, x0 + cx, y0 + r);
         kb2[r * TX + cx] = k;
         flat &= k == a.kmin;
+        ksum += k;
+        ++kcols;
     }
     // When every trip count of the item (both steps, ring included) is kmin, the
     // physics takes kmin as a workgroup-uniform scalar: a loop without per-lane
     // control.  (The reduction also orders the table stores before their reads.)
     const bool uniform = __builtin_amdgcn_readfirstlane(__syncthreads_and(flat)) != 0;
     const int ku = a.kmin;
-    const bool own1 = tcol >= 2 && tcol <= w + 1;   // an item column (step s + 1 counts it)
+    T* const lrow = lds + tcol * nz + zoff;   // this thread's V levels in LDS row buffer 0
+    int par = 0;                              // LDS buffers of the next row (the parity runs on
+                                              // across fields: consecutive rows never share one)
     double chk1 = 0.0, chk2 = 0.0;
-    int ksum = 0, krows = 0;                  // trip counts and rows of this thread's column (field 0)
-    int par = 0;                              // LDS buffers of the next row
     const int n_it = h + 2;                   // iteration n computes step s + 1 on row n - 1
     for (int f = 0; f < a.nfields; ++f) {
         const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
@@ -891,61 +898,41 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
                 const int n = n0 + j;
                 if (n < n_it) {
                     const int i = n - 1;
-                    T* LA = lds + par * RL;           // step s, row i
-                    T* LB = lds + (2 + par) * RL;     // step s + 1, row i - 1
+                    T* const LA = lrow + par * RL;         // step s, row i
+                    T* const LB = lrow + (2 + par) * RL;   // step s + 1, row i - 1
                     par ^= 1;
-                    if (streams) st<T, V>(LA + tcol * nz + zoff, c);
-                    if (act1) st<T, V>(LB + tcol * nz + zoff, s1c);
+                    if (streams) st<T, V>(LA, c);
+                    if (act1) st<T, V>(LB, s1c);
                     __syncthreads();
                     const Vec<T, V> yp = R[j];
                     R[j] = bload<T, V>(in, row_off(n + D));
-                    Vec<T, V> s1n{};
+                    Vec<T, V> s1n;                    // (used only where act1 sets it)
                     if (act1) {
-                        int k;
                         T q[V];
-                        if (uniform) {
-                            k = ku;
-                            cell_update<T, V, KAHAN>(a, LA + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, ku, cc, cn,
-                                                     eps, q);
-                        } else {
-                            k = kb1[n * K1 + tcol - 1];
-                            cell_update<T, V, KAHAN>(a, LA + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, k, cc, cn,
-                                                     eps, q);
-                        }
-                        const bool own = own1 && i >= 0 && i < h;
+                        if (uniform)
+                            cell_update<T, V, KAHAN>(a, LA, c, ym, yp, tzq, NQ, nz, ku, cc, cn, eps, q);
+                        else
+                            cell_update<T, V, KAHAN>(a, LA, c, ym, yp, tzq, NQ, nz, kb1[n * K1 + tcol - 1], cc,
+                                                     cn, eps, q);
 #pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            s1n.v[v] = q[v];
-                            if (own) chk1 += static_cast<double>(q[v]);
-                        }
-                        if (own && f == 0 && tzq == 0) {
-                            ksum += k;
-                            ++krows;
-                        }
+                        for (int v = 0; v < V; ++v) s1n.v[v] = q[v];
                     }
                     if (i >= 1) {                     // step s + 2 on row i - 1
                         Vec<T, V> o;
                         uint32_t so = kOutOfRange;
                         if (act2) {
-                            int k;
                             T q[V];
-                            if (uniform) {
-                                k = ku;
-                                cell_update<T, V, KAHAN>(a, LB + tcol * nz + zoff, s1c, s1m, s1n, tzq, NQ, nz, ku,
-                                                         cc, cn, eps, q);
-                            } else {
-                                k = kb2[(i - 1) * TX + tcol - 2];
-                                cell_update<T, V, KAHAN>(a, LB + tcol * nz + zoff, s1c, s1m, s1n, tzq, NQ, nz, k,
-                                                         cc, cn, eps, q);
-                            }
+                            if (uniform)
+                                cell_update<T, V, KAHAN>(a, LB, s1c, s1m, s1n, tzq, NQ, nz, ku, cc, cn, eps, q);
+                            else
+                                cell_update<T, V, KAHAN>(a, LB, s1c, s1m, s1n, tzq, NQ, nz,
+                                                         kb2[(i - 1) * TX + tcol - 2], cc, cn, eps, q);
+                            // the item's own cells: step s + 1 (row i - 1, as read here), step s + 2
 #pragma unroll
                             for (int v = 0; v < V; ++v) {
                                 o.v[v] = q[v];
+                                chk1 += static_cast<double>(s1c.v[v]);
                                 chk2 += static_cast<double>(q[v]);
-                            }
-                            if (f == 0 && tzq == 0) {
-                                ksum += k;
-                                ++krows;
                             }
                             so = colbytes + static_cast<uint32_t>(y0 + i - 1) * rowbytes;
                         }
@@ -963,7 +950,7 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
         }
     }
     double work = static_cast<double>(nz) * static_cast<double>(a.nfields) *
-                  (static_cast<double>(a.alpha) * static_cast<double>(krows) + static_cast<double>(ksum));
+                  (static_cast<double>(a.alpha) * static_cast<double>(kcols) + static_cast<double>(ksum));
     block_sum3(chk1, chk2, work, red, BS);
     ItemOut2 o;
     o.checksum1 = chk1;
