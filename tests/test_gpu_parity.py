@@ -225,6 +225,26 @@ def test_fused_steps_mixed_launch_forms(precision):
     g.close()
 
 
+def test_fused_steps_graph_replays_fp64():
+    """Graphs of two-step launches replayed many times (each captured for the step
+    slot it starts at), with eager launches and field reads between the replays: the
+    fields after every group equal the oracle's, bit for bit."""
+    wl = mk(40, 36, 12, 4, 3, hot=((7, 30, 1, 1),), split="dirichlet", steps=14, nslots=5)
+    ref = {}
+    for n in (4, 8, 12, 14):
+        ref[n], _, _, _ = oracle.run(wl, nsteps=n)
+    g = Grid(wl, precision="fp64", march=4, item_grid=1, fuse_steps=2, graph_steps=2, tile_x=5, tile_y=4)
+    done = 0
+    for n, mode in ((4, "persistent"), (4, "persistent"), (1, "persistent_eager"), (3, "persistent"),
+                    (2, "persistent")):
+        g.step(n, mode)
+        done += n
+        if done in ref:
+            np.testing.assert_array_equal(gpu_fields(g), ref[done])
+    assert done == 14 and np.all(g.visits() == 14)
+    g.close()
+
+
 def test_fused_steps_wide_tiles_and_small_grids_fp64():
     """The fused launch where its halo wraps around a small grid more than once (a two-
     cell halo on a grid narrower than a tile plus four columns, or shorter than three
