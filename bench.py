@@ -394,15 +394,15 @@ def main(argv=None) -> int:
            "bytes_per_launch": bytes_per_launch}
     alu = {"achieved": tflops, "peak": alu_peak, "unit": "TFLOP/s",
            "frac": tflops / alu_peak if tflops is not None else None, "flops_per_launch": flops_launch}
-    # The two-step launch reads and writes each cell once for two steps and
-    # computes the first step on a ring around each item as well: it is bound by
-    # vector-instruction issue (hardware counters), not by memory.  One step per
-    # launch streams the field at about the device's copy rate.
-    if fused and hbm_resident:
-        roof = dict(bound="alu", **alu, traffic=hbm["traffic"], hbm=hbm)
-    else:
-        roof = dict(bound="hbm" if hbm_resident else "latency", **hbm, alu=alu)
-    roof.update(kernel=kname, steps_per_launch=steps_per_launch, us_per_launch_events=kernel_launch_s * 1e6)
+    # HBM-resident grids are reported against HBM: a launch must read every cell and
+    # write it once, whether it takes one step or two.  A launch of two steps does
+    # that once for two steps, so its fraction per step-equivalent is twice the
+    # per-launch one (and can exceed 1).  The ALU view is reported beside it: the
+    # two-step launch also keeps the vector units busy (hardware counters).
+    roof = dict(bound="hbm" if hbm_resident else "latency", **hbm, alu=alu)
+    roof.update(kernel=kname, steps_per_launch=steps_per_launch,
+                frac_per_step_equivalent=hbm["frac"] * steps_per_launch,
+                us_per_launch_events=kernel_launch_s * 1e6)
 
     out = {
         "metric": METRIC,
