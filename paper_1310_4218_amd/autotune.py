@@ -34,7 +34,7 @@ SPACE = {
     "queue_order": [0, 1],        # 1: hot items longest first, the rest by position
     "hot_cut": [200, 120, 150, 300, 500],   # queue_order 1: hot above this % of the mean
     "tile_x": [8, 16, 32, 64],
-    "tile_y": [2, 4, 8, 12, 16, 24, 32],
+    "tile_y": [2, 4, 8, 12, 16, 24, 32, 40, 48, 64],
     "nqueues": [1, 8, 32, 256],
     "wg_per_queue": [0],          # 0: fill the device (resident workgroups / queues)
     "item_split": [0, 1, 2, 3, 4, 5, 6, 8],
