@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 4
+#define LB_ABI_VERSION 5
 #define LB_MAX_HOT 4
 #define LB_NBUF 3
 
@@ -168,8 +168,12 @@ typedef struct {
                                 step s + 2, with the same bits as two single
                                 steps; an odd step count ends on a single
                                 step.  (tile_x + 4) * nz / 4 threads per
-                                workgroup, at most 512 in FP64.  0 or 1 = one
-                                step per launch (default)                     */
+                                workgroup, at most 512 in FP64.  3 = three
+                                steps at once (a three-cell halo, rings of two
+                                and one cells; (tile_x + 6) * nz / 4 threads),
+                                a remainder ending on a two- or one-step
+                                launch.  0 or 1 = one step per launch
+                                (default)                                     */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;
@@ -204,7 +208,9 @@ typedef struct {
                                 when balanced steps launch one workgroup per
                                 item (keyed by XCD and CU id; unused ones 0)  */
     int32_t block2;          /* threads per workgroup of a two-step launch
-                                (fuse_steps 2), else 0                        */
+                                (fuse_steps 2 or 3), else 0                   */
+    int32_t block3;          /* ... of a three-step launch (fuse_steps 3)     */
+    int32_t pad1;
 } lb_stats_t;
 
 /* Fill *cfg with the defaults listed in lb_config. */

@@ -67,6 +67,7 @@ class LbStats(C.Structure):
         ("measured_steps", C.c_int64),
         ("host_balance_us", C.c_double), ("host_plan_us", C.c_double),
         ("busy_slots", C.c_int32), ("block2", C.c_int32),
+        ("block3", C.c_int32), ("pad1", C.c_int32),
     ]
 
 

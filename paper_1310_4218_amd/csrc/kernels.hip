@@ -275,6 +275,36 @@ struct ItemOut2 {
     double work;       // work units of both steps (thread 0)
 };
 
+// Result of an item that advances its cells by three steps in one pass.
+struct ItemOut3 {
+    double checksum[3];  // sums of the item's outputs of each step (thread 0)
+    double work;         // work units of the three steps (thread 0)
+};
+
+// Four block-wide sums (valid in thread 0); red must hold 4 * kMaxBlock / 64
+// doubles of LDS.
+__device__ void block_sum4(double (&v)[4], double* red, int bs) {
+    constexpr int kW = kMaxBlock / kWave;
+    const int wave = threadIdx.x / kWave;
+    const int nwaves = (bs + kWave - 1) / kWave;
+    const int active = min(kWave, bs - wave * kWave);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i], active);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[i * kW + wave] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double t = 0.0;
+            for (int w = 0; w < nwaves; ++w) t += red[i * kW + w];
+            v[i] = t;
+        }
+    }
+    __syncthreads();
+}
+
 struct NoHook {
     __device__ void operator()() const {}
 };
@@ -959,6 +989,183 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
     return o;
 }
 
+// Three steps of one item in one pass: the two-step march above with one more
+// stage.  The workgroup streams grid columns x0 - 3 .. x0 + w + 2, rows -3 ..
+// h + 2 of the item (thread column tcol holds grid column x0 - 3 + tcol);
+// stage 1 computes step s + 1 on columns -2 .. w + 1 and rows -2 .. h + 1,
+// stage 2 step s + 2 on columns -1 .. w and rows -1 .. h one row behind, and
+// stage 3 step s + 3 on the item's own cells one row further behind.  Each
+// stage's current row goes through LDS (double-buffered) for the next stage's
+// x and z neighbours, one barrier per row; the same arithmetic as one step
+// per launch, so the same bits.  Only the item's own cells count in each
+// step's checksum and work.  hc1, hc2, hc3: hotspot centres of steps s, s + 1
+// and s + 2.
+template <typename T, int V, int KAHAN, int D>
+__device__ ItemOut3 process_item_march3(const DevArgs& a, const ItemDesc& d, const T* __restrict__ src,
+                                        T* __restrict__ dst, const int* hc1x, const int* hc1y,
+                                        const int* hc2x, const int* hc2y, const int* hc3x, const int* hc3y,
+                                        T* lds, double* red) {
+    const int nz = a.nz, nx = a.nx, ny = a.ny;
+    const int NQ = nz / V;
+    const int TX = a.tile_x;
+    const int BS = a.block3;                  // == blockDim.x (at least (TX + 6) columns)
+    int tcol, tzq;
+    const bool lane_used = march_lane<3>(a, NQ, TX, tcol, tzq);
+    const int zoff = tzq * V;
+    const int x0 = d.x0, y0 = d.y0;
+    const int w = d.wh & 0xffff;
+    const int h = d.wh >> 16;
+    const bool streams = lane_used && tcol < w + 6;                // loads grid column x0 - 3 + tcol
+    const bool act1 = lane_used && tcol >= 1 && tcol <= w + 4;      // step s + 1 on column tcol - 3
+    const bool act2 = lane_used && tcol >= 2 && tcol <= w + 3;      // step s + 2
+    const bool act3 = lane_used && tcol >= 3 && tcol <= w + 2;      // step s + 3 (the item's columns)
+    const int gx = streams ? wrap_near(x0 - 3 + tcol, nx) : 0;
+    const uint32_t rowbytes = static_cast<uint32_t>(nx) * static_cast<uint32_t>(nz) * sizeof(T);
+    const uint32_t colbytes = (static_cast<uint32_t>(gx) * nz + zoff) * sizeof(T);
+    const T cc = static_cast<T>(a.cc), cn = static_cast<T>(a.cn), eps = static_cast<T>(a.eps);
+    const int RL = (TX + 6) * nz;             // LDS row (elements); 2 buffers for each of 3 stages
+    const int K1 = TX + 4, K2 = TX + 2;       // row strides of the stage 1 and 2 trip counts
+    int* kb1 = reinterpret_cast<int*>(lds + 6 * RL);
+    int* kb2 = kb1 + K1 * (a.tile_y + 4);
+    int* kb3 = kb2 + K2 * (a.tile_y + 2);
+    // byte offset of row i (-3 .. h + 2) of this thread's column; out of range for
+    // threads without a column and past the last row the item reads
+    auto row_off = [&](int i) -> uint32_t {
+        if (!streams || i > h + 2) return kOutOfRange;
+        return colbytes + static_cast<uint32_t>(wrap_near(y0 + i, ny)) * rowbytes;
+    };
+    // trip counts of the three steps; the item's work (its own columns in each
+    // step) is summed here as well
+    int flat = 1;
+    int ksum = 0, kcols = 0;
+    for (int i = threadIdx.x; i < (w + 4) * (h + 4); i += BS) {
+        const int r = i / (w + 4), cx = i - r * (w + 4);
+        const int k = column_k(a, hc1x, hc1y, wrap_near(x0 - 2 + cx, nx), wrap_near(y0 - 2 + r, ny));
+        kb1[r * K1 + cx] = k;
+        flat &= k == a.kmin;
+        if (r >= 2 && r <= h + 1 && cx >= 2 && cx <= w + 1) {
+            ksum += k;
+            ++kcols;
+        }
+    }
+    for (int i = threadIdx.x; i < (w + 2) * (h + 2); i += BS) {
+        const int r = i / (w + 2), cx = i - r * (w + 2);
+        const int k = column_k(a, hc2x, hc2y, wrap_near(x0 - 1 + cx, nx), wrap_near(y0 - 1 + r, ny));
+        kb2[r * K2 + cx] = k;
+        flat &= k == a.kmin;
+        if (r >= 1 && r <= h && cx >= 1 && cx <= w) {
+            ksum += k;
+            ++kcols;
+        }
+    }
+    for (int i = threadIdx.x; i < w * h; i += BS) {
+        const int r = i / w, cx = i - r * w;
+        const int k = column_k(a, hc3x, hc3y, x0 + cx, y0 + r);
+        kb3[r * TX + cx] = k;
+        flat &= k == a.kmin;
+        ksum += k;
+        ++kcols;
+    }
+    // all trip counts kmin: the physics runs on a scalar count (the reduction also
+    // orders the table stores before their reads)
+    const bool uniform = __builtin_amdgcn_readfirstlane(__syncthreads_and(flat)) != 0;
+    const int ku = a.kmin;
+    T* const lrow = lds + tcol * nz + zoff;   // this thread's V levels in LDS row buffer 0
+    int par = 0;                              // LDS buffers of the next row (runs on across fields)
+    double chk[3] = {0.0, 0.0, 0.0};
+    const int n_it = h + 4;                   // iteration n: stage 1 on row n - 2, 2 on n - 3, 3 on n - 4
+    for (int f = 0; f < a.nfields; ++f) {
+        const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+        const rsrc_t out = field_rsrc(dst + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+        Vec<T, V> ym = bload<T, V>(in, row_off(-3));   // step s rows n - 3, n - 2, then n - 1 ..
+        Vec<T, V> c = bload<T, V>(in, row_off(-2));
+        Vec<T, V> R[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) R[j] = bload<T, V>(in, row_off(j - 1));
+        Vec<T, V> s1m{}, s1c{}, s2m{}, s2c{};   // stage 1 rows n - 4, n - 3; stage 2 rows n - 5, n - 4
+        for (int n0 = 0; n0 < n_it; n0 += D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int n = n0 + j;
+                if (n < n_it) {
+                    T* const LA = lrow + par * RL;         // step s, row n - 2
+                    T* const LB = lrow + (2 + par) * RL;   // stage 1, row n - 3
+                    T* const LC = lrow + (4 + par) * RL;   // stage 2, row n - 4
+                    par ^= 1;
+                    if (streams) st<T, V>(LA, c);
+                    if (act1) st<T, V>(LB, s1c);
+                    if (act2) st<T, V>(LC, s2c);
+                    __syncthreads();
+                    const Vec<T, V> yp = R[j];
+                    R[j] = bload<T, V>(in, row_off(n - 1 + D));
+                    Vec<T, V> s1n, s2n;               // (used only where their stage sets them)
+                    if (act1) {                       // stage 1, row n - 2
+                        T q[V];
+                        if (uniform)
+                            cell_update<T, V, KAHAN>(a, LA, c, ym, yp, tzq, NQ, nz, ku, cc, cn, eps, q);
+                        else
+                            cell_update<T, V, KAHAN>(a, LA, c, ym, yp, tzq, NQ, nz, kb1[n * K1 + tcol - 1], cc,
+                                                     cn, eps, q);
+#pragma unroll
+                        for (int v = 0; v < V; ++v) s1n.v[v] = q[v];
+                    }
+                    if (n >= 2 && act2) {             // stage 2, row n - 3
+                        T q[V];
+                        if (uniform)
+                            cell_update<T, V, KAHAN>(a, LB, s1c, s1m, s1n, tzq, NQ, nz, ku, cc, cn, eps, q);
+                        else
+                            cell_update<T, V, KAHAN>(a, LB, s1c, s1m, s1n, tzq, NQ, nz,
+                                                     kb2[(n - 2) * K2 + tcol - 2], cc, cn, eps, q);
+#pragma unroll
+                        for (int v = 0; v < V; ++v) s2n.v[v] = q[v];
+                    }
+                    if (n >= 4) {                     // stage 3, row n - 4
+                        Vec<T, V> o;
+                        uint32_t so = kOutOfRange;
+                        if (act3) {
+                            T q[V];
+                            if (uniform)
+                                cell_update<T, V, KAHAN>(a, LC, s2c, s2m, s2n, tzq, NQ, nz, ku, cc, cn, eps, q);
+                            else
+                                cell_update<T, V, KAHAN>(a, LC, s2c, s2m, s2n, tzq, NQ, nz,
+                                                         kb3[(n - 4) * TX + tcol - 3], cc, cn, eps, q);
+                            // the item's own cells of row n - 4 in each step
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                o.v[v] = q[v];
+                                chk[0] += static_cast<double>(s1m.v[v]);
+                                chk[1] += static_cast<double>(s2c.v[v]);
+                                chk[2] += static_cast<double>(q[v]);
+                            }
+                            so = colbytes + static_cast<uint32_t>(y0 + n - 4) * rowbytes;
+                        }
+                        if (a.stream_store)
+                            bstore<T, V, 2>(out, so, o);
+                        else
+                            bstore<T, V, 0>(out, so, o);
+                    }
+                    ym = c;
+                    c = yp;
+                    s1m = s1c;
+                    s1c = s1n;
+                    s2m = s2c;
+                    s2c = s2n;
+                }
+            }
+        }
+    }
+    double sums[4] = {chk[0], chk[1], chk[2],
+                      static_cast<double>(nz) * static_cast<double>(a.nfields) *
+                          (static_cast<double>(a.alpha) * static_cast<double>(kcols) + static_cast<double>(ksum))};
+    block_sum4(sums, red, BS);
+    ItemOut3 o;
+    o.checksum[0] = sums[0];
+    o.checksum[1] = sums[1];
+    o.checksum[2] = sums[2];
+    o.work = sums[3];
+    return o;
+}
+
 // ---- step context --------------------------------------------------------------
 struct StepInfo {
     uint64_t step;
@@ -1017,7 +1224,7 @@ __device__ __forceinline__ void record_item(const DevArgs& a, double* partials, 
 // Loads go out 16 at a time so that one memory latency covers a batch.
 constexpr int kSumThreads = 256;
 constexpr int kRedLen = kSumThreads;  // LDS doubles for block sums and partial sums
-static_assert(kRedLen >= 2 * kMaxBlock / 64, "block_sum2 needs two entries per wave");
+static_assert(kRedLen >= 4 * kMaxBlock / 64, "block_sum2..4 need up to four entries per wave");
 __device__ double sum_partials(const double* part, int n, double* acc, int bs) {
     constexpr int kBatch = 16;
     for (int v = threadIdx.x; v < kSumThreads; v += bs) {
@@ -1169,7 +1376,7 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_persistent(DevArgs a) {
     const WgState ws = a.wstate[wg];            // equal in every workgroup of the launch
     const uint64_t step = ws.step;
     const int par = static_cast<int>(step & 1);  // claim-counter set
-    const int b = static_cast<int>(step & 3);    // partials buffer and state slot
+    const int b = static_cast<int>(step & kSlotMask);    // partials buffer and state slot
     const StepInfo si = step_info(ws);
     const T* src = static_cast<const T*>(ws.cur ? a.field1 : a.field0);
     T* dst = static_cast<T*>(ws.cur ? a.field0 : a.field1);
@@ -1192,7 +1399,7 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_persistent(DevArgs a) {
         if (threadIdx.x == 0) {
             a.ctrl->pend_n[b] = a.ctrl->nitems;
             a.ctrl->pend_step[b] = step + 1;
-            a.pstate[(b + 1) & 3] = next_state(a, ws);
+            a.pstate[(b + 1) & kSlotMask] = next_state(a, ws);
         }
     }
     if (wg == a.nwg - 1) settle_others(a, 1u << b, red, a.block);   // earlier steps' sums
@@ -1287,7 +1494,7 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
     const WgState ws = a.wstate[wg];            // equal in every workgroup of the launch
     const uint64_t step = ws.step;
     const int par = uni(static_cast<int>(step & 1));   // claim-counter set
-    const int b = uni(static_cast<int>(step & 3));     // partials buffer and state slot
+    const int b = uni(static_cast<int>(step & kSlotMask));     // partials buffer and state slot
     const int cur = uni(ws.cur);
     StepInfo si;
     si.step = step;
@@ -1314,7 +1521,7 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_persistent_mar
         if (threadIdx.x == 0) {
             a.ctrl->pend_n[b] = a.ctrl->nitems;
             a.ctrl->pend_step[b] = step + 1;
-            a.pstate[(b + 1) & 3] = next_state(a, ws);
+            a.pstate[(b + 1) & kSlotMask] = next_state(a, ws);
         }
     }
     if (wg == a.nwg - 1) settle_others(a, 1u << b, red, a.block);   // earlier steps' sums
@@ -1386,7 +1593,7 @@ __device__ __forceinline__ void add_cu_busy(const DevArgs& a, double ticks) {
 // workgroup as soon as a previous one leaves the CU.  This keeps every CU full
 // of short-lived workgroups whose loads cover neighbouring rows, the pattern a
 // streaming kernel reads HBM fastest with, and needs no claims.  The step
-// state is the shared copy in the step's slot (its number mod 4, from the
+// state is the shared copy in the step's slot (its number mod kStepSlots, from the
 // host); workgroup 0 writes the next step's copy, resets the claim-counter set
 // of the next step, records this step's pending checksum and sums the earlier
 // steps'.
@@ -1415,7 +1622,7 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items(DevArgs 
         if (threadIdx.x == 0) {
             a.ctrl->pend_n[slot] = a.ctrl->nitems;
             a.ctrl->pend_step[slot] = ws.step + 1;
-            a.pstate[(slot + 1) & 3] = next_state(a, ws);
+            a.pstate[(slot + 1) & kSlotMask] = next_state(a, ws);
         }
     }
     const ItemDesc d = uni(a.queue[blockIdx.x]);
@@ -1429,8 +1636,8 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items(DevArgs 
 // Two steps per launch, one workgroup per item (the launch form above with
 // the fused two-step item body).  Step s's shared state is in slot; the
 // state of step s + 1 follows from it.  The launch writes the checksum
-// partials of steps s and s + 1 (buffers slot and slot + 1 mod 4), sums the
-// other buffers, and leaves the state of step s + 2 in slot + 2 mod 4: two
+// partials of steps s and s + 1 (buffers slot and slot + 1 mod kStepSlots), sums the
+// other buffers, and leaves the state of step s + 2 in slot + 2 mod kStepSlots: two
 // steps later, and the field copy flipped once (one launch, one write).
 template <typename T, int V, int KAHAN, int D>
 __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items2(DevArgs a, int slot) {
@@ -1451,7 +1658,7 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items2(DevArgs
     const int cur = uni(ws.cur);
     const T* src = static_cast<const T*>(cur ? a.field1 : a.field0);
     T* dst = static_cast<T*>(cur ? a.field0 : a.field1);
-    const int slot1 = (slot + 1) & 3;
+    const int slot1 = (slot + 1) & kSlotMask;
     if (blockIdx.x == 0) {
         settle_others(a, (1u << slot) | (1u << slot1), red, a.block2);   // earlier steps' sums
         for (int q = threadIdx.x; q < 2 * a.nqueues; q += a.block2) a.heads[q] = a.head0;
@@ -1462,7 +1669,7 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items2(DevArgs
             a.ctrl->pend_step[slot1] = ws.step + 2;
             WgState n2 = next_state(a, ws1);
             n2.cur = ws.cur ^ 1;
-            a.pstate[(slot + 2) & 3] = n2;
+            a.pstate[(slot + 2) & kSlotMask] = n2;
         }
     }
     const ItemDesc d = uni(a.queue[blockIdx.x]);
@@ -1481,6 +1688,65 @@ __global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items2(DevArgs
         __hip_atomic_fetch_add(&a.visits[d.vbase + r], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Three steps per launch, one workgroup per item: as the two-step launch, with
+// the partials of steps s, s + 1 and s + 2 (buffers slot .. slot + 2 mod
+// kStepSlots) and the state of step s + 3 left in slot + 3.
+template <typename T, int V, int KAHAN, int D>
+__global__ __launch_bounds__(max_block<T>(kPipeMarch + D)) void k_items3(DevArgs a, int slot) {
+    extern __shared__ __align__(32) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    __shared__ double red[kRedLen];
+
+    const WgState ws = a.pstate[slot];
+    const WgState ws1 = next_state(a, ws);
+    const WgState ws2 = next_state(a, ws1);
+    int h1x[kMaxHot], h1y[kMaxHot], h2x[kMaxHot], h2y[kMaxHot], h3x[kMaxHot], h3y[kMaxHot];
+#pragma unroll
+    for (int h = 0; h < kMaxHot; ++h) {
+        h1x[h] = uni(ws.hx[h]);
+        h1y[h] = uni(ws.hy[h]);
+        h2x[h] = uni(ws1.hx[h]);
+        h2y[h] = uni(ws1.hy[h]);
+        h3x[h] = uni(ws2.hx[h]);
+        h3y[h] = uni(ws2.hy[h]);
+    }
+    const int cur = uni(ws.cur);
+    const T* src = static_cast<const T*>(cur ? a.field1 : a.field0);
+    T* dst = static_cast<T*>(cur ? a.field0 : a.field1);
+    int sl[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) sl[i] = (slot + i) & kSlotMask;
+    if (blockIdx.x == 0) {
+        settle_others(a, (1u << sl[0]) | (1u << sl[1]) | (1u << sl[2]), red, a.block3);   // earlier sums
+        for (int q = threadIdx.x; q < 2 * a.nqueues; q += a.block3) a.heads[q] = a.head0;
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                a.ctrl->pend_n[sl[i]] = a.ctrl->nitems;
+                a.ctrl->pend_step[sl[i]] = ws.step + 1 + i;
+            }
+            WgState n3 = next_state(a, ws2);
+            n3.cur = ws.cur ^ 1;
+            a.pstate[(slot + 3) & kSlotMask] = n3;
+        }
+    }
+    const ItemDesc d = uni(a.queue[blockIdx.x]);
+    const uint64_t t_start = wall_clock64();
+    const ItemOut3 o =
+        process_item_march3<T, V, KAHAN, D>(a, d, src, dst, h1x, h1y, h2x, h2y, h3x, h3y, lds, red);
+    const double ticks = static_cast<double>(wall_clock64() - t_start);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) a.partials[static_cast<int64_t>(sl[i]) * a.part_stride + d.id] = o.checksum[i];
+        unsafeAtomicAdd(&a.loads_work[d.chunk], o.work);
+        unsafeAtomicAdd(&a.loads_time[d.chunk], ticks);
+        unsafeAtomicAdd(&a.tile_work[d.tile], o.work);
+        add_cu_busy(a, ticks);
+    }
+    for (int r = threadIdx.x; r < (d.wh >> 16); r += a.block3)   // one visit per row and step
+        __hip_atomic_fetch_add(&a.visits[d.vbase + r], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T, int V, int KAHAN, int PIPE>
 __global__ __launch_bounds__(max_block<T>(PIPE)) void k_plain(DevArgs a, int chunk) {
     extern __shared__ __align__(32) unsigned char smem[];
@@ -1489,7 +1755,7 @@ __global__ __launch_bounds__(max_block<T>(PIPE)) void k_plain(DevArgs a, int chu
 
     const WgState ws = a.wstate[0];
     const uint64_t step = ws.step;
-    const int b = static_cast<int>(step & 3);
+    const int b = static_cast<int>(step & kSlotMask);
     const StepInfo si = step_info(ws);
     const T* src = static_cast<const T*>(ws.cur ? a.field1 : a.field0);
     T* dst = static_cast<T*>(ws.cur ? a.field0 : a.field1);
@@ -1517,7 +1783,7 @@ __global__ __launch_bounds__(kSumThreads) void k_finish(DevArgs a) {
     __shared__ double red[kRedLen];
     const WgState ws = a.wstate[0];
     const uint64_t step = ws.step;
-    const int b = static_cast<int>(step & 3);
+    const int b = static_cast<int>(step & kSlotMask);
     settle_others(a, 1u << b, red, kSumThreads);
     const double total = sum_partials(a.partials + static_cast<int64_t>(b) * a.part_stride,
                                       static_cast<int>(a.ctrl->nitems), red, kSumThreads);
@@ -1529,7 +1795,7 @@ __global__ __launch_bounds__(kSumThreads) void k_finish(DevArgs a) {
     __syncthreads();                  // every thread has read wstate[0]
     const WgState nx = next_state(a, ws);
     for (int w = threadIdx.x; w < a.nwg; w += kSumThreads) a.wstate[w] = nx;
-    if (threadIdx.x == 0) a.pstate[(b + 1) & 3] = nx;
+    if (threadIdx.x == 0) a.pstate[(b + 1) & kSlotMask] = nx;
 }
 
 // Every workgroup's own copy of the step state from the shared copy in slot
@@ -1719,6 +1985,19 @@ ItemsFn pick_items2(int prec, int pipe) {
     if (prec == 1) return items2_for<float, 1>(pipe);
     return items2_for<float, 0>(pipe);
 }
+template <typename T, int KAHAN>
+ItemsFn items3_for(int pipe) {
+    switch (pipe) {
+        case kPipeMarch + 4: return k_items3<T, 4, KAHAN, 4>;
+        case kPipeMarch + 8: return k_items3<T, 4, KAHAN, 8>;
+        default: return k_items3<T, 4, KAHAN, 2>;
+    }
+}
+ItemsFn pick_items3(int prec, int pipe) {
+    if (prec == 2) return items3_for<double, 0>(pipe);
+    if (prec == 1) return items3_for<float, 1>(pipe);
+    return items3_for<float, 0>(pipe);
+}
 
 PersistentFn pick_persistent(int prec, int vec, int pipe) {
     if (prec == 2) return persistent_for<double, 0>(vec, pipe);
@@ -1775,6 +2054,15 @@ int launch_items2(const DevArgs& a, int prec, int vec, int nitems, int block, si
     if (vec != 4 || a.march <= 0 || nitems <= 0 || block != a.block2)
         return static_cast<int>(hipErrorInvalidValue);
     hipLaunchKernelGGL(pick_items2(prec, pipe_of(a)), dim3(nitems), dim3(block), lds,
+                       static_cast<hipStream_t>(stream), a, slot);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_items3(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
+                  void* stream) {
+    if (vec != 4 || a.march <= 0 || nitems <= 0 || block != a.block3)
+        return static_cast<int>(hipErrorInvalidValue);
+    hipLaunchKernelGGL(pick_items3(prec, pipe_of(a)), dim3(nitems), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a, slot);
     return static_cast<int>(hipGetLastError());
 }

@@ -20,9 +20,11 @@ constexpr size_t kMaxLds = 160 * 1024;  // gfx950: 160 KiB of LDS per CU
 constexpr int kCuSlots = 2048;
 
 // Checksum partial buffers and shared step-state copies are kept per step
-// mod 4: a launch writes those of its own step(s) (one, or two when it fuses
-// two steps) and never those of the launch before it.
-constexpr int kStepSlots = 4;
+// mod kStepSlots: a launch writes those of its own steps (one, or up to three
+// when it fuses steps) and never those of the launch before it, so the slots
+// must cover two launches of the most steps.
+constexpr int kStepSlots = 8;
+constexpr int kSlotMask = kStepSlots - 1;
 
 // Device control block (first bytes of the workspace).
 struct Ctrl {
@@ -72,14 +74,14 @@ struct DevArgs {
     int32_t* heads;            // 2 x Q claim counters, one set per step parity; a step finds
                                // its set at head0 and resets the other set for the next step
     WgState* wstate;           // nwg: step and hotspot centres, kept by each workgroup
-    WgState* pstate;           // kStepSlots, by step mod 4: the state of a step whose launch
+    WgState* pstate;           // kStepSlots, by step mod kStepSlots: the state of a step whose launch
                                // form reads one shared copy (one workgroup per item); every
                                // form writes the copy of the step after its own
     Ctrl* ctrl;
     double* loads_work;        // C
     double* loads_time;        // C
     double* tile_work;         // ntiles: work units of each tile (rebuilds items from it)
-    double* partials;          // kStepSlots x part_stride, by step mod 4: per item, the sum
+    double* partials;          // kStepSlots x part_stride, by step mod kStepSlots: per item, the sum
                                // of its outputs in that step
     double* hist;              // kHistLen per-step sums
     double* wg_busy;           // nwg (persistent: per workgroup), or kCuSlots (one workgroup
@@ -96,6 +98,7 @@ struct DevArgs {
     int32_t tile_y;            // TY (the trip-count buffers hold TX * TY entries)
     int32_t block;             // threads per workgroup = TX * nz / V (== blockDim.x)
     int32_t block2;            // threads per workgroup of the two-step item launch
+    int32_t block3;            // ... of the three-step item launch
     int32_t stage_rows;        // > 0: rows per direct global->LDS batch (V = 4 only); 0: registers
     int32_t reg_depth;         // register pipeline: rows in flight (2, 4 or 8; 2 unless V = 4)
     int32_t march;             // > 0: column-march pipeline with this many rows in flight (2, 4, 8)
@@ -131,14 +134,17 @@ int  launch_persistent(const DevArgs& a, int prec, int vec, int nwg, int block, 
 int  launch_plain_chunk(const DevArgs& a, int prec, int vec, int chunk, int nitems_chunk,
                         int block, size_t lds, void* stream);
 // One workgroup per item of the installed plan (nitems of them, in queue order);
-// slot is the step's number mod 4 (steps enqueued so far).
+// slot is the step's number mod kStepSlots (steps enqueued so far).
 int  launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
                   void* stream);
-// The same with two steps per launch (temporal blocking): slot is the number mod 4
+// The same with two steps per launch (temporal blocking): slot is the number mod kStepSlots
 // of the first of them, block the threads of a two-step workgroup (a.block2).
 int  launch_items2(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
                    void* stream);
-// Copy the shared state of the step in slot (its number mod 4) into every
+// Three steps per launch.
+int  launch_items3(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
+                   void* stream);
+// Copy the shared state of the step in slot (its number mod kStepSlots) into every
 // workgroup's own copy.
 int  launch_seed_state(const DevArgs& a, int slot, void* stream);
 int  launch_finish(const DevArgs& a, void* stream);

@@ -55,9 +55,11 @@ struct Plan {
     int32_t nrows = 0;      // tile rows over all tiles: the most items a plan can have
     int32_t M = 0;          // rows in flight of the column march; 0 = another pipeline
     bool IG = false;        // balanced steps launch one workgroup per item
-    int32_t F = 1;          // steps per launch of one workgroup per item (1, or 2 fused)
+    int32_t F = 1;          // steps per launch of one workgroup per item (1, or 2 or 3 fused)
     int32_t block2 = 0;     // threads per workgroup of the two-step item launch
     size_t lds2 = 0;        // its LDS bytes
+    int32_t block3 = 0;     // ... of the three-step item launch
+    size_t lds3 = 0;
     int32_t CPW = 0;        // march: whole columns per wave (vertical physics, NQ not dividing 64)
     int32_t B = 0;          // rows per direct global->LDS batch; 0 = register pipeline
     int32_t ring = 4;       // LDS ring rows
@@ -177,8 +179,8 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->hot_cut < 0) return bad("hot_cut must be >= 0");
     if (c->item_grid != 0 && c->item_grid != 1) return bad("item_grid must be 0 or 1");
     if (c->item_grid == 1 && c->march == 0) return bad("item_grid needs the column-march pipeline (march > 0)");
-    if (c->fuse_steps < 0 || c->fuse_steps > 2) return bad("fuse_steps must be 0, 1 or 2");
-    if (c->fuse_steps == 2 && c->item_grid != 1) return bad("fuse_steps 2 needs item_grid 1");
+    if (c->fuse_steps < 0 || c->fuse_steps > 3) return bad("fuse_steps must be 0, 1, 2 or 3");
+    if (c->fuse_steps >= 2 && c->item_grid != 1) return bad("fuse_steps 2 or 3 needs item_grid 1");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
     p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
@@ -209,7 +211,7 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     // rows (V = 4 only) or the register path
     p.M = c->march;
     p.IG = c->item_grid == 1;
-    p.F = c->fuse_steps == 2 ? 2 : 1;
+    p.F = c->fuse_steps >= 2 ? c->fuse_steps : 1;
     if (p.M > 0) {
         if (p.vec != 4) return bad("march needs nz divisible by 4");
         if (static_cast<uint64_t>(p.ncells) * p.elem > 0xFFFFFE00ull)
@@ -243,6 +245,16 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         return size_t{4} * (tx + 4) * col_bytes +
                sizeof(int32_t) * (static_cast<size_t>(tx + 2) * (p.TY + 2) + static_cast<size_t>(tx) * p.TY);
     };
+    // three steps: three halo columns on either side, six LDS rows, three trip-count tables
+    auto threads3_for = [&](int tx) {
+        if (p.CPW > 0) return (tx + 6 + p.CPW - 1) / p.CPW * 64;
+        return (tx + 6) * NQ;
+    };
+    auto lds3_for = [&](int tx) {
+        return size_t{6} * (tx + 6) * col_bytes +
+               sizeof(int32_t) * (static_cast<size_t>(tx + 4) * (p.TY + 4) + static_cast<size_t>(tx + 2) * (p.TY + 2) +
+                                  static_cast<size_t>(tx) * p.TY);
+    };
     const int most = p.M > 0 ? (p.prec == LB_FP64 ? kMaxBlockDeep : kMaxBlock)
                              : (p.B == 0 && (p.RD >= 4 || p.prec == LB_FP64)) ? kMaxBlockDeep : kMaxBlock;
     if (c->tile_x > 0) {
@@ -250,7 +262,8 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     } else {
         p.TX = p.M > 0 ? 32 : 16;
         while (p.TX > 1 && (threads_for(p.TX) > most || lds_for(p.TX) > 64 * 1024 ||
-                            (p.F == 2 && (threads2_for(p.TX) > most || lds2_for(p.TX) > 64 * 1024))))
+                            (p.F >= 2 && (threads2_for(p.TX) > most || lds2_for(p.TX) > 64 * 1024)) ||
+                            (p.F == 3 && (threads3_for(p.TX) > most || lds3_for(p.TX) > 64 * 1024))))
             --p.TX;
     }
     if (p.TX > 1024 || p.TY > 256) return bad("tile sizes must be at most 1024 x 256");
@@ -264,13 +277,21 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         return bad("FP64 with the register pipeline needs tile_x * nz / V <= 512 threads");
     p.lds = lds_for(p.TX);
     if (p.lds > kMaxLds) return bad("tile too large: the LDS row ring and trip counts exceed 160 KiB");
-    if (p.F == 2) {
+    if (p.F >= 2) {   // (three-step launches end an odd remainder with a two-step one)
         p.block2 = threads2_for(p.TX);
         p.lds2 = lds2_for(p.TX);
         if (p.block2 > most)
             return bad(p.prec == LB_FP64 ? "fuse_steps 2 in FP64 needs (tile_x + 4) * nz / 4 <= 512 threads"
                                          : "fuse_steps 2 needs (tile_x + 4) * nz / 4 <= 1024 threads");
         if (p.lds2 > kMaxLds) return bad("tile too large for fuse_steps 2: its LDS rows and trip counts exceed 160 KiB");
+    }
+    if (p.F == 3) {
+        p.block3 = threads3_for(p.TX);
+        p.lds3 = lds3_for(p.TX);
+        if (p.block3 > most)
+            return bad(p.prec == LB_FP64 ? "fuse_steps 3 in FP64 needs (tile_x + 6) * nz / 4 <= 512 threads"
+                                         : "fuse_steps 3 needs (tile_x + 6) * nz / 4 <= 1024 threads");
+        if (p.lds3 > kMaxLds) return bad("tile too large for fuse_steps 3: its LDS rows and trip counts exceed 160 KiB");
     }
 
     // tiles of every chunk, chunks in id order, tiles in raster order; every tile
@@ -380,11 +401,11 @@ struct lb_ctx {
     double host_plan_us = 0.0;        // all plans: items, queue order, staging, upload launch
     hipGraphExec_t g_pers = nullptr;  // graph_steps persistent steps
     hipGraphExec_t g_pers1 = nullptr; // one persistent step
-    // one workgroup per item: graph_steps steps and one step, per slot (number mod 4)
+    // one workgroup per item: graph_steps steps and one step, per slot (number mod kStepSlots)
     // of the first step (the slot is a launch argument), for the plan they were taken on
     hipGraphExec_t g_items[kStepSlots] = {};
     hipGraphExec_t g_items1[kStepSlots] = {};
-    int64_t items_graph_version[kStepSlots] = {-1, -1, -1, -1};
+    int64_t items_graph_version[kStepSlots] = {-1, -1, -1, -1, -1, -1, -1, -1};
     int cur = 0;                      // field copy holding the current step's values
     bool wstate_stale = false;        // only the shared per-parity step state is current
     bool items_stale = false;         // the chunk-order item tables on the device are not the plan's
@@ -733,18 +754,20 @@ int upload_items(lb_ctx* x) {
     return LB_OK;
 }
 
-// Steps a balanced launch takes when `left` steps remain: two when the plan
-// fuses steps and at least two remain, else one.
-int launch_span(const Plan& p, int left) { return p.F == 2 && left >= 2 ? 2 : 1; }
+// Steps a balanced launch takes when `left` steps remain: the plan's steps per
+// launch (F) while at least that many remain, then the rest in one launch (a
+// remainder of 1 or 2 steps: F is at most 3).
+int launch_span(const Plan& p, int left) { return left < p.F ? left : p.F; }
 
 // Field copies written by n balanced steps launched in spans of launch_span.
-int launches_for(const Plan& p, int n) { return p.F == 2 ? n / 2 + n % 2 : n; }
+int launches_for(const Plan& p, int n) { return n / p.F + (n % p.F ? 1 : 0); }
 
 // One balanced launch of n (= launch_span) steps, in the plan's form; slot is the
-// number mod 4 of its first step.
+// number mod kStepSlots of its first step.
 int launch_balanced(lb_ctx* x, int slot, int n, hipStream_t s) {
     const Plan& p = x->plan;
     const int nitems = static_cast<int>(x->items.size());
+    if (p.IG && n == 3) return launch_items3(x->args, p.prec, p.vec, nitems, p.block3, p.lds3, slot, s);
     if (p.IG && n == 2) return launch_items2(x->args, p.prec, p.vec, nitems, p.block2, p.lds2, slot, s);
     if (n != 1) return static_cast<int>(hipErrorInvalidValue);
     if (p.IG) return launch_items(x->args, p.prec, p.vec, nitems, p.block, p.lds, slot, s);
@@ -759,7 +782,7 @@ int capture(lb_ctx* x, int mode, int nsteps, hipGraphExec_t* out, int slot0 = 0)
     for (int i = 0; i < nsteps && rc == 0;) {
         if (mode == LB_PERSISTENT) {
             const int n = launch_span(p, nsteps - i);
-            rc = launch_balanced(x, (slot0 + i) & 3, n, x->cap);
+            rc = launch_balanced(x, (slot0 + i) & kSlotMask, n, x->cap);
             i += n;
         } else {
             ++i;
@@ -947,6 +970,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.tile_y = P.TY;
     a.block = P.block;
     a.block2 = P.block2;
+    a.block3 = P.block3;
     a.stage_rows = P.B;
     a.reg_depth = P.RD;
     a.march = P.M;
@@ -1050,7 +1074,7 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
     // refreshed after steps launched one workgroup per item.
     const bool own_state = !(p.IG && (mode == LB_PERSISTENT || mode == LB_PERSISTENT_EAGER));
     if (own_state && x->wstate_stale) {
-        LAUNCH_TRY(x, launch_seed_state(x->args, static_cast<int>(x->steps & 3), x->stream));
+        LAUNCH_TRY(x, launch_seed_state(x->args, static_cast<int>(x->steps & kSlotMask), x->stream));
         x->wstate_stale = false;
     }
     if (!own_state) x->wstate_stale = true;
@@ -1069,7 +1093,7 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
                         x->items_graph_version[k] = x->plan_version;
                     }
                 for (int i = 0; i < nsteps / R; ++i) {
-                    const int sl = static_cast<int>(x->steps & 3);
+                    const int sl = static_cast<int>(x->steps & kSlotMask);
                     if (!x->g_items[sl] && (rc = capture(x, LB_PERSISTENT, R, &x->g_items[sl], sl)) != LB_OK)
                         return rc;
                     if (forced()) return launch_failed("hipGraphLaunch", 0, false);
@@ -1077,11 +1101,11 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
                     done(R, true);
                 }
                 for (int i = 0; i < nsteps % R;) {
-                    const int sl = static_cast<int>(x->steps & 3);
+                    const int sl = static_cast<int>(x->steps & kSlotMask);
                     const int n = launch_span(p, nsteps % R - i);
-                    if (n == 2) {   // a pair of the remainder: one launch, not worth a graph
+                    if (n >= 2) {   // fused steps of the remainder: one launch, not worth a graph
                         if (forced()) return launch_failed("launch_balanced", 0, false);
-                        if (int e = launch_balanced(x, sl, 2, x->stream)) return launch_failed("launch_balanced", e, false);
+                        if (int e = launch_balanced(x, sl, n, x->stream)) return launch_failed("launch_balanced", e, false);
                     } else {
                         if (!x->g_items1[sl] && (rc = capture(x, LB_PERSISTENT, 1, &x->g_items1[sl], sl)) != LB_OK)
                             return rc;
@@ -1111,7 +1135,7 @@ int lb_step(lb_ctx* x, int32_t nsteps, int32_t mode) {
             for (int i = 0; i < nsteps;) {
                 const int n = launch_span(p, nsteps - i);
                 if (forced()) return launch_failed("launch_balanced", 0, false);
-                if (int e = launch_balanced(x, static_cast<int>(x->steps & 3), n, x->stream))
+                if (int e = launch_balanced(x, static_cast<int>(x->steps & kSlotMask), n, x->stream))
                     return launch_failed("launch_balanced", e, false);
                 done(n, true);
                 i += n;
@@ -1330,6 +1354,7 @@ int lb_stats(lb_ctx* x, lb_stats_t* out) {
     out->nwg = p.nwg;
     out->block = p.block;
     out->block2 = p.block2;
+    out->block3 = p.block3;
     out->tile_x = p.TX;
     out->tile_y = p.TY;
     out->clock_hz = x->clock_hz;

@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_struct_layout_and_version(lib):
-    assert lib.lb_abi_version() == 4
+    assert lib.lb_abi_version() == 5
     assert lib.lb_config_bytes() == C.sizeof(_abi.LbConfig)
     assert lib.lb_stats_bytes() == C.sizeof(_abi.LbStats)
 
@@ -80,7 +80,9 @@ def test_query_rejects_bad_config(lib, field, value, msg):
     (dict(march=4, precision=2, tile_x=70), "FP64 march"), (dict(march=8, tile_x=200), "1024 threads"),
     (dict(item_grid=1), "item_grid needs the column-march"), (dict(item_grid=2, march=2), "item_grid must be"),
     (dict(queue_order=3), "queue_order must be"), (dict(hot_cut=-1), "hot_cut"),
-    (dict(fuse_steps=3), "fuse_steps must be"), (dict(fuse_steps=2, march=2), "fuse_steps 2 needs item_grid"),
+    (dict(fuse_steps=4), "fuse_steps must be"), (dict(fuse_steps=2, march=2), "fuse_steps 2 or 3 needs item_grid"),
+    (dict(fuse_steps=3, march=2), "fuse_steps 2 or 3 needs item_grid"),
+    (dict(fuse_steps=3, march=2, item_grid=1, precision=2, tile_x=59), "fuse_steps 3 in FP64"),
     (dict(fuse_steps=2, march=2, item_grid=1, precision=2, tile_x=61), "fuse_steps 2 in FP64"),
     (dict(fuse_steps=2, march=2, item_grid=1, tile_x=125), "fuse_steps 2 needs (tile_x + 4)"),
 ])
@@ -89,7 +91,8 @@ def test_query_rejects_bad_pipeline(lib, over, msg):
     workgroups of at most 512 threads, and depth 8 is FP32 only.  The column march
     takes 2, 4 or 8 rows in flight, needs V = 4 and (tile_x + 2) * nz / 4 threads, at
     most 512 in FP64; two steps per launch need item_grid 1 and (tile_x + 4) * nz / 4
-    threads.  (64x64x32: tile_x 61 and 125 fit one step per launch but not two.)"""
+    threads, three steps (tile_x + 6) * nz / 4.  (64x64x32: tile_x 61 and 125 fit one step
+    per launch but not two; tile_x 59 fits two in FP64 but not three.)"""
     cfg, keep = _abi.config_from_workload(W.small())
     for k, v in over.items():
         setattr(cfg, k, v)

@@ -143,6 +143,7 @@ def test_launch_forms_bit_identical():
     dict(march=2, queue_order=1, tile_x=4, tile_y=3),
     dict(march=4, item_grid=1, fuse_steps=2), dict(march=2, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3),
     dict(march=8, item_grid=1, fuse_steps=2, tile_y=11, queue_order=1),
+    dict(march=4, item_grid=1, fuse_steps=3), dict(march=2, item_grid=1, fuse_steps=3, tile_x=5, tile_y=3, queue_order=1),
 ])
 def test_schedule_invariance(over):
     wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=3)
@@ -181,11 +182,12 @@ def test_item_grid_mixed_launch_forms_fp64():
     g.close()
 
 
+@pytest.mark.parametrize("fuse", [2, 3])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_fused_steps_mixed_launch_forms(precision):
-    """Two steps per launch: each item reads its cells and a two-cell halo once,
-    computes the first step on a one-cell ring around it as well, and writes the second
-    step.  Runs of fused launches, single steps (odd counts, odd graph lengths), every
+def test_fused_steps_mixed_launch_forms(precision, fuse):
+    """Two (three) steps per launch: each item reads its cells and a two-cell (three-cell)
+    halo once, computes the earlier steps on rings around it as well, and writes the last
+    step.  Runs of fused launches, shorter remainders (odd counts, odd graph lengths), every
     other launch form and a rebalance, in one context: FP64 fields equal the oracle's bit
     for bit and FP32 fields equal those of one step per launch; loads equal the oracle's,
     per-step checksums agree with it, and every tile row is computed once per step."""
@@ -206,7 +208,7 @@ def test_fused_steps_mixed_launch_forms(precision):
                 g.step(n, mode)
         return g, loads
 
-    g, loads = run(fuse_steps=2)
+    g, loads = run(fuse_steps=fuse)
     np.testing.assert_array_equal(loads[0], work[:7].sum(axis=0))
     np.testing.assert_array_equal(loads[1], work[7:].sum(axis=0))
     assert np.all(g.visits() == 16)
@@ -225,15 +227,16 @@ def test_fused_steps_mixed_launch_forms(precision):
     g.close()
 
 
-def test_fused_steps_graph_replays_fp64():
-    """Graphs of two-step launches replayed many times (each captured for the step
+@pytest.mark.parametrize("fuse", [2, 3])
+def test_fused_steps_graph_replays_fp64(fuse):
+    """Graphs of fused launches replayed many times (each captured for the step
     slot it starts at), with eager launches and field reads between the replays: the
     fields after every group equal the oracle's, bit for bit."""
     wl = mk(40, 36, 12, 4, 3, hot=((7, 30, 1, 1),), split="dirichlet", steps=14, nslots=5)
     ref = {}
     for n in (4, 8, 12, 14):
         ref[n], _, _, _ = oracle.run(wl, nsteps=n)
-    g = Grid(wl, precision="fp64", march=4, item_grid=1, fuse_steps=2, graph_steps=2, tile_x=5, tile_y=4)
+    g = Grid(wl, precision="fp64", march=4, item_grid=1, fuse_steps=fuse, graph_steps=fuse, tile_x=5, tile_y=4)
     done = 0
     for n, mode in ((4, "persistent"), (4, "persistent"), (1, "persistent_eager"), (3, "persistent"),
                     (2, "persistent")):
@@ -245,20 +248,22 @@ def test_fused_steps_graph_replays_fp64():
     g.close()
 
 
-def test_fused_steps_wide_tiles_and_small_grids_fp64():
+@pytest.mark.parametrize("fuse", [2, 3])
+def test_fused_steps_wide_tiles_and_small_grids_fp64(fuse):
     """The fused launch where its halo wraps around a small grid more than once (a two-
     cell halo on a grid narrower than a tile plus four columns, or shorter than three
     rows), and with the widest tile an FP64 workgroup allows ((28 + 4) x 64 / 4 = 512
-    threads)."""
+    threads for two steps, (26 + 6) x 64 / 4 for three)."""
     for shape, over in (((5, 3, 8, 1, 1), dict(tile_x=8, tile_y=4)), ((2, 7, 4, 2, 1), dict(tile_x=1, tile_y=2)),
-                        ((3, 1, 12, 1, 1), dict()), ((70, 40, 64, 2, 2), dict(tile_x=28, tile_y=9))):
+                        ((3, 1, 12, 1, 1), dict()),
+                        ((70, 40, 64, 2, 2), dict(tile_x=28 if fuse == 2 else 26, tile_y=9))):
         nx, ny, nz, px, py = shape
         say("fused", shape, over)
         wl = mk(nx, ny, nz, px, py, hot=((nx // 2, ny // 2, 1, 1),), sigma=2.0, kmax=20, steps=5, nslots=2)
         ref, work, _, _ = oracle.run(wl, nsteps=5)
-        g = Grid(wl, precision="fp64", march=2, item_grid=1, fuse_steps=2, **over)
+        g = Grid(wl, precision="fp64", march=2, item_grid=1, fuse_steps=fuse, **over)
         if nz == 64:
-            assert g.stats()["block2"] == (over["tile_x"] + 4) * 16 == 512
+            assert g.stats()["block%d" % fuse] == (over["tile_x"] + 2 * fuse) * 16 == 512
         g.step(5, "persistent_eager")
         np.testing.assert_array_equal(gpu_fields(g), ref)
         np.testing.assert_array_equal(g.measure("work"), work.sum(axis=0))
@@ -343,7 +348,8 @@ def test_ragged_fp64_bit_exact(shape):
     deep = (dict(tile_y=5, stage_rows=2), dict(tile_y=9, stage_rows=-4), dict(tile_x=3, stage_rows=-4),
             dict(march=2), dict(march=4, tile_x=3, tile_y=2), dict(march=8, tile_x=7, tile_y=9),
             dict(march=2, item_grid=1), dict(march=4, item_grid=1, tile_x=3, tile_y=2),
-            dict(march=2, item_grid=1, fuse_steps=2), dict(march=4, item_grid=1, fuse_steps=2, tile_x=3, tile_y=2))
+            dict(march=2, item_grid=1, fuse_steps=2), dict(march=4, item_grid=1, fuse_steps=2, tile_x=3, tile_y=2),
+            dict(march=2, item_grid=1, fuse_steps=3), dict(march=4, item_grid=1, fuse_steps=3, tile_x=3, tile_y=2))
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     for tiles in (dict(), dict(tile_x=3, tile_y=2), dict(stage_rows=-1)) + (deep if nz % 4 == 0 else (dict(tile_y=5),)):
         for mode in (("persistent", "plain") if "march" in tiles else ("persistent",)):
@@ -369,7 +375,8 @@ def test_fp64_register_pipeline_at_its_workgroup_limit():
 
 @pytest.mark.parametrize("over", [dict(), dict(march=4), dict(march=2, tile_x=5, tile_y=3),
                                   dict(march=2, item_grid=1, tile_x=5, tile_y=3),
-                                  dict(march=2, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3)])
+                                  dict(march=2, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3),
+                                  dict(march=2, item_grid=1, fuse_steps=3, tile_x=5, tile_y=3)])
 def test_multi_field_fp64_bit_exact(over):
     wl = mk(24, 20, 8, 3, 2, steps=3).replace(nfields=3)
     g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
@@ -754,7 +761,8 @@ def test_study_load_sources():
 @pytest.mark.parametrize("over", [dict(march=4, item_grid=1, tile_x=8, tile_y=24),
                                   dict(march=2, item_grid=1, tile_x=5, tile_y=7, queue_order=1),
                                   dict(march=8, tile_x=6, tile_y=5), dict(stage_rows=-1),
-                                  dict(march=4, item_grid=1, fuse_steps=2, tile_x=8, tile_y=24)])
+                                  dict(march=4, item_grid=1, fuse_steps=2, tile_x=8, tile_y=24),
+                                  dict(march=4, item_grid=1, fuse_steps=3, tile_x=16, tile_y=8)])
 def test_many_fields_fp64_bit_exact(over):
     """Twelve fields sharing one cost field, in the launch shapes the multi-field benchmark
     uses: FP64 fields bit-identical to the oracle's, loads (counting every field) identical."""
@@ -804,7 +812,8 @@ def test_vertical_physics_fp64_bit_exact(nz):
     for over in (dict(), dict(stage_rows=-1), dict(tile_x=5, tile_y=3)) + \
             ((dict(stage_rows=-4, tile_x=4), dict(march=2), dict(march=4, tile_x=3, tile_y=4),
               dict(march=4, item_grid=1, tile_x=3, tile_y=4),
-              dict(march=4, item_grid=1, fuse_steps=2, tile_x=3, tile_y=4))
+              dict(march=4, item_grid=1, fuse_steps=2, tile_x=3, tile_y=4),
+              dict(march=4, item_grid=1, fuse_steps=3, tile_x=3, tile_y=4))
              if nz % 4 == 0 else ()):
         g, q, w = run_gpu(wl, 3, "persistent", precision="fp64", **over)
         np.testing.assert_array_equal(q, ref)
@@ -864,7 +873,7 @@ def test_vertical_physics_whole_columns_per_wave_fp64(nz):
     for over in (dict(march=2), dict(march=4, tile_x=3, tile_y=4), dict(march=8, tile_x=7, tile_y=9),
                  dict(march=4, item_grid=1, tile_x=5, tile_y=3), dict(march=2, item_grid=1),
                  dict(march=4, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3),
-                 dict(march=2, item_grid=1, fuse_steps=2)):
+                 dict(march=2, item_grid=1, fuse_steps=2), dict(march=2, item_grid=1, fuse_steps=3)):
         for mode in ("persistent", "plain"):
             g, q, w = run_gpu(wl, 3, mode, precision="fp64", **over)
             np.testing.assert_array_equal(q, ref)
