@@ -29,7 +29,7 @@ CACHE = os.path.join(HERE, "tuned.json")
 
 SPACE = {
     "item_grid": [0, 1],          # 1: one workgroup per item (needs march > 0)
-    "fuse_steps": [0, 2],         # 2: two steps per launch (needs item_grid 1)
+    "fuse_steps": [0, 2, 3],      # 2, 3: steps per launch (needs item_grid 1)
     "march": [0, 2, 4, 8],        # > 0: column-march pipeline, rows in flight
     "queue_order": [0, 1],        # 1: hot items longest first, the rest by position
     "hot_cut": [200, 120, 150, 300, 500],   # queue_order 1: hot above this % of the mean
