@@ -67,8 +67,10 @@ enum { LB_FP32 = 0, LB_FP32_KAHAN = 1, LB_FP64 = 2 };
 /* How lb_step runs a step. */
 enum {
     LB_PLAIN = 0,          /* one kernel launch per chunk, chunks in id order  */
-    LB_PERSISTENT = 1,     /* one persistent launch per step, replayed from a
-                              captured HIP graph                               */
+    LB_PERSISTENT = 1,     /* the balanced launch (persistent workgroups, or
+                              one workgroup per item, one step or fuse_steps
+                              steps per launch), replayed from a captured HIP
+                              graph                                            */
     LB_PLAIN_GRAPH = 2,    /* LB_PLAIN's launches replayed from a HIP graph    */
     LB_PERSISTENT_EAGER = 3 /* LB_PERSISTENT launched directly (no graph)      */
 };
@@ -237,7 +239,9 @@ int lb_grid_init(const lb_config *cfg, const lb_buffers *bufs, void *hip_stream,
 
 /* The time-step loop of Fig. 2.  Enqueue nsteps >= 0 time steps in the given
  * mode (LB_PLAIN, LB_PERSISTENT, LB_PLAIN_GRAPH, LB_PERSISTENT_EAGER);
- * asynchronous.  Every mode gives bit-identical fields and loads.  Loads of
+ * asynchronous.  Every mode gives bit-identical fields and loads.  With
+ * fuse_steps 2 or 3 the balanced modes launch that many steps at once while
+ * at least that many remain, and the rest in one shorter launch.  Loads of
  * every step are added to the current measurement window (Section V: the
  * measured time steps).  Errors: LB_E_INVAL (nsteps < 0, unknown mode),
  * LB_E_HIP (a capture or launch failed).  After LB_E_HIP the steps whose
