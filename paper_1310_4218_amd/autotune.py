@@ -2,8 +2,10 @@
 
     python -m paper_1310_4218_amd.autotune --workload moving [--precision fp32]
 
-Searches the launch parameters that do not change the method (tile_x,
-tile_y, nqueues, wg_per_queue, item_split, stage_rows, tail_split, item_alpha), keeping
+Searches the launch parameters that do not change the method (launch form
+item_grid, steps per launch fuse_steps, pipeline march / stage_rows, tile_x,
+tile_y, nqueues, wg_per_queue, queue order and hot_cut, item_split,
+tail_split, item_alpha), keeping
 everything that defines the problem fixed (grid, chunks, hotspots, number of
 balancer slots S).  Each candidate: a fresh context run in windows of R steps
 with a load measurement and a rebalance after each window, as the benchmark
