@@ -1,20 +1,26 @@
 // Device code of liblbgrid for gfx950 (CDNA4): the fused time-step kernel of
 // the over-decomposed grid (3D Jacobi update + column physics, Section IV and
 // Section VI Fig. 4 of the paper) with in-kernel per-chunk load measurement
-// (Section V), in two launch forms:
+// (Section V), in three launch forms:
 //   - plain: one launch per chunk over that chunk's items, chunks in id order;
 //   - persistent: one launch per step whose workgroups claim items from work
 //     queues with atomic counters (the chunks of balancer slot s, the paper's
 //     processors, feed queue s mod Q), optionally taking work from other
-//     queues once their own is empty.
+//     queues once their own is empty;
+//   - one workgroup per item, in the queues' order, the hardware dispatcher
+//     scheduling them; this form can also advance every item by two or three
+//     steps per launch (temporal blocking: each item recomputes the earlier
+//     steps on rings of cells around it, so that no intermediate step goes
+//     through memory).
 //
 // Data layout: field[((f*ny + y)*nx + x)*nz + z] (z fastest).  Chunks are cut
 // into tiles of up to TX x TY columns; a work item is a range of rows of one
 // tile (the whole tile unless the host split a costly tile into row ranges).
-// A workgroup has TX*nz/V threads; thread t owns V consecutive levels of
-// column t / (nz/V) of the current row.  The item is swept row by row (along
-// y) through a ring of LDS rows, each holding TX+2 columns (one halo column on
-// either side) of all nz levels: rows y-1, y, y+1 are read by the stencil
+// In the row pipelines a workgroup has TX*nz/V threads; thread t owns V
+// consecutive levels of column t / (nz/V) of the current row (the column
+// march, below, adds threads for the halo columns).  The item is swept row by
+// row (along y) through a ring of LDS rows, each holding TX+2 columns (one halo
+// column on either side) of all nz levels: rows y-1, y, y+1 are read by the stencil
 // while later rows are in flight, either straight into the ring (direct
 // global->LDS loads, B rows per batch) or through registers (2, 4 or 8 rows).
 // Every cell is read from HBM once per item and written once; halo columns and
