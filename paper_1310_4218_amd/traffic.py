@@ -6,6 +6,8 @@
     python -m paper_1310_4218_amd.traffic --fetch OUT/fetch --write OUT/write --workload W \
         --copy-mib 512
     python -m paper_1310_4218_amd.traffic stats OUT/stats --title T --command C --write F.md
+    python -m paper_1310_4218_amd.traffic counters OUT/pmc --kernel k_items2 --title T \
+        --command C --write F.md
 
 Both counters are reported in KiB per dispatch.  Each is scaled by what the
 same counter reads for the plain device copy of known size that bench.py runs
@@ -103,9 +105,57 @@ def stats_summary(outdir: str, title: str, command: str, top: int = 12) -> str:
     return "\n".join(out) + "\n"
 
 
+def counters_summary(outdir: str, kernel: str, title: str, command: str) -> str:
+    """Markdown table of every counter rocprofv3 --pmc collected under outdir for the
+    dispatches of `kernel` (each dispatch's value summed over the device, then the
+    mean over dispatches), with the dispatches' median duration when a kernel trace
+    was written too."""
+    per = {}
+    for path in glob.glob(os.path.join(outdir, "**", "*counter_collection*.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if kernel + "<" not in row.get("Kernel_Name", ""):
+                    continue
+                key = (row["Counter_Name"], row["Dispatch_Id"])
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    if not per:
+        raise FileNotFoundError(f"no counter values for {kernel} under {outdir}")
+    names = sorted({c for c, _ in per})
+    durs = []
+    for path in glob.glob(os.path.join(outdir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for t in csv.DictReader(f):
+                if kernel + "<" in t["Kernel_Name"]:
+                    durs.append(int(t["End_Timestamp"]) - int(t["Start_Timestamp"]))
+    out = [f"# {title}", "", "Command:", "", "```", command, "```", "",
+           "| counter | dispatches | mean per dispatch |", "|---|---|---|"]
+    for c in names:
+        v = [x for (n, _), x in per.items() if n == c]
+        out.append(f"| `{c}` | {len(v)} | {sum(v) / len(v):.4g} |")
+    if durs:
+        durs.sort()
+        out += ["", f"Median dispatch duration under the counters: {durs[len(durs) // 2] / 1e3:.1f} us "
+                    f"({len(durs)} dispatches)."]
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None) -> int:
     if argv is None:
         argv = sys.argv[1:]
+    if argv and argv[0] == "counters":
+        ap = argparse.ArgumentParser(prog="traffic counters")
+        ap.add_argument("outdir")
+        ap.add_argument("--kernel", required=True)
+        ap.add_argument("--title", required=True)
+        ap.add_argument("--command", required=True)
+        ap.add_argument("--write", help="markdown file to write")
+        a = ap.parse_args(argv[1:])
+        md = counters_summary(a.outdir, a.kernel, a.title, a.command)
+        if a.write:
+            with open(a.write, "w") as f:
+                f.write(md)
+        print(md)
+        return 0
     if argv and argv[0] == "stats":
         ap = argparse.ArgumentParser(prog="traffic stats")
         ap.add_argument("outdir")
