@@ -753,10 +753,15 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
     int* kbuf = reinterpret_cast<int*>(lds + 2 * RL);
     // byte offset of row i (-1 .. h) of this thread's column; out of range for
     // threads without a column and for rows past the item's last halo row
+    // items clear of the grid's y edges by the halo row need no wrap (uniform per item)
+    const bool inner = y0 >= 1 && y0 + h + 1 <= ny;
+    const uint32_t base = colbytes + static_cast<uint32_t>(inner ? y0 : 0) * rowbytes;
     auto row_off = [&](int i) -> uint32_t {
+        if (!streams || i > h) return kOutOfRange;
+        if (inner) return base + static_cast<uint32_t>(i) * rowbytes;
         int gy = y0 + i;
         gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-        return (streams && i <= h) ? colbytes + static_cast<uint32_t>(gy) * rowbytes : kOutOfRange;
+        return colbytes + static_cast<uint32_t>(gy) * rowbytes;
     };
     // trip counts of the item's columns, looked up once per item; the item's work
     // (k of every column, and the number of columns, each nz * nfields times) is
@@ -882,8 +887,12 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
     int* kb2 = kb1 + K1 * (a.tile_y + 2);
     // byte offset of row i (-2 .. h + 1) of this thread's column; out of range for
     // threads without a column and past the last row the item reads
+    // items clear of the grid's y edges by the halo need no wrap (uniform per item)
+    const bool inner = y0 >= 2 && y0 + h + 2 <= ny;
+    const uint32_t base = colbytes + static_cast<uint32_t>(inner ? y0 : 0) * rowbytes;
     auto row_off = [&](int i) -> uint32_t {
         if (!streams || i > h + 1) return kOutOfRange;
+        if (inner) return base + static_cast<uint32_t>(i) * rowbytes;
         return colbytes + static_cast<uint32_t>(wrap_near(y0 + i, ny)) * rowbytes;
     };
     // Trip counts of both steps, looked up once per item.  The item's work (its own
@@ -1036,8 +1045,12 @@ __device__ ItemOut3 process_item_march3(const DevArgs& a, const ItemDesc& d, con
     int* kb3 = kb2 + K2 * (a.tile_y + 2);
     // byte offset of row i (-3 .. h + 2) of this thread's column; out of range for
     // threads without a column and past the last row the item reads
+    // items clear of the grid's y edges by the halo need no wrap (uniform per item)
+    const bool inner = y0 >= 3 && y0 + h + 3 <= ny;
+    const uint32_t base = colbytes + static_cast<uint32_t>(inner ? y0 : 0) * rowbytes;
     auto row_off = [&](int i) -> uint32_t {
         if (!streams || i > h + 2) return kOutOfRange;
+        if (inner) return base + static_cast<uint32_t>(i) * rowbytes;
         return colbytes + static_cast<uint32_t>(wrap_near(y0 + i, ny)) * rowbytes;
     };
     // trip counts of the three steps; the item's work (its own columns in each
