@@ -223,7 +223,8 @@ def run_ablation(Grid, wl, steps, warmup, R, params, torch, balance_host):
     import numpy as np
 
     S = wl.nslots
-    p = {k: v for k, v in params.items() if k not in ("nqueues", "steal", "wg_per_queue", "item_grid", "fuse_steps")}
+    p = {k: v for k, v in params.items() if k not in ("nqueues", "steal", "wg_per_queue", "item_grid", "fuse_steps",
+                                                         "lane_levels")}
     block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)],
                      dtype=np.int32)
     out = {}
@@ -313,7 +314,8 @@ def main(argv=None) -> int:
         wl = wl.replace(vertical=1)
     R = wl.rebalance_every or 10
     S = wl.nslots
-    params = {} if args.no_tuned else tuned_params(args.workload, args.precision)
+    params = {} if args.no_tuned else tuned_params(args.workload, args.precision,
+                                                   physics="vertical" if args.vertical else "pointwise")
     for kv in args.set:
         k, v = kv.split("=")
         params[k] = int(v)

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 5
+#define LB_ABI_VERSION 6
 #define LB_MAX_HOT 4
 #define LB_NBUF 3
 
@@ -176,6 +176,14 @@ typedef struct {
                                 a remainder ending on a two- or one-step
                                 launch.  0 or 1 = one step per launch
                                 (default)                                     */
+    int32_t lane_levels;     /* levels per thread V of the two-step launch: 0
+                                or 4 = 4 (default); 5 = 5, with nz / 5
+                                threads per column, for nz whose nz / 4
+                                threads per column would straddle waves (nz =
+                                80: 16 threads, four whole columns per wave).
+                                5 needs fuse_steps 2, march 2 or 4 and nz % 20
+                                == 0 (the one-step launches keep 4 levels per
+                                thread).  Same bits for either V.            */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;

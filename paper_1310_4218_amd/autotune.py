@@ -51,19 +51,28 @@ def _key(arch: str, workload: str, precision: str) -> str:
     return f"{arch}/{workload}/{precision}"
 
 
-def tuned_params(workload_name: str, precision: str = "fp32", arch: str = None) -> dict:
+def tuned_params(workload_name: str, precision: str = "fp32", arch: str = None,
+                 physics: str = "pointwise") -> dict:
     """Cached launch parameters for a workload, or {} when none were tuned.  FP32
     with Kahan summation has the FP32 data layout and kernels; without an entry
-    of its own it takes the FP32 one."""
+    of its own it takes the FP32 one.  physics "vertical" takes an entry of its
+    own (key suffix /vertical) where there is one, else the pointwise one."""
     if not os.path.exists(CACHE):
         return {}
     with open(CACHE) as f:
         cache = json.load(f)
     if arch is None:
         arch = "gfx950"
-    entry = cache.get(_key(arch, workload_name, precision))
-    if entry is None and precision in ("fp32_kahan", "kahan"):
-        entry = cache.get(_key(arch, workload_name, "fp32"))
+    entry = None
+    precs = (precision, "fp32") if precision in ("fp32_kahan", "kahan") else (precision,)
+    suffixes = ("/vertical", "") if physics == "vertical" else ("",)
+    for suf in suffixes:
+        for pr in precs:
+            entry = cache.get(_key(arch, workload_name, pr) + suf)
+            if entry is not None:
+                break
+        if entry is not None:
+            break
     return dict((entry or {}).get("params", {}))
 
 

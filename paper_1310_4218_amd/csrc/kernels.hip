@@ -48,8 +48,10 @@ namespace {
 
 constexpr int kWave = 64;
 
+// V levels of one thread, aligned to their size when V is a power of two (one
+// wide LDS access); V = 5 is aligned to one element
 template <typename T, int V>
-struct alignas(sizeof(T) * V) Vec {
+struct alignas(sizeof(T) * ((V & (V - 1)) == 0 ? V : 1)) Vec {
     T v[V];
 };
 
@@ -589,7 +591,7 @@ constexpr int kPipeMarch = 100;
 // branch around them).
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 // Far enough above every field (fields are limited to 0xFFFFFE00 bytes) that no
-// part of a 32-byte access from it wraps round to a valid offset.
+// part of a 40-byte access from it wraps round to a valid offset.
 constexpr uint32_t kOutOfRange = 0xFFFFFF00u;
 constexpr int kRsrcWord3 = 0x00020000;   // gfx9 buffer format word: 32-bit data, no swizzle
 
@@ -599,52 +601,59 @@ __device__ __forceinline__ rsrc_t field_rsrc(const void* base, uint32_t bytes) {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
+// Raw loads and stores of 4, 8 or 16 bytes at byte offset off; group_load and
+// group_store cover N bytes with the widest pieces first (so 20 bytes are 16 + 4).
+template <int N>
+__device__ __forceinline__ void group_load(rsrc_t r, uint32_t off, char* x) {
+    if constexpr (N >= 16) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0);
+        __builtin_memcpy(x, &v, 16);
+        group_load<N - 16>(r, off + 16u, x + 16);
+    } else if constexpr (N >= 8) {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0);
+        __builtin_memcpy(x, &v, 8);
+        group_load<N - 8>(r, off + 8u, x + 8);
+    } else if constexpr (N >= 4) {
+        const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0);
+        __builtin_memcpy(x, &v, 4);
+        group_load<N - 4>(r, off + 4u, x + 4);
+    } else {
+        static_assert(N == 0, "element groups are whole multiples of 4 bytes");
+    }
+}
+template <int N, int AUX>
+__device__ __forceinline__ void group_store(rsrc_t r, uint32_t off, const char* x) {
+    if constexpr (N >= 16) {
+        u32x4 v;
+        __builtin_memcpy(&v, x, 16);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, static_cast<int>(off), 0, AUX);
+        group_store<N - 16, AUX>(r, off + 16u, x + 16);
+    } else if constexpr (N >= 8) {
+        u32x2 v;
+        __builtin_memcpy(&v, x, 8);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, static_cast<int>(off), 0, AUX);
+        group_store<N - 8, AUX>(r, off + 8u, x + 8);
+    } else if constexpr (N >= 4) {
+        unsigned v;
+        __builtin_memcpy(&v, x, 4);
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, static_cast<int>(off), 0, AUX);
+        group_store<N - 4, AUX>(r, off + 4u, x + 4);
+    } else {
+        static_assert(N == 0, "element groups are whole multiples of 4 bytes");
+    }
+}
 template <typename T, int V>
 __device__ __forceinline__ Vec<T, V> bload(rsrc_t r, uint32_t off) {
-    constexpr int B = static_cast<int>(sizeof(T)) * V;
+    static_assert(sizeof(T) * V <= 40, "at most 40 bytes per thread and row");
     Vec<T, V> x;
-    if constexpr (B == 32) {
-        const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0);
-        const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off + 16u), 0, 0);
-        __builtin_memcpy(&x, &lo, 16);
-        __builtin_memcpy(reinterpret_cast<char*>(&x) + 16, &hi, 16);
-    } else if constexpr (B == 16) {
-        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0);
-        __builtin_memcpy(&x, &v, 16);
-    } else if constexpr (B == 8) {
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0);
-        __builtin_memcpy(&x, &v, 8);
-    } else {
-        static_assert(B == 4, "element group of 4, 8, 16 or 32 bytes");
-        const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0);
-        __builtin_memcpy(&x, &v, 4);
-    }
+    group_load<static_cast<int>(sizeof(T)) * V>(r, off, reinterpret_cast<char*>(&x));
     return x;
 }
 // AUX: the store's cache policy; 2 marks it non-temporal (streamed past the
 // caches), for output that is not read again before the whole field has gone by.
 template <typename T, int V, int AUX>
 __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, const Vec<T, V>& x) {
-    constexpr int B = static_cast<int>(sizeof(T)) * V;
-    if constexpr (B == 32) {
-        u32x4 lo, hi;
-        __builtin_memcpy(&lo, &x, 16);
-        __builtin_memcpy(&hi, reinterpret_cast<const char*>(&x) + 16, 16);
-        __builtin_amdgcn_raw_buffer_store_b128(lo, r, static_cast<int>(off), 0, AUX);
-        __builtin_amdgcn_raw_buffer_store_b128(hi, r, static_cast<int>(off + 16u), 0, AUX);
-    } else if constexpr (B == 16) {
-        u32x4 v;
-        __builtin_memcpy(&v, &x, 16);
-        __builtin_amdgcn_raw_buffer_store_b128(v, r, static_cast<int>(off), 0, AUX);
-    } else if constexpr (B == 8) {
-        u32x2 v;
-        __builtin_memcpy(&v, &x, 8);
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, static_cast<int>(off), 0, AUX);
-    } else {
-        unsigned v;
-        __builtin_memcpy(&v, &x, 4);
-        __builtin_amdgcn_raw_buffer_store_b32(v, r, static_cast<int>(off), 0, AUX);
-    }
+    group_store<static_cast<int>(sizeof(T)) * V, AUX>(r, off, reinterpret_cast<const char*>(&x));
 }
 
 // One cell group of the march: the 7-point update of this thread's V levels
@@ -680,8 +689,8 @@ __device__ __forceinline__ void cell_update(const DevArgs& a, const T* Lc, const
 // Thread -> (column tcol, lane tzq of the column) of a march workgroup whose
 // thread columns 0 .. TX + 2 HALO - 1 stream grid columns x0 - HALO + tcol.
 // Threads are grouped in column slots: dense, NQ consecutive threads per slot;
-// with col_per_wave > 0 (the vertical physics when NQ does not divide 64)
-// every wave holds col_per_wave whole slots in its first lanes and leaves the
+// with cpw > 0 (the vertical physics when NQ does not divide 64)
+// every wave holds cpw whole slots in its first lanes and leaves the
 // rest idle, so that a column's lanes never straddle two waves.  Slots 0 ..
 // TX - 1 hold the item's own columns, the slots after them the halo columns,
 // innermost first, alternating left and right.  The item's columns thus fill
@@ -689,15 +698,15 @@ __device__ __forceinline__ void cell_update(const DevArgs& a, const T* Lc, const
 // of the cells it does not compute (a wave issues its vector instructions for
 // all of its lanes, idle or not).  Returns whether the lane is used.
 template <int HALO>
-__device__ __forceinline__ bool march_lane(const DevArgs& a, int NQ, int TX, int& tcol, int& tzq) {
+__device__ __forceinline__ bool march_lane(int cpw, int NQ, int TX, int& tcol, int& tzq) {
     int slot;
     bool used = true;
-    if (a.col_per_wave > 0) {
+    if (cpw > 0) {
         const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
         const int cw = lane / NQ;
-        slot = (static_cast<int>(threadIdx.x) >> 6) * a.col_per_wave + cw;
+        slot = (static_cast<int>(threadIdx.x) >> 6) * cpw + cw;
         tzq = lane - cw * NQ;
-        used = cw < a.col_per_wave;
+        used = cw < cpw;
     } else {
         slot = threadIdx.x / NQ;
         tzq = threadIdx.x - slot * NQ;
@@ -737,7 +746,7 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
     const int TX = a.tile_x;
     const int BS = a.block;                   // == blockDim.x (at least (TX + 2) columns)
     int tcol, tzq;
-    const bool lane_used = march_lane<1>(a, NQ, TX, tcol, tzq);
+    const bool lane_used = march_lane<1>(a.col_per_wave, NQ, TX, tcol, tzq);
     const int zoff = tzq * V;
     const int x0 = d.x0, y0 = d.y0;
     const int w = d.wh & 0xffff;
@@ -850,6 +859,9 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
 // once and written once for both steps.  The workgroup has (TX + 4) * NQ
 // threads (or whole columns per wave, as in the one-step march): thread
 // column tcol streams grid column x0 - 2 + tcol, rows -2 .. h + 1 of the item.
+// V is 4 or 5 levels per thread (NQ = nz / V threads per column): 5 where
+// nz / 4 threads would leave a column's lanes straddling waves, e.g. nz = 80
+// gives 16 threads per column and whole waves of columns.
 // Threads 1 .. w + 2 compute step s + 1 on the columns -1 .. w and rows
 // -1 .. h (the item and the ring of cells around it that the item's next
 // update reads); threads 2 .. w + 1 compute step s + 2 on the item's own cells
@@ -869,7 +881,7 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
     const int TX = a.tile_x;
     const int BS = a.block2;                  // == blockDim.x (at least (TX + 4) columns)
     int tcol, tzq;
-    const bool lane_used = march_lane<2>(a, NQ, TX, tcol, tzq);
+    const bool lane_used = march_lane<2>(a.col_per_wave2, NQ, TX, tcol, tzq);
     const int zoff = tzq * V;
     const int x0 = d.x0, y0 = d.y0;
     const int w = d.wh & 0xffff;
@@ -1025,7 +1037,7 @@ __device__ ItemOut3 process_item_march3(const DevArgs& a, const ItemDesc& d, con
     const int TX = a.tile_x;
     const int BS = a.block3;                  // == blockDim.x (at least (TX + 6) columns)
     int tcol, tzq;
-    const bool lane_used = march_lane<3>(a, NQ, TX, tcol, tzq);
+    const bool lane_used = march_lane<3>(a.col_per_wave, NQ, TX, tcol, tzq);
     const int zoff = tzq * V;
     const int x0 = d.x0, y0 = d.y0;
     const int w = d.wh & 0xffff;
@@ -1992,17 +2004,19 @@ ItemsFn pick_items(int prec, int pipe) {
     return items_for<float, 0>(pipe);
 }
 template <typename T, int KAHAN>
-ItemsFn items2_for(int pipe) {
+ItemsFn items2_for(int vec, int pipe) {
+    if (vec == 5)   // rows in flight: 2 or 4
+        return pipe == kPipeMarch + 4 ? k_items2<T, 5, KAHAN, 4> : k_items2<T, 5, KAHAN, 2>;
     switch (pipe) {
         case kPipeMarch + 4: return k_items2<T, 4, KAHAN, 4>;
         case kPipeMarch + 8: return k_items2<T, 4, KAHAN, 8>;
         default: return k_items2<T, 4, KAHAN, 2>;
     }
 }
-ItemsFn pick_items2(int prec, int pipe) {
-    if (prec == 2) return items2_for<double, 0>(pipe);
-    if (prec == 1) return items2_for<float, 1>(pipe);
-    return items2_for<float, 0>(pipe);
+ItemsFn pick_items2(int prec, int vec, int pipe) {
+    if (prec == 2) return items2_for<double, 0>(vec, pipe);
+    if (prec == 1) return items2_for<float, 1>(vec, pipe);
+    return items2_for<float, 0>(vec, pipe);
 }
 template <typename T, int KAHAN>
 ItemsFn items3_for(int pipe) {
@@ -2070,9 +2084,10 @@ int launch_items(const DevArgs& a, int prec, int vec, int nitems, int block, siz
 
 int launch_items2(const DevArgs& a, int prec, int vec, int nitems, int block, size_t lds, int slot,
                   void* stream) {
-    if (vec != 4 || a.march <= 0 || nitems <= 0 || block != a.block2)
+    if ((vec != 4 && vec != 5) || (vec == 5 && a.march == 8) || a.march <= 0 || nitems <= 0 ||
+        block != a.block2)
         return static_cast<int>(hipErrorInvalidValue);
-    hipLaunchKernelGGL(pick_items2(prec, pipe_of(a)), dim3(nitems), dim3(block), lds,
+    hipLaunchKernelGGL(pick_items2(prec, vec, pipe_of(a)), dim3(nitems), dim3(block), lds,
                        static_cast<hipStream_t>(stream), a, slot);
     return static_cast<int>(hipGetLastError());
 }

@@ -109,6 +109,7 @@ struct DevArgs {
     int32_t vertical;          // 1: column physics with the vertical dependency
     int32_t col_per_wave;      // > 0: the march puts this many whole columns in each wave
                                // (vertical physics with nz / V not dividing 64); 0: dense
+    int32_t col_per_wave2;     // the same for the two-step launch, whose V may differ
     int32_t r2cut;
     int32_t kmin;
     int32_t alpha;

@@ -61,6 +61,8 @@ struct Plan {
     int32_t block3 = 0;     // ... of the three-step item launch
     size_t lds3 = 0;
     int32_t CPW = 0;        // march: whole columns per wave (vertical physics, NQ not dividing 64)
+    int32_t vec2 = 4;       // levels per thread of the two-step launch (4 or 5)
+    int32_t CPW2 = 0;       // its whole columns per wave
     int32_t B = 0;          // rows per direct global->LDS batch; 0 = register pipeline
     int32_t ring = 4;       // LDS ring rows
     int32_t r2cut = 0;
@@ -181,6 +183,13 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->item_grid == 1 && c->march == 0) return bad("item_grid needs the column-march pipeline (march > 0)");
     if (c->fuse_steps < 0 || c->fuse_steps > 3) return bad("fuse_steps must be 0, 1, 2 or 3");
     if (c->fuse_steps >= 2 && c->item_grid != 1) return bad("fuse_steps 2 or 3 needs item_grid 1");
+    if (c->lane_levels != 0 && c->lane_levels != 4 && c->lane_levels != 5)
+        return bad("lane_levels must be 0, 4 or 5");
+    if (c->lane_levels == 5 && c->fuse_steps != 2) return bad("lane_levels 5 needs fuse_steps 2");
+    if (c->lane_levels == 5 && c->nz % 20 != 0)
+        return bad("lane_levels 5 needs nz divisible by 20 (5 levels per thread in the two-step launch, "
+                   "4 in the one-step launches)");
+    if (c->lane_levels == 5 && c->march != 2 && c->march != 4) return bad("lane_levels 5 needs march 2 or 4");
 
     p.nx = c->nx; p.ny = c->ny; p.nz = c->nz; p.nfields = c->nfields;
     p.px = c->px; p.py = c->py; p.C = c->px * c->py; p.S = c->nslots;
@@ -207,6 +216,9 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
                     "vertical physics needs nz / V <= 64 lanes per column, and the column-march "
                     "pipeline (march > 0) unless nz / V divides 64 (V = 4, 2 or 1 by divisibility of nz)");
     p.CPW = (c->physics == LB_PHYS_VERTICAL && c->march > 0 && 64 % NQ != 0) ? 64 / NQ : 0;
+    p.vec2 = c->lane_levels == 5 ? 5 : 4;
+    const int NQ2 = p.nz / p.vec2;
+    p.CPW2 = c->lane_levels == 5 ? ((c->physics == LB_PHYS_VERTICAL && 64 % NQ2 != 0) ? 64 / NQ2 : 0) : p.CPW;
     // pipeline: the column march (M rows in flight), direct global->LDS batches of B
     // rows (V = 4 only) or the register path
     p.M = c->march;
@@ -238,8 +250,8 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     // the two-step item launch: two halo columns on either side, four LDS rows
     // (two of each step) and the trip counts of both steps
     auto threads2_for = [&](int tx) {
-        if (p.CPW > 0) return (tx + 4 + p.CPW - 1) / p.CPW * 64;
-        return (tx + 4) * NQ;
+        if (p.CPW2 > 0) return (tx + 4 + p.CPW2 - 1) / p.CPW2 * 64;
+        return (tx + 4) * NQ2;
     };
     auto lds2_for = [&](int tx) {
         return size_t{4} * (tx + 4) * col_bytes +
@@ -281,8 +293,10 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
         p.block2 = threads2_for(p.TX);
         p.lds2 = lds2_for(p.TX);
         if (p.block2 > most)
-            return bad(p.prec == LB_FP64 ? "fuse_steps 2 in FP64 needs (tile_x + 4) * nz / 4 <= 512 threads"
-                                         : "fuse_steps 2 needs (tile_x + 4) * nz / 4 <= 1024 threads");
+            return bad(p.prec == LB_FP64 ? "fuse_steps 2 in FP64 needs (tile_x + 4) * nz / V <= 512 threads "
+                                           "(V = lane_levels, else 4)"
+                                         : "fuse_steps 2 needs (tile_x + 4) * nz / V <= 1024 threads "
+                                           "(V = lane_levels, else 4)");
         if (p.lds2 > kMaxLds) return bad("tile too large for fuse_steps 2: its LDS rows and trip counts exceed 160 KiB");
     }
     if (p.F == 3) {
@@ -768,7 +782,7 @@ int launch_balanced(lb_ctx* x, int slot, int n, hipStream_t s) {
     const Plan& p = x->plan;
     const int nitems = static_cast<int>(x->items.size());
     if (p.IG && n == 3) return launch_items3(x->args, p.prec, p.vec, nitems, p.block3, p.lds3, slot, s);
-    if (p.IG && n == 2) return launch_items2(x->args, p.prec, p.vec, nitems, p.block2, p.lds2, slot, s);
+    if (p.IG && n == 2) return launch_items2(x->args, p.prec, p.vec2, nitems, p.block2, p.lds2, slot, s);
     if (n != 1) return static_cast<int>(hipErrorInvalidValue);
     if (p.IG) return launch_items(x->args, p.prec, p.vec, nitems, p.block, p.lds, slot, s);
     return launch_persistent(x->args, p.prec, p.vec, p.nwg, p.block, p.lds, s);
@@ -852,6 +866,7 @@ void lb_config_default(lb_config* c) {
     c->hot_cut = 200;
     c->item_grid = 0;
     c->fuse_steps = 0;
+    c->lane_levels = 0;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {
@@ -981,6 +996,7 @@ int lb_grid_init(const lb_config* cfg, const lb_buffers* bufs, void* hip_stream,
     a.field_bytes = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(P.ncells) * P.elem, 0xFFFFFFFFull));
     a.vertical = cfg->physics == LB_PHYS_VERTICAL ? 1 : 0;
     a.col_per_wave = P.CPW;
+    a.col_per_wave2 = P.CPW2;
     if (P.G == 0) {  // as many workgroups as can be resident, split evenly over the queues
         int ncu = 0;
         if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device)) != hipSuccess)

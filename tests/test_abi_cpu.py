@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_struct_layout_and_version(lib):
-    assert lib.lb_abi_version() == 5
+    assert lib.lb_abi_version() == 6
     assert lib.lb_config_bytes() == C.sizeof(_abi.LbConfig)
     assert lib.lb_stats_bytes() == C.sizeof(_abi.LbStats)
 
@@ -85,6 +85,11 @@ def test_query_rejects_bad_config(lib, field, value, msg):
     (dict(fuse_steps=3, march=2, item_grid=1, precision=2, tile_x=59), "fuse_steps 3 in FP64"),
     (dict(fuse_steps=2, march=2, item_grid=1, precision=2, tile_x=61), "fuse_steps 2 in FP64"),
     (dict(fuse_steps=2, march=2, item_grid=1, tile_x=125), "fuse_steps 2 needs (tile_x + 4)"),
+    (dict(lane_levels=3), "lane_levels must be"),
+    (dict(lane_levels=5, march=2, item_grid=1), "lane_levels 5 needs fuse_steps 2"),
+    (dict(lane_levels=5, march=2, item_grid=1, fuse_steps=3), "lane_levels 5 needs fuse_steps 2"),
+    (dict(lane_levels=5, march=2, item_grid=1, fuse_steps=2), "nz divisible by 20"),
+    (dict(lane_levels=5, march=8, item_grid=1, fuse_steps=2, nz=40), "march 2 or 4"),
 ])
 def test_query_rejects_bad_pipeline(lib, over, msg):
     """Register pipeline depths are 2, 4 or 8 rows; the deep ones need V = 4 and
@@ -92,7 +97,9 @@ def test_query_rejects_bad_pipeline(lib, over, msg):
     takes 2, 4 or 8 rows in flight, needs V = 4 and (tile_x + 2) * nz / 4 threads, at
     most 512 in FP64; two steps per launch need item_grid 1 and (tile_x + 4) * nz / 4
     threads, three steps (tile_x + 6) * nz / 4.  (64x64x32: tile_x 61 and 125 fit one step
-    per launch but not two; tile_x 59 fits two in FP64 but not three.)"""
+    per launch but not two; tile_x 59 fits two in FP64 but not three.)  Five levels per
+    thread (lane_levels 5) is for the two-step launch only, with nz % 20 == 0 and 2 or 4
+    rows in flight."""
     cfg, keep = _abi.config_from_workload(W.small())
     for k, v in over.items():
         setattr(cfg, k, v)

@@ -42,3 +42,17 @@ def test_kahan_takes_the_fp32_launch_shape():
     for w in ("moving", "precision", "large"):
         assert tuned_params(w, "fp32_kahan") == tuned_params(w, "fp32")
     assert tuned_params("no-such-workload", "fp32_kahan") == {}
+
+
+def test_vertical_physics_takes_its_own_launch_where_tuned():
+    """The 2048x2048x80 grid's vertical physics runs its two-step launch with 5 levels
+    per thread (16 lanes per column); the pointwise launch keeps 4.  Workloads without a
+    vertical entry take their pointwise one."""
+    from paper_1310_4218_amd import _abi
+    from paper_1310_4218_amd import workloads as W
+    vert = tuned_params("large", "fp32", physics="vertical")
+    assert vert.get("lane_levels") == 5 and "lane_levels" not in tuned_params("large", "fp32")
+    assert {k: v for k, v in vert.items() if k != "lane_levels"} == tuned_params("large", "fp32")
+    assert tuned_params("large", "fp32_kahan", physics="vertical") == vert
+    _abi.query(_abi.config_from_workload(W.get("large").replace(vertical=1), **vert)[0])
+    assert tuned_params("precision", "fp32", physics="vertical") == tuned_params("precision", "fp32")

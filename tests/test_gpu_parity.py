@@ -271,6 +271,51 @@ def test_fused_steps_wide_tiles_and_small_grids_fp64(fuse):
         g.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_kahan"])
+def test_fused_steps_five_levels_per_thread(precision):
+    """The two-step launch with 5 levels per thread (nz = 80: 16 threads per column, four
+    whole columns per wave): fields bit-identical to those of 4 levels per thread (and to
+    the oracle's in FP64) through fused launches, single-step remainders, graphs and a
+    rebalance; per-step checksums equal to rounding, loads equal to the oracle's, and every
+    tile row computed once per step; regular and ragged tiles, 2 and 4 rows in flight."""
+    wl = mk(40, 36, 80, 4, 3, hot=((5, 4, 1, 2),), split="dirichlet", steps=9, nslots=5)
+    ref, work, ck, _ = oracle.run(wl, nsteps=9)
+    prog = [(2, "persistent_eager"), (3, "persistent"), ("measure", 5), ("rebalance", 0),
+            (1, "plain"), (3, "persistent_eager"), ("measure", 9)]
+
+    def run(**over):
+        g = Grid(wl, precision=precision, item_grid=1, fuse_steps=2, graph_steps=3, **over)
+        loads = []
+        for n, mode in prog:
+            if n == "measure":
+                loads.append(g.measure("work"))
+            elif n == "rebalance":
+                g.rebalance("greedy")
+            else:
+                g.step(n, mode)
+        return g, loads
+
+    for over in (dict(march=4, tile_x=8, tile_y=6), dict(march=2, tile_x=5, tile_y=3)):
+        say("five levels", precision, over)
+        g, loads = run(lane_levels=5, **over)
+        assert g.stats()["block2"] == (over["tile_x"] + 4) * 16
+        np.testing.assert_array_equal(loads[0], work[:5].sum(axis=0))
+        np.testing.assert_array_equal(loads[1], work[5:].sum(axis=0))
+        assert np.all(g.visits() == 9)
+        four, _ = run(**over)
+        assert four.stats()["block2"] == (over["tile_x"] + 4) * 20
+        q = gpu_fields(g)
+        np.testing.assert_array_equal(q, gpu_fields(four))
+        np.testing.assert_allclose(g.checksums(9), four.checksums(9), rtol=1e-12, atol=1e-9)
+        if precision == "fp64":
+            np.testing.assert_array_equal(q, ref)
+            np.testing.assert_allclose(g.checksums(9), ck, rtol=1e-12, atol=1e-9)
+        else:
+            assert rel_err(q, ref) <= TOL
+        four.close()
+        g.close()
+
+
 def test_measure_in_two_halves():
     """lb_measure_begin snapshots the window behind the steps enqueued so far; steps
     enqueued before lb_measure_end belong to the next window; the rebalance waits for the
@@ -613,12 +658,12 @@ def test_moving_full_size_fp32_step_error():
 
 
 # ------------------------------------------------------------------ full sizes, sampled outputs
-def _launch(name, precision):
+def _launch(name, precision, physics="pointwise"):
     """The benchmark's launch parameters for a workload (tile shapes dropped where the
     wider FP64 rows would not fit the LDS ring)."""
     from paper_1310_4218_amd import _abi
     from paper_1310_4218_amd.autotune import tuned_params
-    p = tuned_params(name, "fp32")
+    p = tuned_params(name, "fp32", physics=physics)
     p.pop("precision", None)
     p["precision"] = precision
     try:
@@ -824,12 +869,16 @@ def test_vertical_physics_fp64_bit_exact(nz):
 @pytest.mark.parametrize("name", ["precision", "large"])
 def test_vertical_physics_full_size_fp64_windows(name):
     """The vertical column physics at full size in the benchmark's launch configuration
-    (the 2048x2048x80 grid has 20 lanes per column, laid out as whole columns per wave):
-    after 6 steps with a rebalance, FP64 sampled windows equal the windowed oracle's and
-    the loads equal the oracle's."""
+    (the 2048x2048x80 grid: 20 lanes per column, laid out as whole columns per wave, in
+    the one-step launches, 16 lanes per column with 5 levels per thread in the two-step
+    launch): after 6 steps with a rebalance, FP64 sampled windows equal the windowed
+    oracle's and the loads equal the oracle's."""
     wl = W.get(name).replace(vertical=1)
     T = 6
-    g = Grid(wl, **_launch(name, "fp64"))
+    launch = _launch(name, "fp64", "vertical")
+    if name == "large":
+        assert launch.get("lane_levels") == 5
+    g = Grid(wl, **launch)
     g.step(3)
     np.testing.assert_array_equal(g.measure("work"), _oracle_loads(wl, 0, 3))
     g.rebalance(wl.strategy, wl.threshold)
@@ -867,13 +916,17 @@ def test_vertical_physics_rejects_unsupported_nz():
 @pytest.mark.parametrize("nz", [80, 40, 48, 100, 12])
 def test_vertical_physics_whole_columns_per_wave_fp64(nz):
     """nz / 4 lanes per column not dividing 64: the march puts 64 // (nz / 4) whole columns
-    in each wave; FP64 fields and loads equal the oracle's in every balanced form."""
+    in each wave; FP64 fields and loads equal the oracle's in every balanced form.  With 5
+    levels per thread in the two-step launch (nz % 20 == 0) 80 and 40 levels give 16 and 8
+    lanes per column (dense), 100 levels 20 (whole columns per wave again)."""
     wl = mk(40, 36, nz, 4, 3, kmax=40, sigma=5.0, split="dirichlet", steps=3).replace(vertical=1)
     ref, work, _, _ = oracle.run(wl, nsteps=3)
     for over in (dict(march=2), dict(march=4, tile_x=3, tile_y=4), dict(march=8, tile_x=7, tile_y=9),
                  dict(march=4, item_grid=1, tile_x=5, tile_y=3), dict(march=2, item_grid=1),
                  dict(march=4, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3),
-                 dict(march=2, item_grid=1, fuse_steps=2), dict(march=2, item_grid=1, fuse_steps=3)):
+                 dict(march=2, item_grid=1, fuse_steps=2), dict(march=2, item_grid=1, fuse_steps=3)) + \
+            ((dict(march=4, item_grid=1, fuse_steps=2, lane_levels=5, tile_x=5, tile_y=3),
+              dict(march=2, item_grid=1, fuse_steps=2, lane_levels=5)) if nz % 20 == 0 else ()):
         for mode in ("persistent", "plain"):
             g, q, w = run_gpu(wl, 3, mode, precision="fp64", **over)
             np.testing.assert_array_equal(q, ref)
