@@ -39,6 +39,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 
 #include "lbgrid.h"
 #include "lbgrid_internal.h"
@@ -658,8 +659,9 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, const Vec<T, V>& 
 
 // One cell group of the march: the 7-point update of this thread's V levels
 // of the current row (x and z neighbours from the row in LDS at Lc, y
-// neighbours ym and yp), then the column physics with k iterations.
-template <typename T, int V, int KAHAN>
+// neighbours ym and yp), then the column physics with k iterations.  PHYS:
+// 0 pointwise, 1 vertical, -1 as a.vertical says.
+template <typename T, int V, int KAHAN, int PHYS = -1>
 __device__ __forceinline__ void cell_update(const DevArgs& a, const T* Lc, const Vec<T, V>& c,
                                             const Vec<T, V>& ym, const Vec<T, V>& yp, int tzq, int NQ,
                                             int nz, int k, T cc, T cn, T eps, T (&q)[V]) {
@@ -680,7 +682,7 @@ __device__ __forceinline__ void cell_update(const DevArgs& a, const T* Lc, const
         sum = sum + zp;
         q[v] = combine(cc, cn, c.v[v], sum);
     }
-    if (a.vertical)
+    if (PHYS == 1 || (PHYS < 0 && a.vertical))
         physics_vertical<T, V>(eps, k, tzq, NQ, q);
     else
         physics_vec<KAHAN, T, V>(eps, k, q);
@@ -940,71 +942,96 @@ __device__ ItemOut2 process_item_march2(const DevArgs& a, const ItemDesc& d, con
                                               // across fields: consecutive rows never share one)
     double chk1 = 0.0, chk2 = 0.0;
     const int n_it = h + 2;                   // iteration n computes step s + 1 on row n - 1
-    for (int f = 0; f < a.nfields; ++f) {
-        const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
-        const rsrc_t out = field_rsrc(dst + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
-        Vec<T, V> ym = bload<T, V>(in, row_off(-2));   // step s rows i - 1, i, then i + 1 ..
-        Vec<T, V> c = bload<T, V>(in, row_off(-1));
-        Vec<T, V> R[D];
+    // Rows of step s sit in a ring of U = D + 2 register rows, row r in slot
+    // (r + 2) mod U: rows r - 1, r, r + 1 of the update and D rows in flight.  Rows
+    // of step s + 1 sit in a ring of P1 rows (the smallest divisor of U of at least
+    // 3), row r in slot (r + 1) mod P1.  The row loop is unrolled U times, so every
+    // slot is a constant register row and no row is ever copied between registers;
+    // it is compiled once for each trip-count form (uniform or per column) and
+    // physics, so no branch of the body merges values from another.
+    constexpr int U = D + 2;
+    constexpr int P1 = (U % 3 == 0) ? 3 : (U % 4 == 0) ? 4 : (U % 5 == 0) ? 5 : U;
+    auto rows = [&](auto uni_c, auto phys_c) {
+        constexpr bool UNI = decltype(uni_c)::value;
+        constexpr int PHYS = decltype(phys_c)::value;
+        for (int f = 0; f < a.nfields; ++f) {
+            const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+            const rsrc_t out = field_rsrc(dst + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+            Vec<T, V> R[U];                   // step s rows -2 .. D - 1 to start
 #pragma unroll
-        for (int j = 0; j < D; ++j) R[j] = bload<T, V>(in, row_off(j));
-        Vec<T, V> s1m{}, s1c{};               // step s + 1 rows i - 2 and i - 1
-        for (int n0 = 0; n0 < n_it; n0 += D) {
+            for (int j = 0; j < U; ++j) R[j] = bload<T, V>(in, row_off(j - 2));
+            Vec<T, V> S[P1];                  // step s + 1 rows
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const int n = n0 + j;
-                if (n < n_it) {
-                    const int i = n - 1;
-                    T* const LA = lrow + par * RL;         // step s, row i
-                    T* const LB = lrow + (2 + par) * RL;   // step s + 1, row i - 1
-                    par ^= 1;
-                    if (streams) st<T, V>(LA, c);
-                    if (act1) st<T, V>(LB, s1c);
-                    __syncthreads();
-                    const Vec<T, V> yp = R[j];
-                    R[j] = bload<T, V>(in, row_off(n + D));
-                    Vec<T, V> s1n;                    // (used only where act1 sets it)
-                    if (act1) {
-                        T q[V];
-                        if (uniform)
-                            cell_update<T, V, KAHAN>(a, LA, c, ym, yp, tzq, NQ, nz, ku, cc, cn, eps, q);
-                        else
-                            cell_update<T, V, KAHAN>(a, LA, c, ym, yp, tzq, NQ, nz, kb1[n * K1 + tcol - 1], cc,
-                                                     cn, eps, q);
+            for (int j = 0; j < P1; ++j)
 #pragma unroll
-                        for (int v = 0; v < V; ++v) s1n.v[v] = q[v];
-                    }
-                    if (i >= 1) {                     // step s + 2 on row i - 1
-                        Vec<T, V> o;
-                        uint32_t so = kOutOfRange;
-                        if (act2) {
+                for (int v = 0; v < V; ++v) S[j].v[v] = T(0);
+            for (int n0 = 0; n0 < n_it; n0 += U) {
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    const int n = n0 + j;
+                    if (n < n_it) {
+                        const int i = n - 1;
+                        Vec<T, V>& ym = R[j];                 // step s row n - 2
+                        const Vec<T, V>& c = R[(j + 1) % U];  // row n - 1
+                        const Vec<T, V>& yp = R[(j + 2) % U]; // row n
+                        Vec<T, V>& s1n = S[j % P1];           // step s + 1 row n - 1 (computed here)
+                        const Vec<T, V>& s1c = S[(j + P1 - 1) % P1];   // row n - 2
+                        const Vec<T, V>& s1m = S[(j + P1 - 2) % P1];   // row n - 3
+                        T* const LA = lrow + par * RL;         // step s, row i
+                        T* const LB = lrow + (2 + par) * RL;   // step s + 1, row i - 1
+                        par ^= 1;
+                        if (streams) st<T, V>(LA, c);
+                        if (act1) st<T, V>(LB, s1c);
+                        __syncthreads();
+                        if (act1) {
                             T q[V];
-                            if (uniform)
-                                cell_update<T, V, KAHAN>(a, LB, s1c, s1m, s1n, tzq, NQ, nz, ku, cc, cn, eps, q);
-                            else
-                                cell_update<T, V, KAHAN>(a, LB, s1c, s1m, s1n, tzq, NQ, nz,
-                                                         kb2[(i - 1) * TX + tcol - 2], cc, cn, eps, q);
-                            // the item's own cells: step s + 1 (row i - 1, as read here), step s + 2
+                            cell_update<T, V, KAHAN, PHYS>(a, LA, c, ym, yp, tzq, NQ, nz,
+                                                            UNI ? ku : kb1[n * K1 + tcol - 1], cc, cn, eps, q);
 #pragma unroll
-                            for (int v = 0; v < V; ++v) {
-                                o.v[v] = q[v];
-                                chk1 += static_cast<double>(s1c.v[v]);
-                                chk2 += static_cast<double>(q[v]);
-                            }
-                            so = colbytes + static_cast<uint32_t>(y0 + i - 1) * rowbytes;
+                            for (int v = 0; v < V; ++v) s1n.v[v] = q[v];
                         }
-                        if (a.stream_store)
-                            bstore<T, V, 2>(out, so, o);
-                        else
-                            bstore<T, V, 0>(out, so, o);
+                        ym = bload<T, V>(in, row_off(n + D));  // its slot takes row n + D
+                        if (i >= 1) {                     // step s + 2 on row i - 1
+                            Vec<T, V> o;
+                            uint32_t so = kOutOfRange;
+                            if (act2) {
+                                T q[V];
+                                cell_update<T, V, KAHAN, PHYS>(a, LB, s1c, s1m, s1n, tzq, NQ, nz,
+                                                                UNI ? ku : kb2[(i - 1) * TX + tcol - 2], cc, cn,
+                                                                eps, q);
+                                // the item's own cells: step s + 1 (row i - 1, as read here), step s + 2
+#pragma unroll
+                                for (int v = 0; v < V; ++v) {
+                                    o.v[v] = q[v];
+                                    chk1 += static_cast<double>(s1c.v[v]);
+                                    chk2 += static_cast<double>(q[v]);
+                                }
+                                so = colbytes + static_cast<uint32_t>(y0 + i - 1) * rowbytes;
+                            }
+                            if (a.stream_store)
+                                bstore<T, V, 2>(out, so, o);
+                            else
+                                bstore<T, V, 0>(out, so, o);
+                        }
                     }
-                    ym = c;
-                    c = yp;
-                    s1m = s1c;
-                    s1c = s1n;
                 }
             }
         }
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    using pointwise = std::integral_constant<int, 0>;
+    using vertical = std::integral_constant<int, 1>;
+    if (uniform) {
+        if (a.vertical)
+            rows(yes{}, vertical{});
+        else
+            rows(yes{}, pointwise{});
+    } else {
+        if (a.vertical)
+            rows(no{}, vertical{});
+        else
+            rows(no{}, pointwise{});
     }
     double work = static_cast<double>(nz) * static_cast<double>(a.nfields) *
                   (static_cast<double>(a.alpha) * static_cast<double>(kcols) + static_cast<double>(ksum));
