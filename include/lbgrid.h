@@ -144,8 +144,10 @@ typedef struct {
     int32_t march;           /* > 0: the column-march pipeline with this many
                                 rows in flight (2, 4 or 8; nz % 4 == 0, every
                                 field below 4 GiB, (tile_x + 2) * nz / 4
-                                threads per workgroup, at most 512 in FP64);
-                                overrides stage_rows.  0 = off (default)      */
+                                threads per workgroup, at most 512 in FP64;
+                                for 8 the persistent launch keeps 6 rows in
+                                flight and the two-step launch 4); overrides
+                                stage_rows.  0 = off (default)                */
     int32_t queue_order;     /* order of the items of a queue: 0 = longest
                                 first (cost per item descending); 1 = the hot
                                 items (cost per item above hot_cut percent of

@@ -793,58 +793,77 @@ __device__ ItemOut process_item_march(const DevArgs& a, const ItemDesc& d, const
     const int ku = a.kmin;
     double chk = 0.0;
     int lpar = 0;                             // LDS buffer of the next row
-    for (int f = 0; f < a.nfields; ++f) {
-        const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
-        const rsrc_t out = field_rsrc(dst + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
-        Vec<T, V> ym = bload<T, V>(in, row_off(-1));
-        Vec<T, V> c = bload<T, V>(in, row_off(0));
-        Vec<T, V> R[D];
+    // Rows sit in a ring of U = D + 2 register rows, row r (-1 .. h) in slot
+    // (r + 1) mod U: rows r - 1, r, r + 1 of the update and D rows in flight.  The
+    // row loop is unrolled U times, so every slot is a constant register row and no
+    // row is copied between registers; it is compiled once for each trip-count form
+    // (uniform or per column) and physics.
+    constexpr int U = D + 2;
+    auto rows = [&](auto uni_c, auto phys_c) {
+        constexpr bool UNI = decltype(uni_c)::value;
+        constexpr int PHYS = decltype(phys_c)::value;
+        for (int f = 0; f < a.nfields; ++f) {
+            const rsrc_t in = field_rsrc(src + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+            const rsrc_t out = field_rsrc(dst + static_cast<int64_t>(f) * a.ncells, a.field_bytes);
+            Vec<T, V> R[U];                   // rows -1 .. D to start
 #pragma unroll
-        for (int j = 0; j < D; ++j) R[j] = bload<T, V>(in, row_off(1 + j));
-        // row r: publish row r in the LDS buffer of this row's parity, take row
-        // r + 1 from the ring and refill its slot with row r + 1 + D, compute row
-        // r, store it.  The parity runs on across fields, so consecutive rows
-        // always use different buffers and one barrier per row suffices.
-        for (int r0 = 0; r0 < h; r0 += D) {
+            for (int j = 0; j < U; ++j) R[j] = bload<T, V>(in, row_off(j - 1));
+            // row r: publish row r in the LDS buffer of this row's parity, compute
+            // row r, store it, and refill the slot of row r - 1 with row r + 1 + D.
+            // The parity runs on across fields, so consecutive rows always use
+            // different buffers and one barrier per row suffices.
+            for (int r0 = 0; r0 < h; r0 += U) {
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const int r = r0 + j;
-                if (r < h) {
-                    T* L = lds + lpar * RL;
-                    lpar ^= 1;
-                    if (streams) st<T, V>(L + tcol * nz + zoff, c);
-                    __syncthreads();
-                    if (f == 0 && r == 0) hook();
-                    const Vec<T, V> yp = R[j];
-                    R[j] = bload<T, V>(in, row_off(r + 1 + D));
-                    Vec<T, V> o;
-                    uint32_t so = kOutOfRange;
-                    if (active) {
-                        T q[V];
-                        if (uniform)
-                            cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz, ku, cc, cn,
-                                                     eps, q);
-                        else
-                            cell_update<T, V, KAHAN>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz,
-                                                     kbuf[r * TX + tcol - 1], cc, cn, eps, q);
+                for (int j = 0; j < U; ++j) {
+                    const int r = r0 + j;
+                    if (r < h) {
+                        Vec<T, V>& ym = R[j];                 // row r - 1
+                        const Vec<T, V>& c = R[(j + 1) % U];  // row r
+                        const Vec<T, V>& yp = R[(j + 2) % U]; // row r + 1
+                        T* L = lds + lpar * RL;
+                        lpar ^= 1;
+                        if (streams) st<T, V>(L + tcol * nz + zoff, c);
+                        __syncthreads();
+                        if (f == 0 && r == 0) hook();
+                        Vec<T, V> o;
+                        uint32_t so = kOutOfRange;
+                        if (active) {
+                            T q[V];
+                            cell_update<T, V, KAHAN, PHYS>(a, L + tcol * nz + zoff, c, ym, yp, tzq, NQ, nz,
+                                                            UNI ? ku : kbuf[r * TX + tcol - 1], cc, cn, eps, q);
 #pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            o.v[v] = q[v];
-                            chk += static_cast<double>(q[v]);
+                            for (int v = 0; v < V; ++v) {
+                                o.v[v] = q[v];
+                                chk += static_cast<double>(q[v]);
+                            }
+                            int gy = y0 + r;
+                            gy = gy >= ny ? gy - ny : gy;
+                            so = colbytes + static_cast<uint32_t>(gy) * rowbytes;
                         }
-                        int gy = y0 + r;
-                        gy = gy >= ny ? gy - ny : gy;
-                        so = colbytes + static_cast<uint32_t>(gy) * rowbytes;
+                        ym = bload<T, V>(in, row_off(r + 1 + D));   // its slot takes row r + 1 + D
+                        if (a.stream_store)
+                            bstore<T, V, 2>(out, so, o);
+                        else
+                            bstore<T, V, 0>(out, so, o);
                     }
-                    if (a.stream_store)
-                        bstore<T, V, 2>(out, so, o);
-                    else
-                        bstore<T, V, 0>(out, so, o);
-                    ym = c;
-                    c = yp;
                 }
             }
         }
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    using pointwise = std::integral_constant<int, 0>;
+    using vertical = std::integral_constant<int, 1>;
+    if (uniform) {
+        if (a.vertical)
+            rows(yes{}, vertical{});
+        else
+            rows(yes{}, pointwise{});
+    } else {
+        if (a.vertical)
+            rows(no{}, vertical{});
+        else
+            rows(no{}, pointwise{});
     }
     double work = static_cast<double>(nz) * static_cast<double>(a.nfields) *
                   (static_cast<double>(a.alpha) * static_cast<double>(kcols) + static_cast<double>(ksum));
@@ -1992,7 +2011,7 @@ PersistentFn persistent_for(int vec, int pipe) {
         switch (pipe) {
             case kPipeMarch + 2: return k_persistent_march<T, 4, KAHAN, 2>;
             case kPipeMarch + 4: return k_persistent_march<T, 4, KAHAN, 4>;
-            case kPipeMarch + 8: return k_persistent_march<T, 4, KAHAN, 8>;
+            case kPipeMarch + 8: return k_persistent_march<T, 4, KAHAN, 6>;   // 6: a ring of 10 would spill
             case kPipeDma: return k_persistent<T, 4, KAHAN, kPipeDma>;
             case 8: return k_persistent<T, 4, KAHAN, sizeof(T) == 4 ? 8 : 4>;
             case 4: return k_persistent<T, 4, KAHAN, 4>;
@@ -2034,11 +2053,9 @@ template <typename T, int KAHAN>
 ItemsFn items2_for(int vec, int pipe) {
     if (vec == 5)   // rows in flight: 2 or 4
         return pipe == kPipeMarch + 4 ? k_items2<T, 5, KAHAN, 4> : k_items2<T, 5, KAHAN, 2>;
-    switch (pipe) {
-        case kPipeMarch + 4: return k_items2<T, 4, KAHAN, 4>;
-        case kPipeMarch + 8: return k_items2<T, 4, KAHAN, 8>;
-        default: return k_items2<T, 4, KAHAN, 2>;
-    }
+    // 8 rows in flight: 4 in the two-step launch, whose register rings of 8 + 2 rows
+    // would spill
+    return pipe >= kPipeMarch + 4 ? k_items2<T, 4, KAHAN, 4> : k_items2<T, 4, KAHAN, 2>;
 }
 ItemsFn pick_items2(int prec, int vec, int pipe) {
     if (prec == 2) return items2_for<double, 0>(vec, pipe);
