@@ -224,7 +224,7 @@ def run_ablation(Grid, wl, steps, warmup, R, params, torch, balance_host):
 
     S = wl.nslots
     p = {k: v for k, v in params.items() if k not in ("nqueues", "steal", "wg_per_queue", "item_grid", "fuse_steps",
-                                                         "lane_levels")}
+                                                         "lane_levels", "xcd_group")}
     block = np.array([(c * S) // wl.nchunks if wl.nchunks >= S else c for c in range(wl.nchunks)],
                      dtype=np.int32)
     out = {}

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 6
+#define LB_ABI_VERSION 7
 #define LB_MAX_HOT 4
 #define LB_NBUF 3
 
@@ -186,6 +186,14 @@ typedef struct {
                                 5 needs fuse_steps 2, march 2 or 4 and nz % 20
                                 == 0 (the one-step launches keep 4 levels per
                                 thread).  Same bits for either V.            */
+    int32_t xcd_group;       /* item_grid 1 only: G > 1 deals the item queue to
+                                the 8 XCDs in runs of G consecutive items (in
+                                position order: neighbours along x, whose halo
+                                columns overlap), so that one XCD runs each run
+                                side by side and reads the shared halos from
+                                its own L2; the queue order stands at a
+                                granularity of 8 G items.  0 or 1 = off
+                                (default); at most 64.  Same bits either way */
     int64_t t0;              /* time index of step 0 (hotspot phase)          */
     uint64_t seed;           /* seed of the SplitMix64 initial field           */
 } lb_config;

@@ -49,7 +49,7 @@ class LbConfig(C.Structure):
         ("tile_x", C.c_int32), ("tile_y", C.c_int32),
         ("steal", C.c_int32), ("graph_steps", C.c_int32), ("item_split", C.c_int32),
         ("stage_rows", C.c_int32), ("physics", C.c_int32), ("tail_split", C.c_int32),
-        ("item_alpha", C.c_int32), ("march", C.c_int32), ("queue_order", C.c_int32), ("hot_cut", C.c_int32), ("item_grid", C.c_int32), ("fuse_steps", C.c_int32), ("lane_levels", C.c_int32), ("t0", C.c_int64), ("seed", C.c_uint64),
+        ("item_alpha", C.c_int32), ("march", C.c_int32), ("queue_order", C.c_int32), ("hot_cut", C.c_int32), ("item_grid", C.c_int32), ("fuse_steps", C.c_int32), ("lane_levels", C.c_int32), ("xcd_group", C.c_int32), ("t0", C.c_int64), ("seed", C.c_uint64),
     ]
 
 
@@ -142,7 +142,7 @@ def make_config(nx, ny, nz, px, py, xsplit=None, ysplit=None, *, nfields=1, prec
                 c_center=0.4, c_nbr=0.1, eps=0.01, hot=(), sigma=8.0, kmin=1, kmax=1,
                 alpha_work=32, nslots=256, nqueues=0, wg_per_queue=0, tile_x=0, tile_y=0, steal=1,
                 graph_steps=10, item_split=2, stage_rows=0, physics=0, tail_split=4, item_alpha=-1,
-                march=0, queue_order=0, hot_cut=200, item_grid=0, fuse_steps=0, lane_levels=0, t0=0, seed=0):
+                march=0, queue_order=0, hot_cut=200, item_grid=0, fuse_steps=0, lane_levels=0, xcd_group=0, t0=0, seed=0):
     """Build an LbConfig; returns (config, keepalive) -- keep both until the call returns."""
     cfg = LbConfig()
     lib().lb_config_default(C.byref(cfg))
@@ -179,6 +179,7 @@ def make_config(nx, ny, nz, px, py, xsplit=None, ysplit=None, *, nfields=1, prec
     cfg.item_grid = item_grid
     cfg.fuse_steps = fuse_steps
     cfg.lane_levels = lane_levels
+    cfg.xcd_group = xcd_group
     cfg.t0, cfg.seed = t0, seed
     return cfg, keep
 

@@ -5,7 +5,7 @@
 Searches the launch parameters that do not change the method (launch form
 item_grid, steps per launch fuse_steps, pipeline march / stage_rows, tile_x,
 tile_y, nqueues, wg_per_queue, queue order and hot_cut, item_split,
-tail_split, item_alpha), keeping
+tail_split, item_alpha, xcd_group, lane_levels), keeping
 everything that defines the problem fixed (grid, chunks, hotspots, number of
 balancer slots S).  Each candidate: a fresh context run in windows of R steps
 with a load measurement and a rebalance after each window, as the benchmark
@@ -44,6 +44,8 @@ SPACE = {
                                               # n > 0: direct-to-LDS batches of n rows
     "tail_split": [0, 2, 4, 8],
     "item_alpha": [-1, 8, 4, 2, 1, 0],  # -1: items sized with the balancer's alpha_work
+    "xcd_group": [0, 4, 8],       # > 1: runs of this many neighbouring items per XCD
+    "lane_levels": [0, 5],        # 5: five levels per thread in the two-step launch
 }
 
 

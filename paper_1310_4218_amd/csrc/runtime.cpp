@@ -183,6 +183,8 @@ int make_plan(const lb_config* c, Plan& p, std::string* err) {
     if (c->item_grid == 1 && c->march == 0) return bad("item_grid needs the column-march pipeline (march > 0)");
     if (c->fuse_steps < 0 || c->fuse_steps > 3) return bad("fuse_steps must be 0, 1, 2 or 3");
     if (c->fuse_steps >= 2 && c->item_grid != 1) return bad("fuse_steps 2 or 3 needs item_grid 1");
+    if (c->xcd_group < 0 || c->xcd_group > 64) return bad("xcd_group must be 0 .. 64");
+    if (c->xcd_group > 1 && c->item_grid != 1) return bad("xcd_group needs item_grid 1");
     if (c->lane_levels != 0 && c->lane_levels != 4 && c->lane_levels != 5)
         return bad("lane_levels must be 0, 4 or 5");
     if (c->lane_levels == 5 && c->fuse_steps != 2) return bad("lane_levels 5 needs fuse_steps 2");
@@ -391,6 +393,7 @@ struct lb_ctx {
     std::vector<int32_t> pos_rank;    // per tile: its rank by (first row, first column)
     std::vector<int32_t> pos_order;   // tiles by that rank
     std::vector<ItemDesc> items;      // the installed plan, chunk order
+    std::vector<ItemDesc> dealt;      // scratch of the XCD dealing of the item queue
     std::vector<int32_t> item_off;    // C + 1
     int64_t plan_version = 0;
     int64_t plain_graph_version = -1;
@@ -686,6 +689,22 @@ int upload_plan(lb_ctx* x, const double* cost, const double* tile_cost) {
         }
     }
     st_seg[p.Q] = k;
+    // One workgroup per item: the hardware hands workgroup b to XCD b mod 8.  With
+    // xcd_group G, runs of G consecutive items of the order (neighbours along x,
+    // whose halo columns overlap) go to workgroups 8 apart, so that one XCD runs
+    // them side by side and reads their shared halos from its own L2: item i =
+    // (8 s + r) G + j runs as workgroup (s G + j) 8 + r.  The order stands at a
+    // granularity of 8 G items; a last partial block of 8 G items keeps its place.
+    const int G = x->cfg.xcd_group;
+    if (p.IG && G > 1) {
+        std::vector<ItemDesc>& tmp = x->dealt;
+        tmp.assign(st_queue, st_queue + k);
+        const int32_t full = (k / (8 * G)) * 8 * G;
+        for (int32_t i = 0; i < full; ++i) {
+            const int32_t g = i / G, j = i - g * G, sg = g >> 3, r = g & 7;
+            st_queue[(sg * G + j) * 8 + r] = tmp[i];
+        }
+    }
     *st_n = n;
     // First two items of every workgroup: items `rank` and 2G - 1 - rank of its
     // home queue, with the same workgroup -> (queue, rank) assignment as the
@@ -867,6 +886,7 @@ void lb_config_default(lb_config* c) {
     c->item_grid = 0;
     c->fuse_steps = 0;
     c->lane_levels = 0;
+    c->xcd_group = 0;
 }
 
 int lb_query(const lb_config* cfg, lb_buffers* out) {

@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_struct_layout_and_version(lib):
-    assert lib.lb_abi_version() == 6
+    assert lib.lb_abi_version() == 7
     assert lib.lb_config_bytes() == C.sizeof(_abi.LbConfig)
     assert lib.lb_stats_bytes() == C.sizeof(_abi.LbStats)
 
@@ -86,6 +86,8 @@ def test_query_rejects_bad_config(lib, field, value, msg):
     (dict(fuse_steps=2, march=2, item_grid=1, precision=2, tile_x=61), "fuse_steps 2 in FP64"),
     (dict(fuse_steps=2, march=2, item_grid=1, tile_x=125), "fuse_steps 2 needs (tile_x + 4)"),
     (dict(lane_levels=3), "lane_levels must be"),
+    (dict(xcd_group=65, march=2, item_grid=1), "xcd_group must be"),
+    (dict(xcd_group=-1), "xcd_group must be"), (dict(xcd_group=4, march=2), "xcd_group needs item_grid 1"),
     (dict(lane_levels=5, march=2, item_grid=1), "lane_levels 5 needs fuse_steps 2"),
     (dict(lane_levels=5, march=2, item_grid=1, fuse_steps=3), "lane_levels 5 needs fuse_steps 2"),
     (dict(lane_levels=5, march=2, item_grid=1, fuse_steps=2), "nz divisible by 20"),

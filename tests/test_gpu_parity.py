@@ -144,6 +144,8 @@ def test_launch_forms_bit_identical():
     dict(march=4, item_grid=1, fuse_steps=2), dict(march=2, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3),
     dict(march=8, item_grid=1, fuse_steps=2, tile_y=11, queue_order=1),
     dict(march=4, item_grid=1, fuse_steps=3), dict(march=2, item_grid=1, fuse_steps=3, tile_x=5, tile_y=3, queue_order=1),
+    dict(march=4, item_grid=1, tile_x=5, tile_y=3, xcd_group=4),
+    dict(march=2, item_grid=1, fuse_steps=2, tile_x=5, tile_y=3, xcd_group=3, queue_order=1),
 ])
 def test_schedule_invariance(over):
     wl = mk(40, 36, 12, 4, 3, split="dirichlet", steps=3)
@@ -314,6 +316,34 @@ def test_fused_steps_five_levels_per_thread(precision):
             assert rel_err(q, ref) <= TOL
         four.close()
         g.close()
+
+
+def test_xcd_dealing_changes_no_bit():
+    """Dealing the item queue to the XCDs in runs of G items (G = 3, 8; 96 items, so the
+    last partial block of 8 G items keeps its place for G = 8) changes only where items
+    run: fields, loads and per-step checksums are bit-identical to the undealt queue
+    through fused and single-step launches, graphs and a rebalance."""
+    wl = mk(40, 36, 20, 4, 3, hot=((5, 4, 1, 2),), split="dirichlet", steps=7, nslots=5)
+
+    def run(**over):
+        g = Grid(wl, march=4, item_grid=1, fuse_steps=2, graph_steps=2, tile_x=5, tile_y=3,
+                 queue_order=1, **over)
+        g.step(3, "persistent")
+        w1 = g.measure("work")
+        g.rebalance("greedy")
+        g.step(4, "persistent_eager")
+        return g, w1, g.measure("work")
+
+    ref, r1, r2 = run()
+    for G in (3, 8):
+        g, w1, w2 = run(xcd_group=G)
+        np.testing.assert_array_equal(gpu_fields(g), gpu_fields(ref))
+        np.testing.assert_array_equal(w1, r1)
+        np.testing.assert_array_equal(w2, r2)
+        np.testing.assert_array_equal(g.checksums(7), ref.checksums(7))
+        assert np.all(g.visits() == 7)
+        g.close()
+    ref.close()
 
 
 def test_measure_in_two_halves():
