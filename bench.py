@@ -75,6 +75,29 @@ def measured_traffic(workload: str, precision: str, launch: dict):
     return t.get("hbm_bytes_per_launch")
 
 
+def measured_valu(workload: str, precision: str, launch: dict):
+    """Vector instructions per launch of the step kernel from the committed
+    rocprofv3 counter record (SQ_INSTS_VALU), if it was taken on the current
+    kernel source, in this precision and with this launch shape; else None."""
+    name = workload if precision == "fp32" else f"{workload}_{precision}"
+    path = os.path.join(ROOT, "profiles", f"counters_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if (t.get("kernel_source_hash") != kernel_source_hash() or t.get("precision", "fp32") != precision
+            or t.get("launch") != launch):
+        return None
+    return t.get("means_per_dispatch", {}).get("SQ_INSTS_VALU")
+
+
+# Vector issue of the chip: 256 CUs x 4 SIMDs, each 16 lanes wide, so a wave's
+# vector instruction holds its SIMD for 4 cycles; 2.4 GHz.
+SIMDS = 1024
+CYCLES_PER_WAVE_INSTRUCTION = 4
+CLOCK_HZ = 2.4e9
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -402,13 +425,21 @@ def main(argv=None) -> int:
     # the ALU view is beside it (the two-step launch also keeps the vector units busy).
     roof = {"bound": "hbm" if hbm_resident else "latency", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, args.precision,
-                                        {k: v for k, v in params.items() if k != "precision"}),
+            "traffic": (measured_traffic(args.workload, args.precision,
+                                         {k: v for k, v in params.items() if k != "precision"})
+                        if not args.vertical else None),   # the records are of the pointwise kernel
             "kernel": kname, "bytes_per_update": bytes_per_update, "units_per_launch": units_per_launch,
             "steps_per_launch": steps_per_launch,
             "compulsory": {"bytes_per_launch": compulsory_bytes, "achieved": compulsory_gbs,
                            "frac": compulsory_gbs / HBM_PEAK_GBS},
             "alu": alu, "us_per_launch_events": kernel_launch_s * 1e6}
+    # Vector issue: the counted vector instructions of a launch over the issue slots of
+    # its duration (every SIMD issuing one wave instruction per 4 cycles at 2.4 GHz).
+    launch_cfg = {k: v for k, v in params.items() if k != "precision"}
+    valu = measured_valu(args.workload, args.precision, launch_cfg) if not args.vertical else None
+    roof["issue"] = {"valu_instructions_per_launch": valu,
+                     "frac": (valu * CYCLES_PER_WAVE_INSTRUCTION / (SIMDS * CLOCK_HZ * kernel_launch_s)
+                              if valu else None)}
 
     out = {
         "metric": METRIC,

@@ -7,7 +7,7 @@
         --copy-mib 512
     python -m paper_1310_4218_amd.traffic stats OUT/stats --title T --command C --write F.md
     python -m paper_1310_4218_amd.traffic counters OUT/pmc --kernel k_items2 --title T \
-        --command C --write F.md
+        --command C --write F.md [--workload W [--precision P]]
 
 Both counters are reported in KiB per dispatch.  Each is scaled by what the
 same counter reads for the plain device copy of known size that bench.py runs
@@ -105,6 +105,24 @@ def stats_summary(outdir: str, title: str, command: str, top: int = 12) -> str:
     return "\n".join(out) + "\n"
 
 
+def counter_means(outdir: str, kernel: str) -> dict:
+    """{counter: mean per dispatch} of `kernel` under outdir (each dispatch's value
+    summed over the device)."""
+    per = {}
+    for path in glob.glob(os.path.join(outdir, "**", "*counter_collection*.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if kernel + "<" not in row.get("Kernel_Name", ""):
+                    continue
+                key = (row["Counter_Name"], row["Dispatch_Id"])
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for c in sorted({c for c, _ in per}):
+        v = [x for (n, _), x in per.items() if n == c]
+        out[c] = sum(v) / len(v)
+    return out
+
+
 def counters_summary(outdir: str, kernel: str, title: str, command: str) -> str:
     """Markdown table of every counter rocprofv3 --pmc collected under outdir for the
     dispatches of `kernel` (each dispatch's value summed over the device, then the
@@ -149,11 +167,22 @@ def main(argv=None) -> int:
         ap.add_argument("--title", required=True)
         ap.add_argument("--command", required=True)
         ap.add_argument("--write", help="markdown file to write")
+        ap.add_argument("--workload", help="with --precision: also write profiles/counters_<workload>.json "
+                                           "(the means, the launch shape and the kernel source hash)")
+        ap.add_argument("--precision", default="fp32")
         a = ap.parse_args(argv[1:])
         md = counters_summary(a.outdir, a.kernel, a.title, a.command)
         if a.write:
             with open(a.write, "w") as f:
                 f.write(md)
+        if a.workload:
+            name = a.workload if a.precision == "fp32" else f"{a.workload}_{a.precision}"
+            rec = dict(workload=a.workload, kernel=a.kernel, precision=a.precision,
+                       means_per_dispatch=counter_means(a.outdir, a.kernel),
+                       launch=tuned_params(a.workload, a.precision),
+                       kernel_source_hash=kernel_source_hash(), command=a.command)
+            with open(os.path.join(ROOT, "profiles", f"counters_{name}.json"), "w") as f:
+                json.dump(rec, f, indent=1)
         print(md)
         return 0
     if argv and argv[0] == "stats":

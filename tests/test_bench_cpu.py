@@ -56,3 +56,21 @@ def test_vertical_physics_takes_its_own_launch_where_tuned():
     assert tuned_params("large", "fp32_kahan", physics="vertical") == vert
     _abi.query(_abi.config_from_workload(W.get("large").replace(vertical=1), **vert)[0])
     assert tuned_params("precision", "fp32", physics="vertical") == tuned_params("precision", "fp32")
+
+
+def test_valu_count_reported_only_for_its_kernel_and_launch():
+    """The vector-instruction count behind roofline.issue comes from the committed counter
+    record of the 2048x2048x80 two-step launch, and only for the kernel source, precision
+    and launch shape it was taken on."""
+    launch = tuned_params("large", "fp32")
+    path = os.path.join(ROOT, "profiles", "counters_large.json")
+    with open(path) as f:
+        rec = json.load(f)
+    if rec["kernel_source_hash"] != bench.kernel_source_hash():
+        pytest.skip("counters_large.json was taken on an earlier kernel source (bench reports null)")
+    got = bench.measured_valu("large", "fp32", launch)
+    assert got == rec["means_per_dispatch"]["SQ_INSTS_VALU"] and got > 1e8
+    assert bench.measured_valu("large", "fp64", launch) is None
+    assert bench.measured_valu("large", "fp32", dict(launch, tile_y=12)) is None
+    # issue slots of one launch: 1024 SIMDs, 4 cycles per wave instruction, 2.4 GHz
+    assert bench.SIMDS * bench.CLOCK_HZ / bench.CYCLES_PER_WAVE_INSTRUCTION == 614.4e9
